@@ -1,0 +1,454 @@
+"""Pins of the CPU oracle against facts fixed outside the oracle itself.
+
+Each test checks the oracle against something it does not compute: a published
+test vector, a closed form, a LAPACK routine, a brute-force enumeration, an
+invariant of the mathematics, or a structural fact printed in the paper
+(tests/golden/paper_structure.json).  Mistakes planted in the oracle at the end
+of this file must be caught by these pins.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import seeded_inputs as si
+from oracle import rng
+from oracle.h2 import H2Matrix
+from oracle.hessians import (AdvDiffGN, DiffusionGN, KernelHessian, dense_from_apply,
+                             tree_order)
+from oracle.ns import build, newton_schulz, power_norm, residual_norm
+from oracle import peel as peel_mod
+from oracle.tree import Tree, sibling_level
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# ----------------------------------------------------------------- RNG
+def test_splitmix64_published_vector():
+    # first five outputs of splitmix64 seeded with 1234567 (Steele-Lea-Flood
+    # generator; the vector distributed with the reference C implementation)
+    want = [6457827717110365317, 3203168211198807973, 9817491932198370423,
+            4593380528125082431, 16408922859458223821]
+    assert [int(x) for x in rng.splitmix64_stream(1234567, 5)] == want
+
+
+def test_gaussian_stream_statistics():
+    key = rng.stream_key(7, rng.PHASE_RANGE, 3, 1, 0)
+    z = rng.gaussian(key, np.arange(15625), np.arange(64)).ravel()
+    n = z.size
+    assert abs(z.mean()) < 5.0 / math.sqrt(n)
+    assert abs(z.var() - 1.0) < 5.0 * math.sqrt(2.0 / n)
+    frac = np.mean(np.abs(z) < 1.0)
+    p = math.erf(1.0 / math.sqrt(2.0))
+    assert abs(frac - p) < 5.0 * math.sqrt(p * (1 - p) / n)
+    # fourth moment of N(0,1) is 3
+    assert abs(np.mean(z ** 4) - 3.0) < 5.0 * math.sqrt(96.0 / n)
+
+
+def test_gaussian_entries_are_position_keyed():
+    key = rng.stream_key(1, rng.PHASE_RANGE, 2, 0, 0)
+    full = rng.gaussian(key, np.arange(100), np.arange(8))
+    part = rng.gaussian(key, np.arange(40, 60), np.arange(3, 5))
+    assert np.array_equal(full[40:60, 3:5], part)
+    other = rng.gaussian(rng.stream_key(1, rng.PHASE_RANGE, 2, 1, 0), np.arange(100), np.arange(8))
+    assert np.abs(np.corrcoef(full.ravel(), other.ravel())[0, 1]) < 0.2
+
+
+# ----------------------------------------------------------------- tree
+def test_tree_levels_match_paper():
+    facts = json.load(open(os.path.join(GOLDEN, "paper_structure.json")))["levels"]
+    for f in facts:
+        if f["dim"] == 1:
+            pts = si.points_1d_cell_centres(f["n"])
+        else:
+            pts = si.points_grid_interior(f["grid"])
+        assert Tree(pts, f["leaf"], 0.7).L == f["levels"], f["cite"]
+
+
+def test_tree_1d_clusters_are_coordinate_ranges():
+    g = np.random.Generator(np.random.PCG64(0))
+    pts = g.uniform(size=777)
+    T = Tree(pts, 20, 0.7)
+    order = np.argsort(pts, kind="stable")
+    assert np.array_equal(T.perm, order)
+    for l in range(T.L + 1):
+        sizes = np.diff(T.offsets[l])
+        assert sizes.max() - sizes.min() <= 1
+        assert sizes.max() <= max(20, -(-777 >> 0)) if l == 0 else True
+    assert np.diff(T.offsets[T.L]).max() <= 20
+
+
+def test_tree_2d_grid_clusters_are_subrectangles():
+    pts = si.points_grid_interior(32)
+    T = Tree(pts, 16, 0.7)
+    h = 1.0 / 33
+    for l in range(T.L + 1):
+        for i in range(1 << l):
+            P = pts[T.perm[T.offsets[l][i]:T.offsets[l][i + 1]]]
+            nx = int(round((P[:, 0].max() - P[:, 0].min()) / h)) + 1
+            ny = int(round((P[:, 1].max() - P[:, 1].min()) / h)) + 1
+            assert nx * ny == len(P)
+    assert np.all(np.diff(T.offsets[T.L]) == 16)
+
+
+# ----------------------------------------------------------------- lists
+def _coverage(T):
+    L = T.L
+    C = np.zeros((T.n, T.n), dtype=np.int64)
+    for l in range(1, L + 1):
+        for (t, s) in T.far[l]:
+            a, b = T.rng(l, t)
+            c, d = T.rng(l, s)
+            C[a:b, c:d] += 1
+    for (t, s) in T.near:
+        a, b = T.rng(L, t)
+        c, d = T.rng(L, s)
+        C[a:b, c:d] += 1
+    return C
+
+
+@pytest.mark.parametrize("pts,leaf", [
+    (si.points_1d_cell_centres(512), 16),
+    (si.points_grid_interior(24), 32),
+    (np.random.Generator(np.random.PCG64(3)).uniform(size=(700, 2)), 24),
+])
+def test_lists_partition_and_symmetry(pts, leaf):
+    T = Tree(pts, leaf, 0.7)
+    assert np.all(_coverage(T) == 1)
+    for l in range(T.L + 1):
+        assert sorted((s, t) for (t, s) in T.far[l]) == T.far[l]
+        for (t, s) in T.far[l]:
+            assert T.admissible(l, t, s)
+    assert sorted((s, t) for (t, s) in T.near) == T.near
+
+
+def test_lists_1d_closed_form():
+    cfg = si.config_kernel1d()
+    T = Tree(cfg["points"], 32, 0.7)
+    for l in range(1, T.L + 1):
+        want = sorted((i, j) for i in range(1 << l) for j in range(1 << l)
+                      if abs(i - j) >= 3 and abs(i // 2 - j // 2) <= 2)
+        assert T.far[l] == want
+    assert len(T.near) == 32 * 5 - 2 * (1 + 2) == 154
+
+
+def test_lists_brute_force_admissibility():
+    # every (t, s) at every level classified by direct geometry, no traversal
+    pts = np.random.Generator(np.random.PCG64(11)).uniform(size=(300, 2))
+    T = Tree(pts, 10, 0.7)
+    for l in range(T.L + 1):
+        for t in range(1 << l):
+            for s in range(1 << l):
+                Pt = pts[T.perm[slice(*T.rng(l, t))]]
+                Ps = pts[T.perm[slice(*T.rng(l, s))]]
+                dt = np.sum((Pt.max(0) - Pt.min(0)) ** 2)
+                ds = np.sum((Ps.max(0) - Ps.min(0)) ** 2)
+                gap = np.maximum(0, np.maximum(Ps.min(0) - Pt.max(0), Pt.min(0) - Ps.max(0)))
+                adm = l >= 1 and max(dt, ds) <= 0.49 * np.sum(gap ** 2) * (1 + 1e-12)
+                # a pair is far iff admissible and no ancestor pair was admissible
+                anc_adm = any(
+                    T.admissible(l - s_, t >> s_, s >> s_) for s_ in range(1, l)
+                ) if l >= 2 else False
+                assert ((t, s) in T.far[l]) == (adm and not anc_adm)
+
+
+def test_lists_counts_diffusion_and_advdiff_grids():
+    # counts computed from the same readings by an independent scratch script
+    # (64 x 64 cell centres; interior nodes (i+1)/65 meet exact admissibility
+    # ties at level 5 that IEEE rounding decides, giving 216/1116 instead)
+    T = Tree(si.points_grid_cell_centres(64, 64), 64, 0.7)
+    assert [len(f) for f in T.far] == [0, 0, 0, 0, 60, 208, 1148]
+    assert len(T.near) == 1156
+    T = Tree(si.points_grid_interior(128), 64, 0.7)
+    assert [len(f) for f in T.far] == [0, 0, 0, 0, 60, 88, 1628, 1536, 6876]
+    assert len(T.near) == 5476
+
+
+def test_sibling_level():
+    assert sibling_level(3, 0, 7) == 1
+    assert sibling_level(3, 2, 3) == 3
+    assert sibling_level(3, 1, 2) == 2
+
+
+# ----------------------------------------------------------------- HGEMV
+def _random_h2(T, k, seed):
+    g = np.random.Generator(np.random.PCG64(seed))
+    H = H2Matrix(T)
+    L = T.L
+    for l in range(L + 1):
+        H.rank[l][:] = 0 if l <= 1 else k
+    for i in range(1 << L):
+        H.U[i] = np.linalg.qr(g.standard_normal((T.size(L, i), k)))[0]
+    for l in range(1, L + 1):
+        for i in range(1 << l):
+            H.E[l][i] = g.standard_normal((H.rank[l][i], H.rank[l - 1][i // 2]))
+        for (t, s) in T.far[l]:
+            if (s, t) in H.S[l]:
+                H.S[l][(t, s)] = H.S[l][(s, t)].T
+            else:
+                H.S[l][(t, s)] = g.standard_normal((H.rank[l][t], H.rank[l][s]))
+    for (t, s) in T.near:
+        if (s, t) in H.D:
+            H.D[(t, s)] = H.D[(s, t)].T
+        else:
+            M = g.standard_normal((T.size(L, t), T.size(L, s)))
+            H.D[(t, s)] = M + M.T if t == s else M
+    return H
+
+
+def test_hgemv_matches_dense_expansion():
+    T = Tree(np.random.Generator(np.random.PCG64(5)).uniform(size=(600, 2)), 20, 0.7)
+    H = _random_h2(T, 6, 9)
+    A = H.dense_user()
+    x = si.gaussian_vectors(T.n, 5, 1)
+    y = H.matvec(x)
+    assert np.max(np.abs(y - A @ x)) <= 1e-13 * np.max(np.abs(A @ x))
+    assert np.allclose(A, A.T, rtol=0, atol=1e-13 * np.abs(A).max())
+
+
+# ----------------------------------------------------------------- peeling
+def test_peel_exact_recovery_exp_kernel():
+    # exp(-|x-y|/ell) = e^{x/ell} e^{-y/ell} for x < y: every sibling block has
+    # rank exactly 1 and the nested basis span{e^{x/ell}, e^{-x/ell}} rank 2
+    cfg = si.config_kernel1d()
+    T = Tree(cfg["points"], cfg["leaf"], cfg["eta"])
+    K = KernelHessian(cfg["points"], cfg["ell"], cfg["shift"])
+    A = tree_order(K.apply, T.perm)
+    nu, _ = power_norm(A, T.n, cfg["seed"])
+    H, pr = build(A, T, cfg["tol"], nu, cfg["cap"], cfg["p"], adaptive=False, seed=cfg["seed"])
+    assert [int(pr.kw[l].max()) for l in range(1, T.L + 1)] == [1] * 5
+    assert [int(pr.kw[l].min()) for l in range(1, T.L + 1)] == [1] * 5
+    assert [int(r.max()) for r in H.rank] == [0, 0, 1, 2, 2, 2]
+    assert pr.applies == 5 * (26 + 1) + 32
+    Hd = K.dense()
+    err = np.linalg.norm(H.dense_user() - Hd, 2) / np.linalg.norm(Hd, 2)
+    assert err <= 1e-12
+
+
+def _random_weak_matrix(T, r, seed):
+    g = np.random.Generator(np.random.PCG64(seed))
+    A = np.zeros((T.n, T.n))
+    for l in range(1, T.L + 1):
+        for p in range(1 << (l - 1)):
+            a1, b1 = T.rng(l, 2 * p)
+            a2, b2 = T.rng(l, 2 * p + 1)
+            M = g.standard_normal((b2 - a2, r)) @ g.standard_normal((r, b1 - a1)) / (2.0 ** l)
+            A[a2:b2, a1:b1] = M
+            A[a1:b1, a2:b2] = M.T
+    for i in range(1 << T.L):
+        a, b = T.rng(T.L, i)
+        M = g.standard_normal((b - a, b - a))
+        A[a:b, a:b] = M + M.T
+    return A
+
+
+def test_peel_exact_recovery_random_weak_structure():
+    T = Tree(si.points_1d_cell_centres(512), 32, 0.7)
+    At = _random_weak_matrix(T, 5, 21)     # tree order
+    A = lambda Om: At @ Om
+    nu = np.linalg.norm(At, 2)
+    pr = peel_mod.peel(A, T, 1e-10, nu, 16, 10, adaptive=False, seed=4)
+    assert all(int(pr.kw[l].max()) == 5 and int(pr.kw[l].min()) == 5 for l in pr.kw)
+    W = peel_mod.weak_dense(T, pr)
+    assert np.linalg.norm(W - At, 2) <= 1e-12 * nu
+    H = peel_mod.recompress(T, pr, 1e-13, nu, 64)
+    assert np.linalg.norm(H.dense_tree() - At, 2) <= 1e-11 * nu
+
+
+def test_peel_adaptive_finds_rank_beyond_one_round():
+    # weak rank 40 > one round of 26 columns: the HMT estimator must ask for more
+    T = Tree(si.points_1d_cell_centres(512), 64, 0.7)
+    At = _random_weak_matrix(T, 40, 8)
+    nu = np.linalg.norm(At, 2)
+    pr = peel_mod.peel(lambda Om: At @ Om, T, 1e-8, nu, 16, 10, adaptive=True, seed=5)
+    assert pr.converged
+    assert all(pr.rounds[l] >= 3 for l in pr.rounds)
+    assert all(int(pr.kw[l].max()) == 40 for l in pr.kw)
+    assert np.linalg.norm(peel_mod.weak_dense(T, pr) - At, 2) <= 1e-10 * nu
+
+
+@pytest.fixture(scope="module")
+def diffusion_small():
+    cfg = si.config_diffusion2d(32)
+    T = Tree(cfg["points"], cfg["leaf"], cfg["eta"])
+    G = DiffusionGN(cfg)
+    A = tree_order(G.apply, T.perm)
+    nu, _ = power_norm(A, T.n, cfg["seed"])
+    H, pr = build(A, T, cfg["tol"], nu, cfg["cap"], cfg["p"], adaptive=True, seed=cfg["seed"])
+    Hd = dense_from_apply(G.apply, T.n)
+    return cfg, T, G, H, pr, Hd
+
+
+def test_build_meets_tolerance_against_dense(diffusion_small):
+    cfg, T, G, H, pr, Hd = diffusion_small
+    nH = np.linalg.norm(Hd, 2)
+    err = np.linalg.norm(H.dense_user() - Hd, 2) / nH
+    assert err <= cfg["tol"]
+    assert pr.converged
+
+
+def test_built_h2_symmetric_and_frobenius_identity(diffusion_small):
+    cfg, T, G, H, pr, Hd = diffusion_small
+    A = H.dense_tree()
+    assert np.max(np.abs(A - A.T)) <= 1e-13 * np.abs(A).max()
+    fro2 = float(np.sum(A * A))
+    assert abs(H.frobenius2_blocks() - fro2) <= 1e-12 * fro2
+    # orthonormal leaf bases and transfers (so explicit bases are orthonormal)
+    B = H.explicit_bases()
+    for l in range(T.L + 1):
+        for b in B[l]:
+            if b.shape[1]:
+                assert np.allclose(b.T @ b, np.eye(b.shape[1]), atol=1e-12)
+
+
+def test_recompression_idempotent():
+    # rebuilding an H2 from its own products at the same threshold keeps it
+    cfg = si.config_kernel1d(256)
+    T = Tree(cfg["points"], 32, 0.7)
+    K = KernelHessian(cfg["points"], 0.1, 1e-2)
+    A = tree_order(K.apply, T.perm)
+    nu, _ = power_norm(A, T.n, 1)
+    H, _ = build(A, T, 1e-8, nu, 16, 10, adaptive=True, seed=1)
+    H2, _ = build(H.matvec_tree, T, 1e-8, nu, 16, 10, adaptive=True, seed=2)
+    d = np.linalg.norm(H2.dense_tree() - H.dense_tree(), 2)
+    assert d <= 1e-12 * nu
+    assert [list(r) for r in H2.rank] == [list(r) for r in H.rank]
+
+
+# ----------------------------------------------------------------- Newton-Schulz
+@pytest.fixture(scope="module")
+def kernel_small():
+    cfg = si.config_kernel1d(256)
+    T = Tree(cfg["points"], 32, 0.7)
+    K = KernelHessian(cfg["points"], 0.1, 1e-2)
+    A = tree_order(K.apply, T.perm)
+    nu, _ = power_norm(A, T.n, 1, rel=1e-12, max_it=500)
+    H, _ = build(A, T, 1e-12, nu, 16, 10, adaptive=True, seed=1)
+    lam = np.linalg.eigvalsh(K.dense())
+    return T, H, lam
+
+
+def test_residual_norm_matches_dense(kernel_small):
+    T, H, lam = kernel_small
+    X = H2Matrix.scaled_identity(T, 1.0 / lam[-1] * 0.9)
+    E = residual_norm(H, X, 1, 0, rel=1e-6, max_it=2000)
+    R = np.eye(T.n) - H.dense_tree() @ X.dense_tree()
+    assert abs(E - np.linalg.norm(R, 2)) <= 1e-3 * np.linalg.norm(R, 2)
+
+
+@pytest.mark.parametrize("x0", ["identity", "scaled"])
+def test_newton_schulz_closed_form(kernel_small, x0):
+    # X0 = p(H) gives X_k = p_k(H) and E_k = max_i |1 - lam_i x0(lam_i)|^(2^k)
+    T, H, lam = kernel_small
+    X, info = newton_schulz(H, 1e-6, 40, 32, 10, x0=x0, adaptive=True, seed=3,
+                            eps_build=1e-9, nu_rel=1e-12, resid_rel=1e-7)
+    nu = info["nu"]
+    r = 1.0 - lam / nu if x0 == "identity" else 1.0 - (lam / nu) ** 2
+    rmax = float(np.max(np.abs(r)))
+    for k, E in enumerate(info["E"]):
+        want = rmax ** (2 ** k)
+        if want < 1e-4:
+            break
+        assert abs(E - want) <= 1e-3 * want, (k, E, want)
+    assert info["status"] == "converged"
+    kappa = lam[-1] / lam[0]
+    bound = (2 * math.log2(kappa) + math.log2(math.log2(1e6))) * (1 if x0 == "identity" else 1.5)
+    assert info["iterations"] <= bound + 2
+
+
+def test_newton_schulz_quadratic_convergence(kernel_small):
+    T, H, lam = kernel_small
+    X, info = newton_schulz(H, 1e-8, 40, 32, 10, x0="identity", adaptive=True, seed=5,
+                            eps_build=1e-11)
+    E = info["E"]
+    tail = [(E[k], E[k + 1]) for k in range(len(E) - 1) if 1e-6 < E[k] < 0.3]
+    assert tail
+    for a, b in tail:
+        assert b <= 1.5 * a * a + 1e-9
+
+
+# ----------------------------------------------------------------- Hessians
+def test_diffusion_forward_matches_matrix_powers():
+    cfg = si.config_diffusion2d(8)
+    cfg["obs_index"] = np.array([1, 4, 6])
+    G = DiffusionGN(cfg)
+    n = G.n
+    # explicit step matrix from the 5-point stencil definition
+    M = np.eye(n)
+    c = cfg["dt"] * cfg["kappa"] / cfg["h"] ** 2
+    for iy in range(8):
+        for ix in range(8):
+            i = iy * 8 + ix
+            M[i, i] -= 4 * c
+            for jy, jx in ((iy - 1, ix), (iy + 1, ix), (iy, ix - 1), (iy, ix + 1)):
+                if 0 <= jy < 8 and 0 <= jx < 8:
+                    M[i, jy * 8 + jx] += c
+    P = np.zeros((9, n))
+    for q, (a, b) in enumerate([(a, b) for a in cfg["obs_index"] for b in cfg["obs_index"]]):
+        P[q, a * 8 + b] = 1.0
+    F = np.vstack([P @ np.linalg.matrix_power(M, s) for s in sorted(cfg["obs_steps"])])
+    v = si.gaussian_vectors(n, 2, 4)
+    got = np.concatenate([o.reshape(9, 2) for o in G.forward(v)])
+    assert np.allclose(got, F @ v, rtol=1e-12, atol=1e-12 * np.abs(F @ v).max())
+    H = dense_from_apply(G.apply, n)
+    Lp = (M - np.eye(n)) / (cfg["dt"] * cfg["kappa"])
+    Rg = np.eye(n) - cfg["beta"] * Lp
+    want = F.T @ F / cfg["sigma"] ** 2 + cfg["gamma"] * Rg @ Rg
+    assert np.allclose(H, want, rtol=1e-10, atol=1e-10 * np.abs(want).max())
+
+
+def test_advdiff_adjoint_identity():
+    cfg = si.config_advdiff2d(16, nobs=30)
+    cfg["steps"] = 40
+    cfg["obs_steps"] = [10, 20, 40]
+    G = AdvDiffGN(cfg)
+    g = np.random.Generator(np.random.PCG64(2))
+    u = g.standard_normal((16, 16, 3))
+    w = g.standard_normal((16, 16, 3))
+    assert abs(np.sum(G.step(u) * w) - np.sum(u * G.step_T(w))) <= 1e-12 * np.abs(np.sum(u * G.step_T(w))) + 1e-12
+    H = dense_from_apply(G.apply, G.n)
+    assert np.allclose(H, H.T, atol=1e-10 * np.abs(H).max())
+    assert np.linalg.eigvalsh(H).min() >= -1e-9 * np.abs(H).max()
+    # bilinear weights reproduce linear functions away from the boundary
+    x = (np.arange(16) + 1) * cfg["h"]
+    lin = np.add.outer(0 * x, x).ravel()            # f(x, y) = x at interior nodes
+    q = (cfg["obs_points"][:, 0] > cfg["h"]) & (cfg["obs_points"][:, 0] < 16 * cfg["h"]) \
+        & (cfg["obs_points"][:, 1] > cfg["h"]) & (cfg["obs_points"][:, 1] < 16 * cfg["h"])
+    assert np.allclose((G.B @ lin)[q], cfg["obs_points"][q, 0], atol=1e-12)
+
+
+def test_kernel_hessian_entries():
+    pts = si.points_grid_cell_centres(8, 8)
+    K = KernelHessian(pts, 0.05, 1e-3)
+    D = K.dense()
+    i, j = 3, 41
+    r = math.hypot(pts[i, 0] - pts[j, 0], pts[i, 1] - pts[j, 1])
+    assert D[i, j] == pytest.approx(math.exp(-r / 0.05), rel=1e-15)
+    assert D[5, 5] == pytest.approx(1.0 + 1e-3, rel=1e-15)
+
+
+# ----------------------------------------------------------------- planted mistakes
+def test_pins_catch_planted_mistakes(monkeypatch):
+    """Each planted oracle mistake must break exact recovery of a weak matrix."""
+    T = Tree(si.points_1d_cell_centres(256), 32, 0.7)
+    At = _random_weak_matrix(T, 4, 3)
+    nu = np.linalg.norm(At, 2)
+    orig = peel_mod.weak_apply
+
+    def dropped_term(tree, l, F, Om):          # forgets the t1 rows
+        Y = orig(tree, l, F, Om)
+        for p in range(1 << (l - 1)):
+            a1, b1 = tree.rng(l, 2 * p)
+            Y[a1:b1] = 0
+        return Y
+
+    def wrong_sign(tree, l, F, Om):
+        return -orig(tree, l, F, Om)
+
+    for bad in (dropped_term, wrong_sign):
+        monkeypatch.setattr(peel_mod, "weak_apply", bad)
+        pr = peel_mod.peel(lambda Om: At @ Om, T, 1e-10, nu, 8, 4, adaptive=False, seed=1)
+        monkeypatch.setattr(peel_mod, "weak_apply", orig)
+        assert np.linalg.norm(peel_mod.weak_dense(T, pr) - At, 2) > 1e-3 * nu
