@@ -1,0 +1,261 @@
+/*
+ * h2.h -- C ABI of the MI355X H2 Hessian library.
+ *
+ * The library builds H2 (nested-basis, strong-admissibility) approximations of
+ * symmetric operators that are available only through products with blocks of
+ * vectors, applies them (HGEMV) and inverts them by hierarchical Newton-Schulz,
+ * following arXiv 2003.10173, "Hierarchical Matrix Approximations of Hessians
+ * Arising in Inverse Problems Governed by PDEs":
+ *   - format and four-stage product: Sec. 3.1 (Fig. 2, A = D + U S V^T) and
+ *     Sec. 3.2 (matrix-vector multiplication; recompression; norms)
+ *   - construction from Hessian-vector products (peeling): Sec. 3.3
+ *   - Newton-Schulz on H2: Appendix A, Alg. 1 (iteration), Alg. 2 (hierarchical
+ *     iteration with a construction threshold per step), Alg. 3 (sampler)
+ *
+ * Conventions for every entry point
+ *   - All functions return h2_status; no C++ exception crosses the ABI.
+ *   - "device" pointers are HIP device memory on the current device; "host"
+ *     pointers are ordinary host memory.  The caller owns every buffer it
+ *     passes; the library owns h2_tree / h2_matrix objects and their device
+ *     storage, released by the matching *_destroy call.
+ *   - Multivectors are column-major (column j starts at ptr + j*ld) in the
+ *     caller's (user) point ordering; the library permutes internally.
+ *   - Work is enqueued on the given stream.  Entry points that must decide
+ *     sizes from device results (ranks, convergence) synchronise that stream.
+ *   - The matrices handled are symmetric (the Hessians of the paper), so the
+ *     row basis tree equals the column basis tree (V = U).
+ */
+#ifndef H2_MI355X_H
+#define H2_MI355X_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct h2_tree h2_tree;
+typedef struct h2_matrix h2_matrix;
+
+typedef enum {
+  H2_OK = 0,
+  H2_EINVAL = -1,         /* bad argument (null pointer, size out of range, ...) */
+  H2_ENOMEM = -2,         /* device or host allocation failed */
+  H2_EDEVICE = -3,        /* a HIP call failed */
+  H2_ECALLBACK = -4,      /* the sampler callback returned nonzero */
+  H2_ENUMERIC = -5,       /* NaN/Inf met in samples or factors */
+  H2_ENOTCONVERGED = 1,   /* usable best-effort result; a budget was exhausted */
+  H2_EDIVERGED = 2        /* Newton-Schulz residual grew above 1 */
+} h2_status;
+
+/* storage / GEMM precision of an H2 matrix (vectors of h2_gemv_f32 are FP32) */
+typedef enum { H2_FP64 = 0, H2_FP32 = 1, H2_BF16 = 2 } h2_precision;
+
+/*
+ * Sampler: Y(:, 0:ncols) = A * Omega(:, 0:ncols)  (Sec. 3.3: the operator is
+ * known only through such products; one Hessian-vector product costs one
+ * forward and one adjoint PDE solve, Sec. 2).  omega and y are device
+ * pointers, column-major, user ordering, FP64.  The callback must only
+ * enqueue work on `stream`.  A nonzero return aborts the calling entry point
+ * with H2_ECALLBACK after the library has released its temporaries.
+ */
+typedef int (*h2_sampler_fn)(void* ctx, int n, int ncols, const double* omega, int ld_omega,
+                             double* y, int ld_y, hipStream_t stream);
+
+/* ------------------------------------------------------------------ tree */
+/*
+ * Cluster tree by KD binary space partition (Sec. 4.2: KD-tree ordering with
+ * leaf clusters of size m) and strong-admissibility block lists (Sec. 2 and
+ * Sec. 3.1: a block is low rank when its clusters are far apart relative to
+ * their size).  Rules: depth L = smallest L with leaf_size * 2^L >= n (0 when
+ * n <= leaf_size); a cluster splits along its widest bounding-box dimension
+ * (lowest index on ties), points ordered by (coordinate, user index), the left
+ * child taking ceil(size/2); (t, s) admissible iff
+ *   max(diam2_t, diam2_s) <= (eta*eta) * dist2(t, s)
+ * with squared box diameters and box distance summed in dimension order (no
+ * fused multiply-add); far pairs at levels >= 1, near pairs at the leaf level.
+ * points_host: n x dim, row-major, host.  1 <= dim <= 3.
+ */
+h2_status h2_tree_create(const double* points_host, int n, int dim, int leaf_size, double eta,
+                         h2_tree** out);
+void h2_tree_destroy(h2_tree* tree);
+/* n, number of levels L (leaves at level L), leaf size, dimension (any may be NULL) */
+h2_status h2_tree_info(const h2_tree* tree, int* n, int* levels, int* leaf_size, int* dim);
+/* perm_host[i] = user index of tree position i (n entries) */
+h2_status h2_tree_perm(const h2_tree* tree, int64_t* perm_host);
+/* cluster boundaries of a level: 2^level + 1 tree positions */
+h2_status h2_tree_offsets(const h2_tree* tree, int level, int64_t* offsets_host);
+/* number of far pairs at `level` (level in 0..L) or near pairs (level = -1) */
+h2_status h2_tree_pair_count(const h2_tree* tree, int level, int64_t* count);
+/* the pairs (t, s), sorted by (t, s): pairs_host[2*i], pairs_host[2*i+1] */
+h2_status h2_tree_pairs(const h2_tree* tree, int level, int32_t* pairs_host);
+
+/* ------------------------------------------------------------------ H2 */
+typedef struct {
+  int rank_cap;        /* destination H2 rank cap per cluster basis */
+  int oversample;      /* p: columns per sampling round = rank_cap + p */
+  double tol;          /* relative 2-norm target eps; tau = eps * nu / (4 L) */
+  int adaptive;        /* 1: HMT-estimated rounds; 0: one round per level */
+  int max_rounds;      /* adaptive round budget per level (>= 2) */
+  uint64_t seed;       /* counter-based Gaussian stream seed */
+  uint32_t iteration;  /* stream tag (Newton-Schulz iteration index) */
+  double norm;         /* ||A||_2 if known (> 0); else estimated (power method) */
+  h2_precision prec;   /* FP64 only for construction; see h2_matrix_convert */
+  int learned;         /* reserved: 0 */
+} h2_opts;
+
+#define H2_MAX_LEVELS 32
+typedef struct {
+  int levels;
+  int weak_rank[H2_MAX_LEVELS];    /* max rank of the sampled sibling blocks, level l */
+  int range_cols[H2_MAX_LEVELS];   /* max range-basis width k0 at level l */
+  int rounds[H2_MAX_LEVELS];       /* sampling rounds at level l */
+  int strong_rank[H2_MAX_LEVELS];  /* max cluster-basis rank at level l (destination) */
+  int64_t applies;                 /* sampler columns requested (norm + samples) */
+  double norm;                     /* ||A||_2 used for the thresholds */
+  int converged;                   /* 1 if every level met the estimator */
+  int cap_hit;                     /* 1 if the rank cap truncated a basis */
+  double time_ms[8];               /* norm, sample, range, project, diag, recompress, sampler, total */
+} h2_build_stats;
+
+/* default options: cap 32, p 10, tol 1e-4, adaptive, 16 rounds, seed 1 */
+void h2_opts_default(h2_opts* opts);
+
+/*
+ * Construct an H2 approximation of the operator behind `sampler` by
+ * randomized peeling on the weak (sibling) partition, level by level from
+ * the root (Sec. 3.3), followed by recompression into the strong partition
+ * of the tree (Sec. 3.2: QR downsweep, truncated-SVD upsweep, projection).
+ * The result is FP64 on the device.
+ */
+h2_status h2_build(const h2_tree* tree, h2_sampler_fn sampler, void* ctx, const h2_opts* opts,
+                   hipStream_t stream, h2_matrix** out, h2_build_stats* stats);
+
+/*
+ * y = alpha * A x + beta * y for nv columns (Sec. 3.2, four-stage product:
+ * upsweep, couplings, downsweep, dense near field).  FP64, device, user order.
+ */
+h2_status h2_gemv(const h2_matrix* A, int nv, double alpha, const double* x, int ldx,
+                  double beta, double* y, int ldy, hipStream_t stream);
+/* same with FP32 vectors; the matrix may be stored in FP64, FP32 or BF16 */
+h2_status h2_gemv_f32(const h2_matrix* A, int nv, float alpha, const float* x, int ldx,
+                      float beta, float* y, int ldy, hipStream_t stream);
+
+/* ||A||_2 by the power method stopped at relative change rel (Sec. 3.2) */
+h2_status h2_norm2(const h2_matrix* A, int max_iter, double rel, uint64_t seed,
+                   hipStream_t stream, double* out);
+
+/* copy with storage in `prec` (FP32 or BF16 couplings/bases/dense blocks) */
+h2_status h2_matrix_convert(const h2_matrix* A, h2_precision prec, h2_matrix** out);
+/* scaled copy alpha*A, and the scaled identity alpha*I on a tree */
+h2_status h2_matrix_scale(const h2_matrix* A, double alpha, h2_matrix** out);
+h2_status h2_matrix_identity(const h2_tree* tree, double alpha, h2_matrix** out);
+void h2_destroy(h2_matrix* A);
+
+/*
+ * Import / export in the packed host layout (all row-major FP64):
+ *   ranks: one int32 per cluster, cluster (l, i) at index 2^l - 1 + i
+ *   U:     leaf bases U_i (|leaf_i| x k_i) concatenated over leaves
+ *   E:     transfers E_c (k_c x k_parent) for clusters c = 1 .. 2^(L+1)-2
+ *   S:     couplings (k_t x k_s) of the far pairs in h2_tree_pairs order,
+ *          levels ascending
+ *   D:     dense blocks (|t| x |s|) of the near pairs in h2_tree_pairs order
+ * h2_matrix_sizes returns the element counts of U, E, S, D for given ranks
+ * (ranks_host NULL: the matrix's own ranks; tree from A or from `tree`).
+ */
+h2_status h2_matrix_sizes(const h2_tree* tree, const int32_t* ranks_host, int64_t* nU,
+                          int64_t* nE, int64_t* nS, int64_t* nD);
+h2_status h2_matrix_import(const h2_tree* tree, const int32_t* ranks_host, const double* U,
+                           const double* E, const double* S, const double* D, h2_matrix** out);
+h2_status h2_matrix_ranks(const h2_matrix* A, int32_t* ranks_host);
+h2_status h2_matrix_export(const h2_matrix* A, double* U, double* E, double* S, double* D);
+/* matrix words per HGEMV (U, E, S, D element counts summed) and storage bytes */
+h2_status h2_matrix_words(const h2_matrix* A, int64_t* words, int64_t* bytes);
+
+/* ------------------------------------------------------------------ Newton-Schulz */
+typedef struct {
+  double eps;          /* stop when E = ||I - A X||_2 <= eps (0: never) */
+  int max_iter;        /* iteration budget */
+  int x0;              /* 0: X0 = I / ||A||_2;  1: X0 = A^T / ||A||_2^2 */
+  int dynamic;         /* 1: eps_k = clamp(0.1 E^2, eps_build, 1e-2); 0: eps_build */
+  double eps_build;    /* static construction threshold (0: eps / 10) */
+  double norm_rel;     /* power-method relative change for ||A||_2 (0: 1e-2) */
+  double resid_rel;    /* power-method relative change for E (0: 1e-2) */
+  int rank_cap;        /* iterate rank cap (0: the leaf size) */
+  int oversample;
+  int adaptive;
+  int max_rounds;
+  uint64_t seed;
+  h2_precision prec;   /* FP64, or FP32 sampling with an FP64 residual + refinement */
+} h2_ns_opts;
+
+#define H2_MAX_NS_ITERS 128
+typedef struct {
+  int iterations;
+  double norm;                      /* ||A||_2 estimate */
+  double resid[H2_MAX_NS_ITERS + 1];/* E_k history, FP64 */
+  int64_t applies[H2_MAX_NS_ITERS]; /* sampler columns per iteration */
+  int max_rank[H2_MAX_NS_ITERS];    /* largest basis rank of each iterate */
+  double time_ms[4];                /* residual, build, refine, total */
+} h2_ns_stats;
+
+void h2_ns_opts_default(h2_ns_opts* opts);
+
+/*
+ * Hierarchical Newton-Schulz (Appendix A, Alg. 2): X_{k+1} is rebuilt by
+ * h2_build from the sampler Y = 2W - X_k (A W), W = X_k Omega (Alg. 3), at
+ * threshold eps_k, on the tree and partition of A; iterates are built to
+ * absolute accuracy eps_k / ||A||_2.  Returns H2_OK when E <= eps,
+ * H2_ENOTCONVERGED when the budget ran out, H2_EDIVERGED on growth above 1.
+ * *X_out always receives the last iterate.
+ */
+h2_status h2_newton_schulz(const h2_matrix* A, const h2_ns_opts* opts, hipStream_t stream,
+                           h2_matrix** X_out, h2_ns_stats* stats);
+
+/* E = ||I - A X||_2 by the power method on R^T R (four HGEMVs per step) */
+h2_status h2_residual_norm(const h2_matrix* A, const h2_matrix* X, double rel, int max_iter,
+                           uint64_t seed, uint32_t iteration, hipStream_t stream, double* out);
+
+/* ------------------------------------------------------------------ samplers */
+/*
+ * Built-in samplers for the synthetic Hessians (h2_sampler_fn compatible;
+ * pass the returned context as ctx).  They run as HIP kernels on `stream`.
+ *   kernel:    H_ij = exp(-|p_i - p_j| / ell) + shift delta_ij, points n x dim
+ *   diffusion: H = F^T F / sigma^2 + gamma (I - beta Lap)^2 on a g x g interior
+ *              grid (h = 1/(g+1)), F = point observations (obs_count^2 nodes
+ *              from obs_index) after explicit Euler heat steps u <- u + dt kappa
+ *              Lap u at the listed step numbers; F^T by exact adjoint steps
+ *   advdiff:   H = F^T F / sigma^2, upwind advection-diffusion on a g x g grid
+ *              with velocity from sum_j s_j sin(pi a_j x) sin(pi b_j y), and
+ *              bilinear point observations (x, y in (0,1)) at the listed steps
+ */
+h2_status h2_sampler_kernel_create(const double* points_host, int n, int dim, double ell,
+                                   double shift, void** ctx);
+int h2_sampler_kernel_apply(void* ctx, int n, int ncols, const double* omega, int ld_omega,
+                            double* y, int ld_y, hipStream_t stream);
+h2_status h2_sampler_diffusion_create(int g, double kappa, double dt, int steps,
+                                      const int32_t* obs_steps, int n_obs_steps,
+                                      const int32_t* obs_index, int obs_count, double sigma,
+                                      double gamma, double beta, void** ctx);
+int h2_sampler_diffusion_apply(void* ctx, int n, int ncols, const double* omega, int ld_omega,
+                               double* y, int ld_y, hipStream_t stream);
+h2_status h2_sampler_advdiff_create(int g, double kappa, int steps, const int32_t* obs_steps,
+                                    int n_obs_steps, const double* obs_points_host, int n_obs,
+                                    double sigma, const int32_t* mode_a, const int32_t* mode_b,
+                                    const double* mode_s, int n_modes, void** ctx);
+int h2_sampler_advdiff_apply(void* ctx, int n, int ncols, const double* omega, int ld_omega,
+                             double* y, int ld_y, hipStream_t stream);
+/* sampler that applies an H2 matrix (h2_gemv) -- ctx is the h2_matrix pointer */
+int h2_sampler_h2_apply(void* ctx, int n, int ncols, const double* omega, int ld_omega,
+                        double* y, int ld_y, hipStream_t stream);
+void h2_sampler_destroy(void* ctx);
+
+const char* h2_status_string(h2_status s);
+/* last error message of this thread (for diagnostics) */
+const char* h2_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* H2_MI355X_H */

@@ -1,0 +1,360 @@
+"""MI355X-native H2 Hessian construction, HGEMV and Newton-Schulz inversion.
+
+Thin Python layer over the C ABI in include/h2.h (libh2hip.so): it marshals
+arguments only.  Device memory and streams come from PyTorch (ROCm); every step
+of construction, product and inversion runs in the library's HIP kernels.
+Implements arXiv 2003.10173 (Sec. 3 construction and operations, Appendix A
+Newton-Schulz) -- see the header for the passage behind each entry point.
+"""
+import ctypes as C
+
+import numpy as np
+
+from . import _lib
+from ._lib import (H2_BF16, H2_FP32, H2_FP64, H2BuildStats, H2Error, H2NSOpts, H2NSStats,
+                   H2Opts, SAMPLER_FN, check, lib)
+
+__all__ = ["Tree", "H2Matrix", "build", "newton_schulz", "residual_norm", "KernelSampler",
+           "DiffusionSampler", "AdvDiffSampler", "H2Sampler", "PythonSampler", "opts",
+           "ns_opts", "H2_FP64", "H2_FP32", "H2_BF16", "H2Error", "lib"]
+
+
+def _stream(stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr())
+
+
+class Tree:
+    """Cluster tree + admissibility lists (host C++; bit-exact with the oracle)."""
+
+    def __init__(self, points, leaf_size, eta=0.7):
+        pts = np.ascontiguousarray(np.asarray(points, dtype=np.float64))
+        if pts.ndim == 1:
+            pts = pts.reshape(-1, 1)
+        self.points = pts
+        h = C.c_void_p()
+        check(lib().h2_tree_create(pts.ctypes.data, pts.shape[0], pts.shape[1], int(leaf_size),
+                                   float(eta), C.byref(h)), "h2_tree_create")
+        self.handle = h
+        n, L, lf, d = C.c_int(), C.c_int(), C.c_int(), C.c_int()
+        check(lib().h2_tree_info(h, C.byref(n), C.byref(L), C.byref(lf), C.byref(d)), "info")
+        self.n, self.L, self.leaf_size, self.dim = n.value, L.value, lf.value, d.value
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value:
+            lib().h2_tree_destroy(h)
+            self.handle = None
+
+    @property
+    def perm(self):
+        p = np.empty(self.n, dtype=np.int64)
+        check(lib().h2_tree_perm(self.handle, p.ctypes.data), "h2_tree_perm")
+        return p
+
+    def offsets(self, level):
+        o = np.empty((1 << level) + 1, dtype=np.int64)
+        check(lib().h2_tree_offsets(self.handle, level, o.ctypes.data), "h2_tree_offsets")
+        return o
+
+    def pairs(self, level):
+        """Far pairs at `level` (0..L) or near pairs (level=-1), sorted (t, s)."""
+        cnt = C.c_int64()
+        check(lib().h2_tree_pair_count(self.handle, level, C.byref(cnt)), "pair_count")
+        out = np.empty((cnt.value, 2), dtype=np.int32)
+        if cnt.value:
+            check(lib().h2_tree_pairs(self.handle, level, out.ctypes.data), "pairs")
+        return out
+
+    def nclusters(self):
+        return (2 << self.L) - 1
+
+
+class H2Matrix:
+    """Device-resident H2 matrix handle."""
+
+    def __init__(self, handle, tree):
+        self.handle = handle
+        self.tree = tree          # keep the tree alive as long as the matrix
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value:
+            lib().h2_destroy(h)
+            self.handle = None
+
+    # -- construction from host arrays (packed layout of include/h2.h)
+    @staticmethod
+    def from_host(tree, ranks, U, E, S, D):
+        ranks = np.ascontiguousarray(ranks, dtype=np.int32)
+        arrs = [np.ascontiguousarray(a, dtype=np.float64) for a in (U, E, S, D)]
+        ptrs = [a.ctypes.data if a.size else None for a in arrs]
+        h = C.c_void_p()
+        check(lib().h2_matrix_import(tree.handle, ranks.ctypes.data, *ptrs, C.byref(h)),
+              "h2_matrix_import")
+        return H2Matrix(h, tree)
+
+    @staticmethod
+    def identity(tree, alpha):
+        h = C.c_void_p()
+        check(lib().h2_matrix_identity(tree.handle, float(alpha), C.byref(h)), "identity")
+        return H2Matrix(h, tree)
+
+    def ranks(self):
+        r = np.empty(self.tree.nclusters(), dtype=np.int32)
+        check(lib().h2_matrix_ranks(self.handle, r.ctypes.data), "h2_matrix_ranks")
+        return r
+
+    def sizes(self):
+        r = self.ranks()
+        out = [C.c_int64() for _ in range(4)]
+        check(lib().h2_matrix_sizes(self.tree.handle, r.ctypes.data, *[C.byref(o) for o in out]),
+              "h2_matrix_sizes")
+        return [o.value for o in out]
+
+    def export(self):
+        nU, nE, nS, nD = self.sizes()
+        arrs = [np.empty(max(k, 1)) for k in (nU, nE, nS, nD)]
+        check(lib().h2_matrix_export(self.handle, *[a.ctypes.data for a in arrs]), "export")
+        return self.ranks(), arrs[0][:nU], arrs[1][:nE], arrs[2][:nS], arrs[3][:nD]
+
+    def words(self):
+        w, b = C.c_int64(), C.c_int64()
+        check(lib().h2_matrix_words(self.handle, C.byref(w), C.byref(b)), "h2_matrix_words")
+        return w.value, b.value
+
+    def convert(self, prec):
+        h = C.c_void_p()
+        check(lib().h2_matrix_convert(self.handle, int(prec), C.byref(h)), "h2_matrix_convert")
+        return H2Matrix(h, self.tree)
+
+    def scaled(self, alpha):
+        h = C.c_void_p()
+        check(lib().h2_matrix_scale(self.handle, float(alpha), C.byref(h)), "h2_matrix_scale")
+        return H2Matrix(h, self.tree)
+
+    # -- products (torch CUDA tensors, column-major = torch (nv, n) row-major)
+    def gemv(self, x, y=None, alpha=1.0, beta=0.0, stream=None):
+        """y = alpha A x + beta y for x of shape (n,) or (nv, n) (columns = rows of x)."""
+        import torch
+        xv = x.reshape(-1, self.tree.n)
+        assert xv.is_contiguous() and xv.is_cuda
+        if y is None:
+            y = torch.empty_like(xv)
+            beta = 0.0
+        yv = y.reshape(-1, self.tree.n)
+        nv = xv.shape[0]
+        if xv.dtype == torch.float64:
+            check(lib().h2_gemv(self.handle, nv, float(alpha), _ptr(xv), self.tree.n, float(beta),
+                                _ptr(yv), self.tree.n, _stream(stream)), "h2_gemv")
+        elif xv.dtype == torch.float32:
+            check(lib().h2_gemv_f32(self.handle, nv, float(alpha), _ptr(xv), self.tree.n,
+                                    float(beta), _ptr(yv), self.tree.n, _stream(stream)),
+                  "h2_gemv_f32")
+        else:
+            raise TypeError("vectors must be float64 or float32")
+        return y
+
+    def norm2(self, max_iter=30, rel=1e-2, seed=1, stream=None):
+        out = C.c_double()
+        check(lib().h2_norm2(self.handle, max_iter, rel, seed, _stream(stream), C.byref(out)),
+              "h2_norm2")
+        return out.value
+
+
+# ---------------------------------------------------------------- samplers
+class _SamplerBase:
+    fn = None      # ctypes function pointer (h2_sampler_fn)
+    ctx = None
+
+    def __call__(self, omega, stream=None):
+        """Apply to a (ncols, n) float64 CUDA tensor (columns = rows)."""
+        import torch
+        y = torch.empty_like(omega)
+        rc = self.fn(self.ctx, omega.shape[1], omega.shape[0], _ptr(omega), omega.shape[1],
+                     _ptr(y), omega.shape[1], _stream(stream))
+        if rc != 0:
+            raise RuntimeError("sampler failed with %d" % rc)
+        return y
+
+
+class _NativeSampler(_SamplerBase):
+    apply_name = None
+
+    def _finish(self, h):
+        self.ctx = h
+        self.fn = C.cast(getattr(lib()._dll, self.apply_name), C.c_void_p).value
+        self.fn = SAMPLER_FN(self.fn)
+
+    def __del__(self):
+        if getattr(self, "ctx", None) is not None and self.ctx.value:
+            lib().h2_sampler_destroy(self.ctx)
+            self.ctx = None
+
+
+class KernelSampler(_NativeSampler):
+    """H_ij = exp(-|p_i - p_j|/ell) + shift delta_ij (HIP kernel)."""
+    apply_name = "h2_sampler_kernel_apply"
+
+    def __init__(self, points, ell, shift):
+        pts = np.ascontiguousarray(np.asarray(points, dtype=np.float64))
+        if pts.ndim == 1:
+            pts = pts.reshape(-1, 1)
+        h = C.c_void_p()
+        check(lib().h2_sampler_kernel_create(pts.ctypes.data, pts.shape[0], pts.shape[1],
+                                             float(ell), float(shift), C.byref(h)), "kernel")
+        self._finish(h)
+
+
+class DiffusionSampler(_NativeSampler):
+    apply_name = "h2_sampler_diffusion_apply"
+
+    def __init__(self, cfg):
+        steps = np.ascontiguousarray(cfg["obs_steps"], dtype=np.int32)
+        oi = np.ascontiguousarray(cfg["obs_index"], dtype=np.int32)
+        h = C.c_void_p()
+        check(lib().h2_sampler_diffusion_create(cfg["grid"], cfg["kappa"], cfg["dt"],
+                                                cfg["steps"], steps.ctypes.data, len(steps),
+                                                oi.ctypes.data, len(oi), cfg["sigma"],
+                                                cfg["gamma"], cfg["beta"], C.byref(h)),
+              "diffusion")
+        self._finish(h)
+
+
+class AdvDiffSampler(_NativeSampler):
+    apply_name = "h2_sampler_advdiff_apply"
+
+    def __init__(self, cfg):
+        steps = np.ascontiguousarray(cfg["obs_steps"], dtype=np.int32)
+        pts = np.ascontiguousarray(cfg["obs_points"], dtype=np.float64)
+        a = np.ascontiguousarray(cfg["mode_a"], dtype=np.int32)
+        b = np.ascontiguousarray(cfg["mode_b"], dtype=np.int32)
+        s = np.ascontiguousarray(cfg["mode_s"], dtype=np.float64)
+        h = C.c_void_p()
+        check(lib().h2_sampler_advdiff_create(cfg["grid"], cfg["kappa"], cfg["steps"],
+                                              steps.ctypes.data, len(steps), pts.ctypes.data,
+                                              len(pts), cfg["sigma"], a.ctypes.data,
+                                              b.ctypes.data, s.ctypes.data, len(a), C.byref(h)),
+              "advdiff")
+        self._finish(h)
+
+
+class H2Sampler(_SamplerBase):
+    """Sampler applying an existing H2 matrix (for rebuild / idempotence checks)."""
+
+    def __init__(self, mat):
+        self.mat = mat
+        self.ctx = mat.handle
+        self.fn = SAMPLER_FN(C.cast(lib()._dll.h2_sampler_h2_apply, C.c_void_p).value)
+
+
+class PythonSampler(_SamplerBase):
+    """Wrap a Python callable f(omega_tensor (ncols, n)) -> y_tensor on the device.
+
+    For tests (counting / failing wrappers); the callable must enqueue its work on
+    the current torch stream.
+    """
+
+    def __init__(self, n, func):
+        import torch
+        self.n = n
+        self.func = func
+        self.calls = 0
+        self.columns = 0
+
+        def cb(ctx, n_, ncols, om, ldo, y, ldy, stream):
+            try:
+                self.calls += 1
+                self.columns += ncols
+                omv = _wrap(om, ncols, ldo)
+                yv = _wrap(y, ncols, ldy)
+                out = func(omv[:, :n_])
+                if out is None:
+                    return 1
+                yv[:, :n_].copy_(out)
+                return 0
+            except Exception:  # noqa: BLE001 - reported as a callback failure
+                return 1
+
+        def _wrap(ptr, ncols, ld):
+            return _tensor_from_ptr(ptr, ncols, ld)
+
+        self._cb = SAMPLER_FN(cb)
+        self.fn = self._cb
+        self.ctx = None
+
+
+def _tensor_from_ptr(ptr, ncols, ld):
+    import torch
+
+    class _Iface:
+        def __init__(self):
+            self.__cuda_array_interface__ = {
+                "shape": (ncols, ld), "typestr": "<f8", "data": (ptr, False), "version": 2,
+                "strides": None}
+    return torch.as_tensor(_Iface(), device="cuda")
+
+
+# ---------------------------------------------------------------- construction
+def opts(**kw):
+    o = H2Opts()
+    lib().h2_opts_default(C.byref(o))
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+def ns_opts(**kw):
+    o = H2NSOpts()
+    lib().h2_ns_opts_default(C.byref(o))
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+def stats_dict(st, levels):
+    return dict(levels=st.levels, weak_rank=list(st.weak_rank[1:levels + 1]),
+                range_cols=list(st.range_cols[1:levels + 1]),
+                rounds=list(st.rounds[1:levels + 1]),
+                strong_rank=list(st.strong_rank[:levels + 1]), applies=st.applies,
+                norm=st.norm, converged=bool(st.converged), cap_hit=bool(st.cap_hit),
+                time_ms=list(st.time_ms))
+
+
+def build(tree, sampler, o=None, stream=None, allow_not_converged=True):
+    """Peeling + recompression (h2_build); returns (H2Matrix, stats dict)."""
+    if o is None:
+        o = opts()
+    h = C.c_void_p()
+    st = H2BuildStats()
+    allow = (0, 1) if allow_not_converged else (0,)
+    check(lib().h2_build(tree.handle, C.cast(sampler.fn, C.c_void_p), sampler.ctx, C.byref(o),
+                         _stream(stream), C.byref(h), C.byref(st)), "h2_build", allow)
+    return H2Matrix(h, tree), stats_dict(st, tree.L)
+
+
+def newton_schulz(A, o=None, stream=None):
+    """Hierarchical Newton-Schulz (h2_newton_schulz); returns (X, stats dict, status)."""
+    if o is None:
+        o = ns_opts()
+    h = C.c_void_p()
+    st = H2NSStats()
+    rc = lib().h2_newton_schulz(A.handle, C.byref(o), _stream(stream), C.byref(h), C.byref(st))
+    check(rc, "h2_newton_schulz", (0, 1, 2))
+    k = st.iterations
+    info = dict(iterations=k, norm=st.norm, resid=list(st.resid[:k + 1]),
+                applies=list(st.applies[:k]), max_rank=list(st.max_rank[:k]),
+                time_ms=list(st.time_ms), status=rc)
+    return H2Matrix(h, A.tree), info
+
+
+def residual_norm(A, X, rel=1e-2, max_iter=30, seed=1, iteration=0, stream=None):
+    out = C.c_double()
+    check(lib().h2_residual_norm(A.handle, X.handle, rel, max_iter, seed, iteration,
+                                 _stream(stream), C.byref(out)), "h2_residual_norm")
+    return out.value

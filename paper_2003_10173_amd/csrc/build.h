@@ -1,0 +1,45 @@
+// Construction interface shared by h2_build and the Newton-Schulz driver.
+#pragma once
+
+#include <memory>
+
+#include "internal.h"
+#include "linalg.h"
+
+namespace h2 {
+
+// Operator to be compressed, applied to tree-ordered column-major blocks
+// (ld = n): Y = A Omega.  `applies` counts columns.
+struct Sampler {
+  int64_t applies = 0;
+  virtual ~Sampler() = default;
+  virtual void apply(Ctx& c, int ncols, const double* om, double* y) = 0;
+};
+
+// Wraps a user h2_sampler_fn (user ordering) with the tree permutation.
+struct UserSampler : Sampler {
+  const h2_tree* t;
+  h2_sampler_fn fn;
+  void* ctx;
+  DevBuf buf;
+  UserSampler(const h2_tree* t_, h2_sampler_fn f, void* c_) : t(t_), fn(f), ctx(c_) {}
+  void apply(Ctx& c, int ncols, const double* om, double* y) override;
+};
+
+struct BuildParams {
+  int rank_cap = 32;
+  int oversample = 10;
+  double tol = 1e-4;
+  bool adaptive = true;
+  int max_rounds = 16;
+  uint64_t seed = 1;
+  uint32_t iteration = 0;
+  double norm = 0;        // > 0: use as ||A||_2; else estimate
+  double norm_rel = 1e-2;
+};
+
+// Peeling on the weak partition + recompression into the strong H2 of `t`.
+std::unique_ptr<h2_matrix> build_h2(const h2_tree* t, Sampler& S, const BuildParams& p, Ctx& c,
+                                    h2_build_stats* st, bool* converged);
+
+}  // namespace h2

@@ -1,0 +1,104 @@
+// Batched FP64 dense kernels of the construction (Sec. 3.3 sampling and
+// compression phases): generic batched GEMM, Householder QR with explicit
+// thin Q, one-sided Jacobi SVD, batched block copies and column norms.
+#pragma once
+
+#include <vector>
+
+#include "internal.h"
+
+namespace h2 {
+
+// Pinned host + device ring used to ship descriptor arrays to kernels without
+// synchronising the stream (a wrap of the ring synchronises once).
+struct Staging {
+  char* host = nullptr;
+  DevBuf dev;
+  size_t cap = 0, head = 0;
+  explicit Staging(size_t cap_bytes = (size_t)32 << 20);
+  ~Staging();
+  Staging(const Staging&) = delete;
+  Staging& operator=(const Staging&) = delete;
+  void* put(const void* src, size_t bytes, hipStream_t s);
+  void reset() { head = 0; }  // only when the stream is known to be idle
+};
+
+// Grow-only scratch arena reused across launches of one driver call.
+struct Scratch {
+  std::vector<DevBuf> bufs;
+  size_t used = 0;
+  double* get(size_t elems);  // returns a fresh region valid until clear()
+  void clear();               // only when the stream is idle
+};
+
+// C (M x N) = alpha op(A) op(B) + beta C, column-major; op(X) = X or X^T.
+struct GemmDesc {
+  const double* A;
+  const double* B;
+  double* C;
+  int M, N, K;
+  int lda, ldb, ldc;
+  int ta, tb;
+  double alpha, beta;
+};
+
+// In-place Householder QR of A (m x n): R (min(m,n) x n, upper) to R, explicit
+// thin Q (m x min(m,n)) to Q when Q is non-null.  A keeps the reflectors.
+struct QRDesc {
+  double* A;
+  int lda, m, n;
+  double* Q;
+  int ldq;
+  double* R;
+  int ldr;
+};
+
+// One-sided Jacobi SVD of A (m x n, m >= n, destroyed): sigma descending (n),
+// U (m x n) left singular vectors, V (n x n) right singular vectors (either may
+// be null).
+struct SVDDesc {
+  double* A;
+  int lda, m, n;
+  double* sigma;
+  double* U;
+  int ldu;
+  double* V;
+  int ldv;
+};
+
+// dst (rows x cols) = alpha * src (+ beta * dst), column-major blocks
+struct CopyDesc {
+  const double* src;
+  int lds;
+  double* dst;
+  int ldd;
+  int rows, cols;
+  double alpha, beta;
+  int trans;  // 1: dst = alpha src^T (src is cols x rows)
+};
+
+struct Ctx {
+  hipStream_t s = 0;
+  Staging stage;
+  Scratch scratch;
+  Ctx() = default;
+};
+
+// X[:, j] *= sigma[j] for a rows x cols block (column-major, ld)
+struct ScaleDesc {
+  double* X;
+  int ld, rows, cols;
+  const double* sigma;
+};
+
+void gemm_batched(Ctx& c, const std::vector<GemmDesc>& d);
+void scale_columns(Ctx& c, const std::vector<ScaleDesc>& d);
+void qr_batched(Ctx& c, const std::vector<QRDesc>& d);
+void svd_batched(Ctx& c, const std::vector<SVDDesc>& d);
+void copy_batched(Ctx& c, const std::vector<CopyDesc>& d);
+// out[i] = max_j || X_i[:, j] || for blocks X_i (rows_i x cols_i, ld_i)
+void colnorm_max_batched(Ctx& c, const std::vector<CopyDesc>& blocks, double* out);
+// zero a column-major block
+void zero_block(Ctx& c, double* p, int rows, int cols, int ld);
+
+}  // namespace h2

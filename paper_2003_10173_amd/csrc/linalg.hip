@@ -1,0 +1,533 @@
+// Batched FP64 dense kernels for the construction (Sec. 3.3: sampling by
+// batched products, compression by batched QR and SVD).  One launch covers
+// every block of a level; descriptors travel through a pinned staging ring.
+//
+// The GEMM is a 64x64-tile FP64 FMA kernel (FP64 vector and matrix peaks are
+// equal on CDNA4, so the vector path loses nothing for FP64); tall reductions
+// (K >> M, N) are split over K into partial tiles that a second kernel sums in
+// a fixed order, so results are deterministic.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "kernels_common.h"
+#include "linalg.h"
+
+namespace h2 {
+
+// ------------------------------------------------------------------ staging
+Staging::Staging(size_t cap_bytes) : cap(cap_bytes) {
+  H2_HIP(hipHostMalloc((void**)&host, cap, hipHostMallocDefault));
+  dev.alloc(cap);
+}
+Staging::~Staging() {
+  if (host) (void)hipHostFree(host);
+}
+void* Staging::put(const void* src, size_t bytes, hipStream_t s) {
+  const size_t n = (bytes + 255) & ~(size_t)255;
+  H2_CHECK(n <= cap, H2_EINVAL, "descriptor batch exceeds the staging ring");
+  if (head + n > cap) {
+    H2_HIP(hipStreamSynchronize(s));
+    head = 0;
+  }
+  std::memcpy(host + head, src, bytes);
+  char* d = dev.as<char>() + head;
+  H2_HIP(hipMemcpyAsync(d, host + head, bytes, hipMemcpyHostToDevice, s));
+  head += n;
+  return d;
+}
+
+double* Scratch::get(size_t elems) {
+  const size_t bytes = ((std::max<size_t>(elems, 1) * sizeof(double)) + 255) & ~(size_t)255;
+  if (bufs.empty() || used + bytes > bufs.back().bytes) {
+    bufs.emplace_back(std::max(bytes, (size_t)64 << 20));
+    used = 0;
+  }
+  double* p = (double*)(bufs.back().as<char>() + used);
+  used += bytes;
+  return p;
+}
+
+void Scratch::clear() {
+  // callers clear only when the stream is idle; merge growth into one buffer
+  if (bufs.size() > 1) {
+    size_t tot = 0;
+    for (auto& b : bufs) tot += b.bytes;
+    bufs.clear();
+    bufs.emplace_back(tot);
+  }
+  used = 0;
+}
+
+// ------------------------------------------------------------------ GEMM
+constexpr int TM = 64, TN = 64, TK = 16;
+
+struct GemmTask {
+  GemmDesc d;
+  int tiles_m, tiles_n;
+  int k0, k1;           // K range of this task
+  double* out;          // output (C or a partial buffer)
+  int ldo;
+  double beta;          // applied to `out`
+};
+
+__global__ __launch_bounds__(256) void k_gemm(const GemmTask* __restrict__ tasks,
+                                              const int64_t* __restrict__ tile_start, int ntasks) {
+  __shared__ double As[TK][TM + 1];
+  __shared__ double Bs[TK][TN + 1];
+  // locate the task of this block
+  int lo = 0, hi = ntasks - 1;
+  const int64_t b = blockIdx.x;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (tile_start[mid] <= b) lo = mid; else hi = mid - 1;
+  }
+  const GemmTask& t = tasks[lo];
+  const GemmDesc& d = t.d;
+  const int tile = (int)(b - tile_start[lo]);
+  const int bm = (tile % t.tiles_m) * TM, bn = (tile / t.tiles_m) * TN;
+  const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
+  double acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = 0;
+  for (int k0 = t.k0; k0 < t.k1; k0 += TK) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int e = tid + 256 * q;
+      int i, k;
+      if (!d.ta) { i = e & 63; k = e >> 6; } else { k = e & 15; i = e >> 4; }
+      const int gi = bm + i, gk = k0 + k;
+      double v = 0;
+      if (gi < d.M && gk < t.k1)
+        v = d.ta ? d.A[(size_t)gi * d.lda + gk] : d.A[(size_t)gk * d.lda + gi];
+      As[k][i] = v;
+      int j, kk;
+      if (!d.tb) { kk = e & 15; j = e >> 4; } else { j = e & 63; kk = e >> 6; }
+      const int gj = bn + j, gk2 = k0 + kk;
+      double w = 0;
+      if (gj < d.N && gk2 < t.k1)
+        w = d.tb ? d.B[(size_t)gk2 * d.ldb + gj] : d.B[(size_t)gj * d.ldb + gk2];
+      Bs[kk][j] = w;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < TK; ++k) {
+      double a[4], bb[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) a[i] = As[k][tx + 16 * i];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) bb[j] = Bs[k][ty + 16 * j];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = fma(a[i], bb[j], acc[i][j]);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int gi = bm + tx + 16 * i, gj = bn + ty + 16 * j;
+      if (gi < d.M && gj < d.N) {
+        double* o = t.out + (size_t)gj * t.ldo + gi;
+        const double v = d.alpha * acc[i][j];
+        *o = t.beta == 0.0 ? v : v + t.beta * *o;
+      }
+    }
+}
+
+struct ReduceTask {
+  double* C;
+  int ldc, M, N;
+  double beta;
+  const double* parts;  // nparts consecutive M x N blocks (ld = M)
+  int nparts;
+};
+
+__global__ void k_reduce_parts(const ReduceTask* __restrict__ tasks, int ntasks) {
+  const ReduceTask& t = tasks[blockIdx.y];
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (int64_t)t.M * t.N) return;
+  const int i = (int)(e % t.M), j = (int)(e / t.M);
+  double s = 0;
+  for (int p = 0; p < t.nparts; ++p) s += t.parts[(size_t)p * t.M * t.N + e];
+  double* o = t.C + (size_t)j * t.ldc + i;
+  *o = t.beta == 0.0 ? s : s + t.beta * *o;
+}
+
+void gemm_batched(Ctx& c, const std::vector<GemmDesc>& ds) {
+  std::vector<GemmTask> tasks;
+  std::vector<ReduceTask> reds;
+  constexpr int KCHUNK = 1024;
+  for (const auto& d : ds) {
+    if (d.M <= 0 || d.N <= 0) continue;
+    const int tm = (d.M + TM - 1) / TM, tn = (d.N + TN - 1) / TN;
+    if (d.K <= 0) {
+      // C = beta C only
+      GemmTask t{d, tm, tn, 0, 0, d.C, d.ldc, d.beta};
+      tasks.push_back(t);
+      continue;
+    }
+    const int nsplit = (d.K > 2 * KCHUNK && tm * tn <= 64) ? std::min(64, (d.K + KCHUNK - 1) / KCHUNK) : 1;
+    if (nsplit == 1) {
+      tasks.push_back(GemmTask{d, tm, tn, 0, d.K, d.C, d.ldc, d.beta});
+    } else {
+      double* parts = c.scratch.get((size_t)nsplit * d.M * d.N);
+      const int chunk = ((d.K + nsplit - 1) / nsplit + TK - 1) / TK * TK;
+      int used = 0;
+      for (int p = 0; p < nsplit; ++p) {
+        const int k0 = p * chunk, k1 = std::min(d.K, k0 + chunk);
+        if (k0 >= k1) break;
+        tasks.push_back(GemmTask{d, tm, tn, k0, k1, parts + (size_t)p * d.M * d.N, d.M, 0.0});
+        ++used;
+      }
+      reds.push_back(ReduceTask{d.C, d.ldc, d.M, d.N, d.beta, parts, used});
+    }
+  }
+  if (tasks.empty()) return;
+  std::vector<int64_t> start(tasks.size() + 1, 0);
+  for (size_t i = 0; i < tasks.size(); ++i)
+    start[i + 1] = start[i] + (int64_t)tasks[i].tiles_m * tasks[i].tiles_n;
+  auto* dt = (GemmTask*)c.stage.put(tasks.data(), tasks.size() * sizeof(GemmTask), c.s);
+  auto* dsf = (int64_t*)c.stage.put(start.data(), start.size() * sizeof(int64_t), c.s);
+  H2_CHECK(start.back() < (int64_t)1 << 31, H2_EINVAL, "GEMM batch too large");
+  k_gemm<<<(unsigned)start.back(), 256, 0, c.s>>>(dt, dsf, (int)tasks.size());
+  H2_LAUNCH_CHECK();
+  if (!reds.empty()) {
+    int64_t mx = 0;
+    for (auto& r : reds) mx = std::max(mx, (int64_t)r.M * r.N);
+    auto* dr = (ReduceTask*)c.stage.put(reds.data(), reds.size() * sizeof(ReduceTask), c.s);
+    dim3 grid((unsigned)((mx + 255) / 256), (unsigned)reds.size());
+    k_reduce_parts<<<grid, 256, 0, c.s>>>(dr, (int)reds.size());
+    H2_LAUNCH_CHECK();
+  }
+}
+
+// ------------------------------------------------------------------ Householder QR
+constexpr int QR_VCACHE = 8192;  // rows of the current reflector kept in LDS
+
+__global__ __launch_bounds__(256) void k_qr(const QRDesc* __restrict__ descs) {
+  const QRDesc d = descs[blockIdx.x];
+  __shared__ double vcache[QR_VCACHE];
+  __shared__ double taus[1024];
+  __shared__ double red[8];
+  __shared__ double bcast[2];
+  const int m = d.m, n = d.n, kmin = min(m, n);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  double* A = d.A;
+  const int lda = d.lda;
+  for (int j = 0; j < kmin; ++j) {
+    double* aj = A + (size_t)j * lda;
+    double s = 0;
+    for (int i = j + 1 + tid; i < m; i += 256) s += aj[i] * aj[i];
+    s = block_sum256(s, red);
+    if (tid == 0) {
+      const double alpha = aj[j];
+      double tau = 0, scale = 0;
+      if (s != 0.0) {
+        const double norm = sqrt(alpha * alpha + s);
+        const double beta = alpha >= 0 ? -norm : norm;
+        tau = (beta - alpha) / beta;
+        scale = 1.0 / (alpha - beta);
+        aj[j] = beta;
+      }
+      bcast[0] = tau;
+      bcast[1] = scale;
+      taus[j] = tau;
+    }
+    __syncthreads();
+    const double tau = bcast[0], scale = bcast[1];
+    const bool cached = (m - j) <= QR_VCACHE;
+    for (int i = j + 1 + tid; i < m; i += 256) {
+      const double v = aj[i] * scale;
+      aj[i] = v;
+      if (cached) vcache[i - j] = v;
+    }
+    if (tid == 0 && cached) vcache[0] = 1.0;
+    __syncthreads();
+    if (tau != 0.0) {
+      for (int col = j + 1 + wave; col < n; col += 4) {
+        double* ac = A + (size_t)col * lda;
+        double w = 0;
+        for (int i = j + lane; i < m; i += 64) {
+          const double v = i == j ? 1.0 : (cached ? vcache[i - j] : aj[i]);
+          w += v * ac[i];
+        }
+        w = wave_sum(w) * tau;
+        for (int i = j + lane; i < m; i += 64) {
+          const double v = i == j ? 1.0 : (cached ? vcache[i - j] : aj[i]);
+          ac[i] -= v * w;
+        }
+      }
+    }
+    __syncthreads();
+  }
+  // R (kmin x n, upper trapezoidal)
+  if (d.R) {
+    for (int e = tid; e < kmin * n; e += 256) {
+      const int i = e % kmin, c = e / kmin;
+      d.R[(size_t)c * d.ldr + i] = i <= c ? A[(size_t)c * lda + i] : 0.0;
+    }
+  }
+  if (!d.Q) return;
+  // explicit thin Q = H_0 ... H_{kmin-1} [I; 0]
+  for (int e = tid; e < m * kmin; e += 256) {
+    const int i = e % m, c = e / m;
+    d.Q[(size_t)c * d.ldq + i] = i == c ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  for (int j = kmin - 1; j >= 0; --j) {
+    const double tau = taus[j];
+    if (tau == 0.0) continue;
+    const double* aj = A + (size_t)j * lda;
+    const bool cached = (m - j) <= QR_VCACHE;
+    if (cached) {
+      for (int i = j + 1 + tid; i < m; i += 256) vcache[i - j] = aj[i];
+      if (tid == 0) vcache[0] = 1.0;
+    }
+    __syncthreads();
+    for (int col = j + wave; col < kmin; col += 4) {
+      double* qc = d.Q + (size_t)col * d.ldq;
+      double w = 0;
+      for (int i = j + lane; i < m; i += 64) {
+        const double v = i == j ? 1.0 : (cached ? vcache[i - j] : aj[i]);
+        w += v * qc[i];
+      }
+      w = wave_sum(w) * tau;
+      for (int i = j + lane; i < m; i += 64) {
+        const double v = i == j ? 1.0 : (cached ? vcache[i - j] : aj[i]);
+        qc[i] -= v * w;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+void qr_batched(Ctx& c, const std::vector<QRDesc>& ds) {
+  std::vector<QRDesc> v;
+  for (auto& d : ds) {
+    if (d.m <= 0 || d.n <= 0) continue;
+    H2_CHECK(std::min(d.m, d.n) <= 1024, H2_EINVAL, "QR: more than 1024 columns");
+    v.push_back(d);
+  }
+  if (v.empty()) return;
+  auto* dd = (QRDesc*)c.stage.put(v.data(), v.size() * sizeof(QRDesc), c.s);
+  k_qr<<<(unsigned)v.size(), 256, 0, c.s>>>(dd);
+  H2_LAUNCH_CHECK();
+}
+
+// ------------------------------------------------------------------ Jacobi SVD
+__global__ __launch_bounds__(256) void k_svd(const SVDDesc* __restrict__ descs) {
+  const SVDDesc d = descs[blockIdx.x];
+  const int n = d.n, m = d.m;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  __shared__ int rotated;
+  __shared__ double sig[1024];
+  __shared__ int order[1024];
+  double* A = d.A;
+  const int lda = d.lda;
+  double* V = d.V;
+  const int ldv = d.ldv;
+  const bool wantV = V != nullptr;
+  if (wantV)
+    for (int e = tid; e < n * n; e += 256) V[(size_t)(e / n) * ldv + e % n] = (e / n == e % n) ? 1.0 : 0.0;
+  const int np = n + (n & 1);
+  for (int sweep = 0; sweep < 60; ++sweep) {
+    if (tid == 0) rotated = 0;
+    __syncthreads();
+    for (int r = 0; r < np - 1; ++r) {
+      for (int k = wave; k < np / 2; k += 4) {
+        int a, b;
+        if (k == 0) { a = np - 1; b = r; }
+        else { a = (r + k) % (np - 1); b = (r - k + (np - 1)) % (np - 1); }
+        if (a >= n || b >= n) continue;
+        if (a > b) { int tmp = a; a = b; b = tmp; }
+        double* ca = A + (size_t)a * lda;
+        double* cb = A + (size_t)b * lda;
+        double al = 0, be = 0, ga = 0;
+        for (int i = lane; i < m; i += 64) {
+          const double x = ca[i], y = cb[i];
+          al += x * x;
+          be += y * y;
+          ga += x * y;
+        }
+        al = wave_sum(al);
+        be = wave_sum(be);
+        ga = wave_sum(ga);
+        if (ga == 0.0 || !(fabs(ga) > 1e-15 * sqrt(al) * sqrt(be))) continue;
+        const double zeta = (be - al) / (2.0 * ga);
+        double t;
+        if (fabs(zeta) > 1e150) t = 0.5 / zeta;
+        else t = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+        const double cs = 1.0 / sqrt(1.0 + t * t), sn = cs * t;
+        for (int i = lane; i < m; i += 64) {
+          const double x = ca[i], y = cb[i];
+          ca[i] = cs * x - sn * y;
+          cb[i] = sn * x + cs * y;
+        }
+        if (wantV) {
+          double* va = V + (size_t)a * ldv;
+          double* vb = V + (size_t)b * ldv;
+          for (int i = lane; i < n; i += 64) {
+            const double x = va[i], y = vb[i];
+            va[i] = cs * x - sn * y;
+            vb[i] = sn * x + cs * y;
+          }
+        }
+        if (lane == 0) rotated = 1;
+      }
+      __syncthreads();
+    }
+    if (!rotated) break;
+    __syncthreads();
+  }
+  // singular values = column norms; sort descending (stable)
+  for (int col = wave; col < n; col += 4) {
+    const double* ca = A + (size_t)col * lda;
+    double s = 0;
+    for (int i = lane; i < m; i += 64) s += ca[i] * ca[i];
+    s = wave_sum(s);
+    if (lane == 0) sig[col] = sqrt(s);
+  }
+  __syncthreads();
+  if (tid == 0) {
+    for (int i = 0; i < n; ++i) order[i] = i;
+    for (int i = 1; i < n; ++i) {
+      const int key = order[i];
+      int j = i - 1;
+      while (j >= 0 && sig[order[j]] < sig[key]) { order[j + 1] = order[j]; --j; }
+      order[j + 1] = key;
+    }
+  }
+  __syncthreads();
+  for (int e = tid; e < n; e += 256) d.sigma[e] = sig[order[e]];
+  if (d.U) {
+    for (int e = tid; e < m * n; e += 256) {
+      const int i = e % m, r = e / m;
+      const int src = order[r];
+      const double s = sig[src];
+      d.U[(size_t)r * d.ldu + i] = s > 0 ? A[(size_t)src * lda + i] / s : 0.0;
+    }
+  }
+  __syncthreads();
+  if (wantV) {
+    // permute V columns in place through A (A is no longer needed)
+    for (int e = tid; e < n * n; e += 256) {
+      const int i = e % n, c = e / n;
+      A[(size_t)c * lda + i] = V[(size_t)c * ldv + i];
+    }
+    __syncthreads();
+    for (int e = tid; e < n * n; e += 256) {
+      const int i = e % n, r = e / n;
+      V[(size_t)r * ldv + i] = A[(size_t)order[r] * lda + i];
+    }
+  }
+}
+
+void svd_batched(Ctx& c, const std::vector<SVDDesc>& ds) {
+  std::vector<SVDDesc> v;
+  for (auto& d : ds) {
+    if (d.n <= 0) continue;
+    H2_CHECK(d.n <= 1024, H2_EINVAL, "SVD: more than 1024 columns");
+    H2_CHECK(d.m >= d.n, H2_EINVAL, "SVD: needs m >= n");
+    H2_CHECK(d.sigma != nullptr, H2_EINVAL, "SVD: sigma output required");
+    v.push_back(d);
+  }
+  if (v.empty()) return;
+  auto* dd = (SVDDesc*)c.stage.put(v.data(), v.size() * sizeof(SVDDesc), c.s);
+  k_svd<<<(unsigned)v.size(), 256, 0, c.s>>>(dd);
+  H2_LAUNCH_CHECK();
+}
+
+// ------------------------------------------------------------------ copies, norms
+__global__ void k_copy(const CopyDesc* __restrict__ ds) {
+  const CopyDesc d = ds[blockIdx.y];
+  const int64_t tot = (int64_t)d.rows * d.cols;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < tot;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int i = (int)(e % d.rows), j = (int)(e / d.rows);
+    const double v = d.trans ? d.src[(size_t)i * d.lds + j] : d.src[(size_t)j * d.lds + i];
+    double* o = d.dst + (size_t)j * d.ldd + i;
+    *o = d.beta == 0.0 ? d.alpha * v : d.alpha * v + d.beta * *o;
+  }
+}
+
+void copy_batched(Ctx& c, const std::vector<CopyDesc>& ds) {
+  std::vector<CopyDesc> v;
+  int64_t mx = 0;
+  for (auto& d : ds)
+    if (d.rows > 0 && d.cols > 0) {
+      v.push_back(d);
+      mx = std::max(mx, (int64_t)d.rows * d.cols);
+    }
+  if (v.empty()) return;
+  H2_CHECK(v.size() < 65535, H2_EINVAL, "copy batch too large");
+  auto* dd = (CopyDesc*)c.stage.put(v.data(), v.size() * sizeof(CopyDesc), c.s);
+  dim3 grid((unsigned)std::min<int64_t>((mx + 255) / 256, 1024), (unsigned)v.size());
+  k_copy<<<grid, 256, 0, c.s>>>(dd);
+  H2_LAUNCH_CHECK();
+}
+
+__global__ __launch_bounds__(256) void k_colnorm_max(const CopyDesc* __restrict__ ds,
+                                                     double* __restrict__ out) {
+  const CopyDesc d = ds[blockIdx.x];
+  __shared__ double red[4];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  double best = 0;
+  for (int j = wave; j < d.cols; j += 4) {
+    const double* col = d.src + (size_t)j * d.lds;
+    double s = 0;
+    for (int i = lane; i < d.rows; i += 64) s += col[i] * col[i];
+    s = wave_sum(s);
+    best = fmax(best, sqrt(s));
+  }
+  if (lane == 0) red[wave] = best;
+  __syncthreads();
+  if (threadIdx.x == 0) out[blockIdx.x] = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+}
+
+void colnorm_max_batched(Ctx& c, const std::vector<CopyDesc>& blocks, double* out) {
+  if (blocks.empty()) return;
+  auto* dd = (CopyDesc*)c.stage.put(blocks.data(), blocks.size() * sizeof(CopyDesc), c.s);
+  k_colnorm_max<<<(unsigned)blocks.size(), 256, 0, c.s>>>(dd, out);
+  H2_LAUNCH_CHECK();
+}
+
+__global__ void k_scale_cols(const ScaleDesc* __restrict__ ds) {
+  const ScaleDesc d = ds[blockIdx.y];
+  const int64_t tot = (int64_t)d.rows * d.cols;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < tot;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int i = (int)(e % d.rows), j = (int)(e / d.rows);
+    d.X[(size_t)j * d.ld + i] *= d.sigma[j];
+  }
+}
+
+void scale_columns(Ctx& c, const std::vector<ScaleDesc>& ds) {
+  if (ds.empty()) return;
+  H2_CHECK(ds.size() < 65535, H2_EINVAL, "scale batch too large");
+  int64_t mx = 0;
+  for (auto& d : ds) mx = std::max(mx, (int64_t)d.rows * d.cols);
+  auto* dd = (ScaleDesc*)c.stage.put(ds.data(), ds.size() * sizeof(ScaleDesc), c.s);
+  dim3 grid((unsigned)std::min<int64_t>((mx + 255) / 256, 1024), (unsigned)ds.size());
+  k_scale_cols<<<grid, 256, 0, c.s>>>(dd);
+  H2_LAUNCH_CHECK();
+}
+
+__global__ void k_zero(double* p, int rows, int cols, int ld) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (int64_t)rows * cols) return;
+  p[(size_t)(e / rows) * ld + e % rows] = 0.0;
+}
+
+void zero_block(Ctx& c, double* p, int rows, int cols, int ld) {
+  const int64_t tot = (int64_t)rows * cols;
+  if (tot <= 0) return;
+  k_zero<<<(unsigned)((tot + 255) / 256), 256, 0, c.s>>>(p, rows, cols, ld);
+  H2_LAUNCH_CHECK();
+}
+
+}  // namespace h2

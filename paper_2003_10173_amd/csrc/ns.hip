@@ -1,0 +1,205 @@
+// Hierarchical Newton-Schulz inversion (Appendix A).  Alg. 1: the iteration
+// X <- (2I - X A) X for a symmetric positive definite A started from a scaled
+// identity; Alg. 2: every iterate is rebuilt by the construction of Sec. 3.3
+// at a threshold eps_k chosen per iteration; Alg. 3: the sampler of the next
+// iterate evaluates (2I - X_k A) X_k Omega, here as W = X_k Omega,
+// Y = 2W - X_k (A W) -- three HGEMVs per block of samples.
+//
+// The residual E = ||I - A X||_2 is estimated by the power method on R^T R
+// (R v = v - A (X v), R^T w = w - X (A w)); two significant digits by default
+// (Sec. 3.2 norms).  Iterates are built to absolute accuracy eps_k / ||A||_2,
+// the scale at which their error enters I - A X.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <functional>
+
+#include "build.h"
+#include "kernels_common.h"
+#include "vecops.h"
+
+namespace h2 {
+
+h2_status guarded_status(const std::function<void()>& f);
+void matrix_copy_convert(const h2_matrix* A, h2_matrix* B, double scale, hipStream_t s);
+void matrix_identity(h2_matrix* A, const h2_tree* t, double alpha, hipStream_t s);
+
+static double now_ms2() {
+  using namespace std::chrono;
+  return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
+}
+
+// Y = (2I - X A) X Omega in tree order
+struct NSSampler : Sampler {
+  const h2_matrix* X;
+  const h2_matrix* A;
+  DevBuf buf;
+  NSSampler(const h2_matrix* x, const h2_matrix* a) : X(x), A(a) {}
+  void apply(Ctx& c, int ncols, const double* om, double* y) override {
+    if (ncols <= 0) return;
+    const int n = X->tree->n;
+    buf.reserve((size_t)2 * n * ncols * sizeof(double));
+    double* W = buf.as<double>();
+    double* T = W + (size_t)n * ncols;
+    gemv_tree_f64(X, ncols, 1.0, om, n, 0.0, W, n, c.s);
+    gemv_tree_f64(A, ncols, 1.0, W, n, 0.0, T, n, c.s);
+    axpby(n, ncols, 2.0, W, n, 0.0, y, n, c.s);
+    gemv_tree_f64(X, ncols, -1.0, T, n, 1.0, y, n, c.s);
+    applies += ncols;
+  }
+};
+
+// Sampler that applies one H2 matrix (tree order)
+struct GemvSampler : Sampler {
+  const h2_matrix* A;
+  explicit GemvSampler(const h2_matrix* a) : A(a) {}
+  void apply(Ctx& c, int ncols, const double* om, double* y) override {
+    gemv_tree_f64(A, ncols, 1.0, om, A->tree->n, 0.0, y, A->tree->n, c.s);
+    applies += ncols;
+  }
+};
+
+double residual_norm_device(const h2_matrix* A, const h2_matrix* X, double rel, int max_it,
+                            uint64_t seed, uint32_t iteration, hipStream_t s) {
+  const int n = A->tree->n;
+  DevBuf tmp((size_t)2 * n * sizeof(double));
+  double* t1 = tmp.as<double>();
+  double* r = t1 + n;
+  auto op = [&](const double* v, double* w) {
+    // r = v - A (X v);  w = r - X (A r)
+    gemv_tree_f64(X, 1, 1.0, v, n, 0.0, t1, n, s);
+    H2_HIP(hipMemcpyAsync(r, v, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    gemv_tree_f64(A, 1, -1.0, t1, n, 1.0, r, n, s);
+    gemv_tree_f64(A, 1, 1.0, r, n, 0.0, t1, n, s);
+    H2_HIP(hipMemcpyAsync(w, r, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    gemv_tree_f64(X, 1, -1.0, t1, n, 1.0, w, n, s);
+  };
+  return power_norm_device(n, op, seed, iteration, rel, 3, max_it, s, nullptr, PHASE_RESID, true);
+}
+
+std::unique_ptr<h2_matrix> ns_iterate(const h2_matrix* A, const h2_ns_opts& o, hipStream_t s,
+                                      h2_ns_stats* st, h2_status* status) {
+  const h2_tree* t = A->tree;
+  const double t_begin = now_ms2();
+  h2_ns_stats local{};
+  h2_ns_stats& stats = st ? *st : local;
+  stats = h2_ns_stats{};
+  const int n = t->n;
+  const double norm_rel = o.norm_rel > 0 ? o.norm_rel : 1e-2;
+  const double resid_rel = o.resid_rel > 0 ? o.resid_rel : 1e-2;
+  const double eps_build = o.eps_build > 0 ? o.eps_build : o.eps / 10.0;
+  H2_CHECK(eps_build > 0, H2_EINVAL, "need eps > 0 or eps_build > 0");
+  auto gop = [&](const double* v, double* w) { gemv_tree_f64(A, 1, 1.0, v, n, 0.0, w, n, s); };
+  const double nuA = power_norm_device(n, gop, o.seed, 0, norm_rel, 3, norm_rel >= 1e-2 ? 30 : 500,
+                                       s, nullptr);
+  H2_CHECK(std::isfinite(nuA) && nuA > 0, H2_ENUMERIC, "norm of A is zero or not finite");
+  stats.norm = nuA;
+  auto X = std::make_unique<h2_matrix>();
+  if (o.x0 == 0) {
+    matrix_identity(X.get(), t, 1.0 / nuA, s);
+  } else {
+    matrix_layout(X.get(), t, A->rank);
+    matrix_alloc(X.get(), H2_FP64);
+    matrix_copy_convert(A, X.get(), 1.0 / (nuA * nuA), s);
+  }
+  BuildParams bp;
+  bp.rank_cap = o.rank_cap > 0 ? o.rank_cap : t->leaf;
+  bp.oversample = o.oversample;
+  bp.adaptive = o.adaptive != 0;
+  bp.max_rounds = o.max_rounds;
+  bp.seed = o.seed;
+  bp.norm = 1.0 / nuA;
+  Ctx c;
+  c.s = s;
+  *status = H2_ENOTCONVERGED;
+  int k = 0;
+  double prevE = -1;
+  while (true) {
+    double t0 = now_ms2();
+    const int max_it = resid_rel >= 1e-2 ? 30 : 3000;
+    const double E = residual_norm_device(A, X.get(), resid_rel, max_it, o.seed, (uint32_t)k, s);
+    stats.time_ms[0] += now_ms2() - t0;
+    H2_CHECK(std::isfinite(E), H2_ENUMERIC, "residual is not finite");
+    if (k <= H2_MAX_NS_ITERS) stats.resid[k] = E;
+    if (o.eps > 0 && E <= o.eps) { *status = H2_OK; break; }
+    if (k >= 1 && E > prevE && E > 1.0) { *status = H2_EDIVERGED; break; }
+    if (k >= o.max_iter || k >= H2_MAX_NS_ITERS) break;
+    prevE = E;
+    const double eps_k = o.dynamic ? std::min(std::max(0.1 * E * E, eps_build), 1e-2) : eps_build;
+    bp.tol = eps_k;
+    bp.iteration = (uint32_t)(k + 1);
+    NSSampler S(X.get(), A);
+    h2_build_stats bst{};
+    bool conv = true;
+    t0 = now_ms2();
+    auto Xn = build_h2(t, S, bp, c, &bst, &conv);
+    stats.time_ms[1] += now_ms2() - t0;
+    stats.applies[k] = bst.applies;
+    int mr = 0;
+    for (int l = 0; l <= t->L; ++l) mr = std::max(mr, bst.strong_rank[l]);
+    stats.max_rank[k] = mr;
+    X = std::move(Xn);
+    ++k;
+  }
+  stats.iterations = k;
+  stats.time_ms[3] = now_ms2() - t_begin;
+  return X;
+}
+
+}  // namespace h2
+
+using namespace h2;
+
+extern "C" {
+
+void h2_ns_opts_default(h2_ns_opts* o) {
+  if (!o) return;
+  *o = h2_ns_opts{};
+  o->eps = 1e-4;
+  o->max_iter = 60;
+  o->x0 = 0;
+  o->dynamic = 1;
+  o->eps_build = 0;
+  o->norm_rel = 1e-2;
+  o->resid_rel = 1e-2;
+  o->rank_cap = 0;
+  o->oversample = 10;
+  o->adaptive = 1;
+  o->max_rounds = 16;
+  o->seed = 1;
+  o->prec = H2_FP64;
+}
+
+h2_status h2_newton_schulz(const h2_matrix* A, const h2_ns_opts* opts, hipStream_t stream,
+                           h2_matrix** X_out, h2_ns_stats* stats) {
+  h2_status result = H2_OK;
+  h2_status st = guarded_status([&] {
+    H2_CHECK(A && opts && X_out, H2_EINVAL, "null argument");
+    H2_CHECK(A->st.prec == H2_FP64, H2_EINVAL, "Newton-Schulz needs an FP64 matrix");
+    H2_CHECK(opts->max_iter >= 0, H2_EINVAL, "max_iter must be >= 0");
+    H2_CHECK(opts->prec == H2_FP64, H2_EINVAL, "Newton-Schulz precision must be FP64 here");
+    auto X = ns_iterate(A, *opts, stream, stats, &result);
+    *X_out = X.release();
+  });
+  return st != H2_OK ? st : result;
+}
+
+h2_status h2_residual_norm(const h2_matrix* A, const h2_matrix* X, double rel, int max_iter,
+                           uint64_t seed, uint32_t iteration, hipStream_t stream, double* out) {
+  return guarded_status([&] {
+    H2_CHECK(A && X && out, H2_EINVAL, "null argument");
+    H2_CHECK(A->tree == X->tree, H2_EINVAL, "A and X must share a tree");
+    H2_CHECK(A->st.prec == H2_FP64 && X->st.prec == H2_FP64, H2_EINVAL, "FP64 matrices needed");
+    *out = residual_norm_device(A, X, rel > 0 ? rel : 1e-2, max_iter > 0 ? max_iter : 30, seed,
+                                iteration, stream);
+  });
+}
+
+int h2_sampler_h2_apply(void* ctx, int n, int ncols, const double* omega, int ld_omega, double* y,
+                        int ld_y, hipStream_t stream) {
+  h2_status st = h2_gemv((const h2_matrix*)ctx, ncols, 1.0, omega, ld_omega, 0.0, y, ld_y, stream);
+  (void)n;
+  return st == H2_OK ? 0 : 1;
+}
+
+}  // extern "C"

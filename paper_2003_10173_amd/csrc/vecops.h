@@ -1,0 +1,28 @@
+// Small device vector utilities used by the drivers (norms, scaling, fills).
+#pragma once
+
+#include <functional>
+
+#include "internal.h"
+
+namespace h2 {
+
+// v[r] = Gaussian entry (tree row r, column col) of stream key, r < n, for
+// `ncols` columns of a column-major array with leading dimension ld
+void gauss_fill(uint64_t key, int n, int ncols, int col0, double* v, int ld, hipStream_t s);
+// Euclidean norm of a device vector (synchronises the stream)
+double nrm2(int n, const double* v, hipStream_t s);
+// v *= a
+void scal(int n, double a, double* v, hipStream_t s);
+// y = a x + b y (column-major blocks of ncols columns)
+void axpby(int n, int ncols, double a, const double* x, int ldx, double b, double* y, int ldy,
+           hipStream_t s);
+
+// Power method on a symmetric operator op(v, w): w = A v (device, n-vectors).
+// Start vector: Gaussian stream (seed, phase, 0, 0, iteration), column 0.
+// Stops when |nu - nu_prev| <= rel nu after at least min_it steps.
+double power_norm_device(int n, const std::function<void(const double*, double*)>& op,
+                         uint64_t seed, uint32_t iteration, double rel, int min_it, int max_it,
+                         hipStream_t s, int* iters, int phase = PHASE_NORM, bool sqrt_out = false);
+
+}  // namespace h2

@@ -1,0 +1,109 @@
+"""GPU parity of HGEMV (Sec. 3.2 four-stage product) against the oracle.
+
+Oracle-built H2 matrices are imported into the device layout through the C ABI
+and applied to seeded vectors; FP64 must match the oracle's product within
+1e-12 relative (a handful of reordered sums per entry).
+"""
+import numpy as np
+import pytest
+
+import seeded_inputs as si
+from oracle.h2 import H2Matrix as OH2
+from oracle.hessians import KernelHessian, tree_order
+from oracle.ns import build as obuild, power_norm
+from oracle.tree import Tree as OTree
+from tests.h2_helpers import oracle_to_packed, rel_err
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+h2 = pytest.importorskip("paper_2003_10173_amd")
+
+
+def _random_h2(T, kmax, seed):
+    g = np.random.Generator(np.random.PCG64(seed))
+    H = OH2(T)
+    L = T.L
+    for l in range(2, L + 1):
+        H.rank[l][:] = g.integers(0, kmax + 1, size=1 << l)
+    for i in range(1 << L):
+        H.U[i] = g.standard_normal((T.size(L, i), H.rank[L][i]))
+    for l in range(1, L + 1):
+        for i in range(1 << l):
+            H.E[l][i] = g.standard_normal((H.rank[l][i], H.rank[l - 1][i // 2]))
+        for (t, s) in T.far[l]:
+            H.S[l][(t, s)] = g.standard_normal((H.rank[l][t], H.rank[l][s]))
+    for (t, s) in T.near:
+        H.D[(t, s)] = g.standard_normal((T.size(L, t), T.size(L, s)))
+    return H
+
+
+@pytest.fixture(scope="module")
+def kernel1d():
+    cfg = si.config_kernel1d()
+    T = OTree(cfg["points"], cfg["leaf"], cfg["eta"])
+    K = KernelHessian(cfg["points"], cfg["ell"], cfg["shift"])
+    A = tree_order(K.apply, T.perm)
+    nu, _ = power_norm(A, T.n, cfg["seed"])
+    H, _ = obuild(A, T, cfg["tol"], nu, cfg["cap"], cfg["p"], adaptive=False, seed=cfg["seed"])
+    return cfg, T, H
+
+
+def _run(H, T, nv, seed, alpha=1.0, beta=0.0):
+    gt = h2.Tree(T.points, T.leaf_size, T.eta)
+    G = h2.H2Matrix.from_host(gt, *oracle_to_packed(H))
+    x = si.gaussian_vectors(T.n, nv, seed)
+    y0 = si.gaussian_vectors(T.n, nv, seed + 1)
+    xd = torch.tensor(x.T.copy(), device="cuda")
+    yd = torch.tensor(y0.T.copy(), device="cuda")
+    G.gemv(xd, yd, alpha=alpha, beta=beta)
+    torch.cuda.synchronize()
+    want = alpha * H.matvec(x) + beta * y0
+    return yd.cpu().numpy().T, want, G
+
+
+@pytest.mark.parametrize("nv", [1, 16, 33])
+def test_hgemv_kernel1d_matches_oracle(kernel1d, nv):
+    cfg, T, H = kernel1d
+    got, want, _ = _run(H, T, nv, 101)
+    assert rel_err(got, want) <= 1e-12
+
+
+@pytest.mark.parametrize("shape,leaf,kmax,nv", [
+    ((2100, 2), 64, 12, 7),       # ragged leaves, random ranks incl. zero
+    ((777, 1), 20, 6, 64),        # 1D, leaf 20, many vectors
+    ((1500, 3), 32, 9, 40),       # 3D, two column chunks with a ragged tail
+])
+def test_hgemv_random_h2_matches_oracle(shape, leaf, kmax, nv):
+    pts = np.random.Generator(np.random.PCG64(shape[0])).uniform(size=shape)
+    T = OTree(pts, leaf, 0.7)
+    H = _random_h2(T, kmax, 3)
+    got, want, G = _run(H, T, nv, 5, alpha=0.75, beta=-1.5)
+    assert rel_err(got, want) <= 1e-12
+    r, U, E, S, D = G.export()
+    r0, U0, E0, S0, D0 = oracle_to_packed(H)
+    assert np.array_equal(r, r0) and np.array_equal(D, D0) and np.array_equal(S, S0)
+
+
+def test_hgemv_single_leaf_and_identity():
+    T = OTree(np.linspace(0, 1, 40), 64, 0.7)     # L = 0: one dense leaf
+    H = _random_h2(T, 0, 1)
+    got, want, _ = _run(H, T, 3, 2)
+    assert rel_err(got, want) <= 1e-13
+    gt = h2.Tree(np.linspace(0, 1, 300), 32, 0.7)
+    I = h2.H2Matrix.identity(gt, 2.5)
+    x = torch.randn(4, 300, dtype=torch.float64, device="cuda")
+    assert torch.allclose(I.gemv(x), 2.5 * x, rtol=0, atol=0)
+
+
+def test_hgemv_reduced_precision_storage(kernel1d):
+    cfg, T, H = kernel1d
+    gt = h2.Tree(T.points, T.leaf_size, T.eta)
+    G = h2.H2Matrix.from_host(gt, *oracle_to_packed(H))
+    x = si.gaussian_vectors(T.n, 16, 7)
+    want = H.matvec(x)
+    xf = torch.tensor(x.T.copy(), device="cuda", dtype=torch.float32)
+    for prec, tol in ((h2.H2_FP64, 1e-6), (h2.H2_FP32, 1e-6), (h2.H2_BF16, 1e-2)):
+        Gp = G if prec == h2.H2_FP64 else G.convert(prec)
+        y = Gp.gemv(xf)
+        torch.cuda.synchronize()
+        assert rel_err(y.cpu().numpy().T, want) <= tol, prec
