@@ -19,7 +19,12 @@ Readings taken here (the paper gives no formulas for them):
     round r >= 1, e = 10 sqrt(2/pi) max_j ||(I - Q Q^T) y_j|| with Q from the
     earlier rounds; a pair whose e <= tau freezes; at least 2 rounds
   * range basis Q0: Householder QR of the samples, SVD of R, keep the
-    singular values above 1e-13 sigma_1
+    singular values above 1e-13 sigma_1; each column gets a canonical sign
+    (its largest-magnitude entry positive, first index on ties).  One
+    projection matrix carries the bases of every pair of a level, and after
+    the coarser levels are removed a residual of size tau still couples
+    neighbouring pairs, so without a canonical sign the result would depend
+    on the sign convention of the QR/SVD routine used
   * projection Y' = A [0; Q0] (minus peeled levels), B0 = Y'[t1];
     SVD(B0) = W S V^T truncated at tau gives A[t2,t1] ~ (Q0 V) (W S)^T
   * leaf diagonal blocks from stacked identities, symmetrised
@@ -47,7 +52,16 @@ def range_basis(Z):
     if s[0] == 0.0:
         return np.zeros((Z.shape[0], 0))
     k = int(np.sum(s > RANK_CUT * s[0]))
-    return Q @ Ur[:, :k]
+    return canonical_signs(Q @ Ur[:, :k])
+
+
+def canonical_signs(Q):
+    """Flip columns so that each column's largest-magnitude entry is positive."""
+    if Q.shape[1] == 0:
+        return Q
+    idx = np.argmax(np.abs(Q), axis=0)
+    sgn = np.where(Q[idx, np.arange(Q.shape[1])] < 0, -1.0, 1.0)
+    return Q * sgn
 
 
 class PeelResult:

@@ -317,6 +317,27 @@ def test_recompression_idempotent():
     assert [list(r) for r in H2.rank] == [list(r) for r in H.rank]
 
 
+def test_range_basis_sign_convention_does_not_matter():
+    # the shared projection of all pairs of a level must not depend on the
+    # sign convention of the orthogonalisation: flipping the signs of the
+    # range-basis columns before the canonical-sign step changes nothing
+    cfg = si.config_diffusion2d(16)
+    cfg["obs_index"] = np.array([2, 7, 12])
+    T = Tree(cfg["points"], 32, 0.7)
+    G = DiffusionGN(cfg)
+    A = tree_order(G.apply, T.perm)
+    nu, _ = power_norm(A, T.n, 2)
+    H1, _ = build(A, T, 1e-4, nu, 16, 10, adaptive=True, seed=2)
+    orig = peel_mod.canonical_signs
+    g = np.random.default_rng(0)
+    peel_mod.canonical_signs = lambda Q: orig(Q * g.choice([-1.0, 1.0], size=Q.shape[1]))
+    try:
+        H2_, _ = build(A, T, 1e-4, nu, 16, 10, adaptive=True, seed=2)
+    finally:
+        peel_mod.canonical_signs = orig
+    assert np.linalg.norm(H1.dense_tree() - H2_.dense_tree(), 2) <= 1e-12 * nu
+
+
 # ----------------------------------------------------------------- Newton-Schulz
 @pytest.fixture(scope="module")
 def kernel_small():
