@@ -1,0 +1,178 @@
+"""Benchmark: H2 Hessian build + Newton-Schulz inverse at 1e-4, and HGEMV GB/s.
+
+One step = the whole hot path on one batch of synthetic input: randomized
+peeling of the Hessian from Hessian-vector products (norm estimate, sampling
+rounds, range bases, projections, leaf diagonal), recompression into the
+strong H2, then hierarchical Newton-Schulz from X0 = I/||A|| until
+||I - A X||_2 <= 1e-4 (every iterate rebuilt by peeling from HGEMV samples).
+
+Default workload: the 2D time-dependent diffusion Gauss-Newton Hessian on a
+64 x 64 interior grid (N = 4096, leaf 64, rank cap 24, adaptive sampling,
+eps = 1e-4), plain FP64 GPU path.  Prints ONE JSON line (rank 0).
+"""
+import argparse
+import json
+import os
+import subprocess
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0           # MI355X HBM3E, GB/s
+FP64_PEAK_TFLOPS = 78.6         # MI355X FP64 vector / matrix, TFLOP/s
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--grid", type=int, default=64)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--hgemv-nv", type=int, default=34)
+    ap.add_argument("--hgemv-reps", type=int, default=50)
+    return ap.parse_args()
+
+
+def hip_events_time(fn, reps, stream):
+    """Average duration (ms) of fn() over reps launches, HIP events on `stream`."""
+    import torch
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    start.record(stream)
+    for _ in range(reps):
+        fn()
+    stop.record(stream)
+    stop.synchronize()
+    return start.elapsed_time(stop) / reps
+
+
+def cpu_baseline(cfg, gpu_iters):
+    """Oracle timed on a bounded sample: the full FP64 build of the Hessian plus
+    one Newton-Schulz iteration, extrapolated to the GPU's iteration count."""
+    import numpy as np
+    from oracle.hessians import DiffusionGN, tree_order
+    from oracle.h2 import H2Matrix
+    from oracle.ns import build as obuild, power_norm, residual_norm
+    from oracle.tree import Tree as OTree
+
+    T = OTree(cfg["points"], cfg["leaf"], cfg["eta"])
+    G = DiffusionGN(cfg)
+    A = tree_order(G.apply, T.perm)
+    t0 = time.perf_counter()
+    nu, _ = power_norm(A, T.n, cfg["seed"])
+    H, pr = obuild(A, T, cfg["tol"], nu, cfg["cap"], cfg["p"], adaptive=True, seed=cfg["seed"])
+    t_build = time.perf_counter() - t0
+    # one Newton-Schulz iteration: residual + rebuild of X1 from X0 = I / ||A||
+    t0 = time.perf_counter()
+    nuA, _ = power_norm(H.matvec_tree, T.n, 2)
+    X = H2Matrix.scaled_identity(T, 1.0 / nuA)
+    residual_norm(H, X, 2, 0)
+
+    def sampler(Om):
+        W = X.matvec_tree(Om)
+        return 2.0 * W - X.matvec_tree(H.matvec_tree(W))
+    obuild(sampler, T, 1e-2, 1.0 / nuA, T.leaf_size, cfg["p"], adaptive=True, seed=2,
+           iteration=1)
+    t_it = time.perf_counter() - t0
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    try:
+        import numpy.__config__  # noqa: F401
+    except Exception:  # noqa: BLE001
+        pass
+    est = t_build + t_it * gpu_iters
+    return {"value": est, "unit": "s", "cores": threads, "kind": "oracle",
+            "sample": "full FP64 oracle build of the diffusion2d Hessian (%.1f s) + one "
+                      "Newton-Schulz iteration at the loosest dynamic threshold (%.1f s), "
+                      "extrapolated to %d iterations" % (t_build, t_it, gpu_iters)}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(problems would shard by independent Hessians or subtrees); use --gpus 1",
+              file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import paper_2003_10173_amd as h2
+    import seeded_inputs as si
+
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    cfg = si.config_diffusion2d(args.grid)
+    tree = h2.Tree(cfg["points"], cfg["leaf"], cfg["eta"])
+    sampler = h2.DiffusionSampler(cfg)
+    bopts = h2.opts(rank_cap=cfg["cap"], oversample=cfg["p"], tol=cfg["tol"], adaptive=1,
+                    max_rounds=16, seed=cfg["seed"])
+    nopts = h2.ns_opts(eps=1e-4, max_iter=60, x0=0, dynamic=1, rank_cap=0,
+                       oversample=cfg["p"], adaptive=1, max_rounds=16, seed=cfg["seed"])
+
+    def step():
+        A, bst = h2.build(tree, sampler, bopts)
+        X, nst = h2.newton_schulz(A, nopts)
+        return A, bst, X, nst
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        A, bst, X, nst = step()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ms_per_step = 1e3 * elapsed / args.steps
+
+    # ---- dominant kernel: HGEMV of the built Hessian (the NS sampler is all HGEMVs)
+    nv = args.hgemv_nv
+    n = tree.n
+    x = torch.randn(nv, n, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    words, mbytes = A.words()
+    ms = hip_events_time(lambda: A.gemv(x, y), args.hgemv_reps, stream)
+    alg_bytes = mbytes + 2 * 8 * n * nv
+    gbs = alg_bytes / (ms * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "achieved": round(gbs, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(gbs / HBM_PEAK_GBS, 5), "traffic": None,
+                "kernel": "hgemv (all stages, FP64, nv=%d)" % nv,
+                "alg_bytes_per_call": int(alg_bytes), "ms_per_call": round(ms, 5)}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(cfg, nst["iterations"])
+
+    out = {
+        "metric": "build+inverse s at 1e-4 rel err (mixed/batched/learned vs plain FP64); HGEMV GB/s",
+        "value": round(ms_per_step / 1e3, 4),
+        "unit": "s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 2),
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "diffusion2d Gauss-Newton Hessian, %dx%d grid, N=%d, leaf %d, "
+                               "rank cap %d, eps 1e-4, build + Newton-Schulz (FP64)"
+                               % (args.grid, args.grid, n, cfg["leaf"], cfg["cap"]),
+                   "form": "plain FP64 GPU"},
+        "ns_iterations": nst["iterations"],
+        "ns_residual": nst["resid"][-1],
+        "build_applies": bst["applies"],
+        "build_ms": round(bst["time_ms"][7], 2),
+        "ns_ms": round(nst["time_ms"][3], 2),
+        "hgemv_gbs": round(gbs, 2),
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -112,7 +112,8 @@ typedef struct {
   int range_cols[H2_MAX_LEVELS];   /* max range-basis width k0 at level l */
   int rounds[H2_MAX_LEVELS];       /* sampling rounds at level l */
   int strong_rank[H2_MAX_LEVELS];  /* max cluster-basis rank at level l (destination) */
-  int64_t applies;                 /* sampler columns requested (norm + samples) */
+  int64_t applies;                 /* sampler columns of the peeling (samples, projections, diagonal) */
+  int64_t norm_applies;            /* sampler columns of the norm estimate */
   double norm;                     /* ||A||_2 used for the thresholds */
   int converged;                   /* 1 if every level met the estimator */
   int cap_hit;                     /* 1 if the rank cap truncated a basis */

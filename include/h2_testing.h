@@ -1,0 +1,34 @@
+/*
+ * h2_testing.h -- test hooks of the MI355X H2 library (not for production use).
+ *
+ * They expose the batched dense primitives of the construction and the weak
+ * (sibling-block) factors of the most recent h2_build on this thread, so tests
+ * can compare each stage with an independent CPU computation.  All arrays are
+ * host, column-major, FP64; the hooks allocate, copy, run on the null stream
+ * and synchronise.  Return value: h2_status.
+ */
+#ifndef H2_MI355X_TESTING_H
+#define H2_MI355X_TESTING_H
+
+#include "h2.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* C = alpha op(A) op(B) + beta C (op = transpose when t* != 0); C in/out */
+h2_status h2_test_gemm(int ta, int tb, int M, int N, int K, double alpha, const double* A, int lda,
+                       const double* B, int ldb, double beta, double* C, int ldc);
+/* Householder QR of A (m x n): Q (m x min(m,n)), R (min(m,n) x n); either may be NULL */
+h2_status h2_test_qr(int m, int n, const double* A, double* Q, double* R);
+/* one-sided Jacobi SVD of A (m x n, m >= n): sigma (n), U (m x n), V (n x n) */
+h2_status h2_test_svd(int m, int n, const double* A, double* sigma, double* U, double* V);
+/* keep the weak factors of subsequent h2_build calls on this thread (1) or not (0) */
+void h2_test_keep_factors(int on);
+/* factors of level l of the last kept build: ranks (2^(l-1)) and F (n x K, K = max rank) */
+h2_status h2_test_factors(int level, int32_t* ranks_out, int* K_out, double* F_out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

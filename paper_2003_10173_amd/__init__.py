@@ -48,7 +48,10 @@ class Tree:
     def __del__(self):
         h = getattr(self, "handle", None)
         if h is not None and h.value:
-            lib().h2_tree_destroy(h)
+            try:
+                lib().h2_tree_destroy(h)
+            except Exception:  # noqa: BLE001 - interpreter shutdown
+                pass
             self.handle = None
 
     @property
@@ -85,7 +88,10 @@ class H2Matrix:
     def __del__(self):
         h = getattr(self, "handle", None)
         if h is not None and h.value:
-            lib().h2_destroy(h)
+            try:
+                lib().h2_destroy(h)
+            except Exception:  # noqa: BLE001 - interpreter shutdown
+                pass
             self.handle = None
 
     # -- construction from host arrays (packed layout of include/h2.h)
@@ -193,7 +199,10 @@ class _NativeSampler(_SamplerBase):
 
     def __del__(self):
         if getattr(self, "ctx", None) is not None and self.ctx.value:
-            lib().h2_sampler_destroy(self.ctx)
+            try:
+                lib().h2_sampler_destroy(self.ctx)
+            except Exception:  # noqa: BLE001 - interpreter shutdown
+                pass
             self.ctx = None
 
 
@@ -322,6 +331,7 @@ def stats_dict(st, levels):
                 range_cols=list(st.range_cols[1:levels + 1]),
                 rounds=list(st.rounds[1:levels + 1]),
                 strong_rank=list(st.strong_rank[:levels + 1]), applies=st.applies,
+                norm_applies=st.norm_applies,
                 norm=st.norm, converged=bool(st.converged), cap_hit=bool(st.cap_hit),
                 time_ms=list(st.time_ms))
 

@@ -31,7 +31,8 @@ class H2Opts(C.Structure):
 class H2BuildStats(C.Structure):
     _fields_ = [("levels", C.c_int), ("weak_rank", C.c_int * H2_MAX_LEVELS),
                 ("range_cols", C.c_int * H2_MAX_LEVELS), ("rounds", C.c_int * H2_MAX_LEVELS),
-                ("strong_rank", C.c_int * H2_MAX_LEVELS), ("applies", i64), ("norm", dbl),
+                ("strong_rank", C.c_int * H2_MAX_LEVELS), ("applies", i64),
+                ("norm_applies", i64), ("norm", dbl),
                 ("converged", C.c_int), ("cap_hit", C.c_int), ("time_ms", dbl * 8)]
 
 
@@ -86,6 +87,13 @@ SIGNATURES = {
     "h2_sampler_advdiff_apply": (C.c_int, [vp, C.c_int, C.c_int, vp, C.c_int, vp, C.c_int, vp]),
     "h2_sampler_h2_apply": (C.c_int, [vp, C.c_int, C.c_int, vp, C.c_int, vp, C.c_int, vp]),
     "h2_sampler_destroy": (None, [vp]),
+    # test hooks (include/h2_testing.h)
+    "h2_test_gemm": (C.c_int, [C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, dbl, vp, C.c_int, vp,
+                               C.c_int, dbl, vp, C.c_int]),
+    "h2_test_qr": (C.c_int, [C.c_int, C.c_int, vp, vp, vp]),
+    "h2_test_svd": (C.c_int, [C.c_int, C.c_int, vp, vp, vp, vp]),
+    "h2_test_keep_factors": (None, [C.c_int]),
+    "h2_test_factors": (C.c_int, [C.c_int, vp, vp, vp]),
 }
 
 

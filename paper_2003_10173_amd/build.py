@@ -26,6 +26,7 @@ SOURCES = [
     "ns.hip",
     "samplers.hip",
     "mlp.hip",
+    "testing.hip",
 ]
 
 # host geometry code is compiled without contraction so that admissibility

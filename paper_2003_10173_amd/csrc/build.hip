@@ -15,7 +15,10 @@
 // blocks D of the strong partition of the tree.
 //
 // Thresholds: tau = eps * nu / (4 L) for the sampled blocks and the bases;
-// numerical-rank cut 1e-13 sigma_1 for the range basis.
+// numerical-rank cut 1e-13 sigma_1 for the range basis, whose columns take a
+// canonical sign (largest-magnitude entry positive) because one projection
+// matrix carries the bases of all pairs of a level and a tau-sized residual of
+// the coarser levels couples neighbouring pairs.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -28,6 +31,9 @@
 #include "vecops.h"
 
 namespace h2 {
+
+void keep_factors(int l, const std::vector<int>& k, int K, const double* F_dev, int n);
+void reset_factors();
 
 static double now_ms() {
   using namespace std::chrono;
@@ -208,7 +214,8 @@ std::unique_ptr<h2_matrix> build_h2(const h2_tree* t, Sampler& S, const BuildPar
   const int b = prm.rank_cap + prm.oversample;
   H2_CHECK(b >= 1 && prm.rank_cap >= 1, H2_EINVAL, "rank_cap + oversample must be >= 1");
   H2_CHECK(!prm.adaptive || prm.max_rounds >= 2, H2_EINVAL, "adaptive mode needs max_rounds >= 2");
-  H2_CHECK(prm.max_rounds * b <= 1024, H2_EINVAL, "max_rounds * (rank_cap + oversample) > 1024");
+  H2_CHECK((prm.adaptive ? prm.max_rounds * b : b) <= 1024, H2_EINVAL,
+           "more than 1024 sample columns per level (max_rounds * (rank_cap + oversample))");
   h2_build_stats local{};
   h2_build_stats& stats = st ? *st : local;
   stats = h2_build_stats{};
@@ -227,12 +234,15 @@ std::unique_ptr<h2_matrix> build_h2(const h2_tree* t, Sampler& S, const BuildPar
   }
   H2_CHECK(std::isfinite(nu), H2_ENUMERIC, "norm estimate is not finite");
   stats.norm = nu;
+  stats.norm_applies = S.applies - applies0;
+  const int64_t applies1 = S.applies;
   stats.time_ms[0] = now_ms() - t0;
   const double tau = prm.tol * nu / (4.0 * std::max(L, 1));
   const double kHMT = 10.0 * std::sqrt(2.0 / M_PI);
 
   std::vector<Level> lv(L + 1);
   DevBuf om_buf, y_buf;
+  reset_factors();
   for (int l = 1; l <= L; ++l) {
     const int np = 1 << (l - 1);
     std::vector<Pair> pr(np);
@@ -369,6 +379,12 @@ std::unique_ptr<h2_matrix> build_h2(const h2_tree* t, Sampler& S, const BuildPar
         if (k > 0) g.push_back({Qp[p], Vp[p], Q0[p], pr[p].m2, k, kq[p], pr[p].m2, kq[p], pr[p].m2, 0, 0, 1.0, 0.0});
       }
       gemm_batched(c, g);
+      // canonical column signs: the projection below carries every pair's
+      // basis in the same columns, so the result must not depend on signs
+      std::vector<CopyDesc> cs;
+      for (int p = 0; p < np; ++p)
+        if (k0[p] > 0) cs.push_back({Q0[p], pr[p].m2, nullptr, 0, pr[p].m2, k0[p], 1.0, 0.0, 0});
+      canonical_signs(c, cs);
     }
     stats.range_cols[l] = K0;
     zbuf.release();
@@ -454,6 +470,7 @@ std::unique_ptr<h2_matrix> build_h2(const h2_tree* t, Sampler& S, const BuildPar
     }
     stats.weak_rank[l] = LV.K;
     H2_HIP(hipStreamSynchronize(c.s));
+    keep_factors(l, LV.k, LV.K, LV.F.as<double>(), n);
     c.scratch.clear();
     c.stage.reset();
     stats.time_ms[3] += now_ms() - t0;
@@ -746,7 +763,7 @@ std::unique_ptr<h2_matrix> build_h2(const h2_tree* t, Sampler& S, const BuildPar
     for (int i = 0; i < (1 << lev); ++i) mx = std::max(mx, (int)rank[cid(lev, i)]);
     stats.strong_rank[lev] = mx;
   }
-  stats.applies = S.applies - applies0;
+  stats.applies = S.applies - applies1;
   stats.converged = converged;
   stats.time_ms[7] = now_ms() - t_start;
   if (converged_out) *converged_out = converged;

@@ -92,6 +92,9 @@ struct ScaleDesc {
 };
 
 void gemm_batched(Ctx& c, const std::vector<GemmDesc>& d);
+// flip each column of X (rows x cols, ld) so that its largest-magnitude entry
+// is positive (first index on ties); uses CopyDesc src/lds/rows/cols
+void canonical_signs(Ctx& c, const std::vector<CopyDesc>& blocks);
 void scale_columns(Ctx& c, const std::vector<ScaleDesc>& d);
 void qr_batched(Ctx& c, const std::vector<QRDesc>& d);
 void svd_batched(Ctx& c, const std::vector<SVDDesc>& d);

@@ -517,6 +517,42 @@ void scale_columns(Ctx& c, const std::vector<ScaleDesc>& ds) {
   H2_LAUNCH_CHECK();
 }
 
+// one block per matrix, one wave per column: arg-max of |x| (first index on
+// ties), then the column is negated when that entry is negative
+__global__ __launch_bounds__(256) void k_canon_sign(const CopyDesc* __restrict__ ds) {
+  const CopyDesc d = ds[blockIdx.x];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  double* X = const_cast<double*>(d.src);
+  for (int j = wave; j < d.cols; j += 4) {
+    double* col = X + (size_t)j * d.lds;
+    double best = -1.0;
+    int bi = 0x7fffffff;
+    for (int i = lane; i < d.rows; i += 64) {
+      const double a = fabs(col[i]);
+      if (a > best) { best = a; bi = i; }   // ascending i: keeps the first maximum
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      const double ob = __shfl_xor(best, off, 64);
+      const int oi = __shfl_xor(bi, off, 64);
+      if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+    }
+    const bool flip = bi < d.rows && col[bi] < 0.0;
+    if (flip)
+      for (int i = lane; i < d.rows; i += 64) col[i] = -col[i];
+  }
+}
+
+void canonical_signs(Ctx& c, const std::vector<CopyDesc>& blocks) {
+  std::vector<CopyDesc> v;
+  for (auto& b : blocks)
+    if (b.rows > 0 && b.cols > 0) v.push_back(b);
+  if (v.empty()) return;
+  auto* dd = (CopyDesc*)c.stage.put(v.data(), v.size() * sizeof(CopyDesc), c.s);
+  k_canon_sign<<<(unsigned)v.size(), 256, 0, c.s>>>(dd);
+  H2_LAUNCH_CHECK();
+}
+
 __global__ void k_zero(double* p, int rows, int cols, int ld) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= (int64_t)rows * cols) return;

@@ -1,0 +1,91 @@
+"""GPU checks of the batched dense primitives of the construction against
+LAPACK (numpy) through the test hooks of include/h2_testing.h."""
+import ctypes as C
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+h2 = pytest.importorskip("paper_2003_10173_amd")
+L = h2.lib
+
+
+def F(a):
+    return np.asfortranarray(a, dtype=np.float64)
+
+
+def gemm(ta, tb, A, B, Cm, alpha=1.0, beta=0.0):
+    A, B, Cm = F(A), F(B), F(Cm.copy())
+    M, N = Cm.shape
+    K = A.shape[0] if ta else A.shape[1]
+    h2.check(L().h2_test_gemm(ta, tb, M, N, K, alpha, A.ctypes.data, A.shape[0], B.ctypes.data,
+                              B.shape[0], beta, Cm.ctypes.data, M), "gemm")
+    return Cm
+
+
+@pytest.mark.parametrize("M,N,K", [(5, 7, 3), (64, 64, 64), (130, 33, 70), (20, 30, 5000),
+                                   (100, 1, 4099), (1, 1, 1)])
+@pytest.mark.parametrize("ta,tb", [(0, 0), (1, 0), (0, 1), (1, 1)])
+def test_gemm_matches_numpy(M, N, K, ta, tb):
+    g = np.random.default_rng(M * 7 + N + K)
+    A = g.standard_normal((K, M) if ta else (M, K))
+    B = g.standard_normal((N, K) if tb else (K, N))
+    C0 = g.standard_normal((M, N))
+    got = gemm(ta, tb, A, B, C0, alpha=0.5, beta=-2.0)
+    want = 0.5 * (A.T if ta else A) @ (B.T if tb else B) - 2.0 * C0
+    assert np.abs(got - want).max() <= 1e-12 * max(1.0, np.abs(want).max()) * np.sqrt(K)
+
+
+def qr(A):
+    A = F(A)
+    m, n = A.shape
+    k = min(m, n)
+    Q = np.zeros((m, k), order="F")
+    R = np.zeros((k, n), order="F")
+    h2.check(L().h2_test_qr(m, n, A.ctypes.data, Q.ctypes.data, R.ctypes.data), "qr")
+    return Q, R
+
+
+@pytest.mark.parametrize("m,n,rank", [(50, 20, 20), (64, 102, 64), (300, 40, 7), (3000, 60, 60),
+                                      (9000, 30, 30), (10, 10, 0), (33, 1, 1)])
+def test_qr_backward_stable_and_matches_lapack(m, n, rank):
+    g = np.random.default_rng(m + n)
+    A = g.standard_normal((m, rank)) @ g.standard_normal((rank, n)) if rank else np.zeros((m, n))
+    Q, R = qr(A)
+    k = min(m, n)
+    assert np.abs(Q.T @ Q - np.eye(k)).max() <= 1e-13 * max(1, m / 100)
+    assert np.abs(Q @ R - A).max() <= 1e-13 * max(1.0, np.abs(A).max()) * np.sqrt(m)
+    assert np.allclose(np.triu(R), R)
+    Rl = np.linalg.qr(A, mode="r")
+    # same Householder sign convention as LAPACK: R agrees up to rounding
+    if rank == min(m, n):
+        assert np.abs(np.abs(R) - np.abs(Rl)).max() <= 1e-11 * max(1.0, np.abs(Rl).max())
+
+
+def svd(A):
+    A = F(A)
+    m, n = A.shape
+    s = np.zeros(n)
+    U = np.zeros((m, n), order="F")
+    V = np.zeros((n, n), order="F")
+    h2.check(L().h2_test_svd(m, n, A.ctypes.data, s.ctypes.data, U.ctypes.data, V.ctypes.data), "svd")
+    return s, U, V
+
+
+@pytest.mark.parametrize("m,n,decay", [(40, 40, 0.0), (102, 64, 0.3), (200, 64, 0.6),
+                                       (256, 256, 0.1), (70, 70, 1.0)])
+def test_jacobi_svd_matches_lapack(m, n, decay):
+    g = np.random.default_rng(m * n)
+    U0 = np.linalg.qr(g.standard_normal((m, n)))[0]
+    V0 = np.linalg.qr(g.standard_normal((n, n)))[0]
+    sv = np.exp(-decay * np.arange(n))
+    A = U0 @ np.diag(sv) @ V0.T
+    s, U, V = svd(A)
+    sl = np.linalg.svd(A, compute_uv=False)
+    assert np.abs(s - sl).max() <= 1e-14 * sl[0] * n
+    assert np.all(np.diff(s) <= 0)
+    keep = s > 1e-10 * s[0]
+    assert np.abs(U[:, keep].T @ U[:, keep] - np.eye(keep.sum())).max() <= 1e-12
+    assert np.abs(V.T @ V - np.eye(n)).max() <= 1e-12
+    assert np.abs(U[:, keep] * s[keep] @ V[:, keep].T - A).max() <= 1e-12 * sl[0] * n
