@@ -117,12 +117,17 @@ def main():
         X, nst = h2.newton_schulz(A, nopts)
         return A, bst, X, nst
 
-    for _ in range(args.warmup):
-        step()
+    for i in range(args.warmup):
+        _, b0, _, n0 = step()
+        print("warmup step %d: build %.1f ms, NS %d iterations %.1f ms" % (
+            i, b0["time_ms"][7], n0["iterations"], n0["time_ms"][3]), file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for i in range(args.steps):
         A, bst, X, nst = step()
+        print("step %d: build %.1f ms, NS %d iterations %.1f ms, residual %.2e" % (
+            i, bst["time_ms"][7], nst["iterations"], nst["time_ms"][3], nst["resid"][-1]),
+            file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     ms_per_step = 1e3 * elapsed / args.steps

@@ -22,6 +22,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
 #include <functional>
 #include <map>
 #include <tuple>
@@ -214,8 +215,11 @@ std::unique_ptr<h2_matrix> build_h2(const h2_tree* t, Sampler& S, const BuildPar
   const int b = prm.rank_cap + prm.oversample;
   H2_CHECK(b >= 1 && prm.rank_cap >= 1, H2_EINVAL, "rank_cap + oversample must be >= 1");
   H2_CHECK(!prm.adaptive || prm.max_rounds >= 2, H2_EINVAL, "adaptive mode needs max_rounds >= 2");
-  H2_CHECK((prm.adaptive ? prm.max_rounds * b : b) <= 1024, H2_EINVAL,
-           "more than 1024 sample columns per level (max_rounds * (rank_cap + oversample))");
+  H2_CHECK(b <= (prm.adaptive ? 512 : 1024), H2_EINVAL,
+           "rank_cap + oversample must be <= 512 (adaptive) or 1024 (one round)");
+  // the per-pair sample store holds at most 1024 columns (QR / SVD limit):
+  // the round budget is clamped to what fits
+  const int max_rounds = std::max(2, std::min(prm.max_rounds, 1024 / b));
   h2_build_stats local{};
   h2_build_stats& stats = st ? *st : local;
   stats = h2_build_stats{};
@@ -249,13 +253,20 @@ std::unique_ptr<h2_matrix> build_h2(const h2_tree* t, Sampler& S, const BuildPar
     for (int p = 0; p < np; ++p)
       pr[p] = {t->cstart[cid(l, 2 * p)], t->csize[cid(l, 2 * p)], t->cstart[cid(l, 2 * p + 1)],
                t->csize[cid(l, 2 * p + 1)]};
-    const int cmax = prm.adaptive ? prm.max_rounds * b : b;
-    // per-pair sample storage Z_p (m2 x cmax, ld m2)
-    std::vector<int64_t> zoff(np + 1, 0);
-    for (int p = 0; p < np; ++p) zoff[p + 1] = zoff[p] + (int64_t)pr[p].m2 * cmax;
+    const int cmax = prm.adaptive ? max_rounds * b : b;
+    // per-pair sample storage Z_p (m2 x cmax, ld m2) and an orthonormal basis
+    // Qe_p of the samples kept so far (block Gram-Schmidt with two projections
+    // per round), used by the estimator and by the final range basis
+    std::vector<int64_t> zoff(np + 1, 0), qoff(np + 1, 0);
+    for (int p = 0; p < np; ++p) {
+      zoff[p + 1] = zoff[p] + (int64_t)pr[p].m2 * cmax;
+      qoff[p + 1] = qoff[p] + (int64_t)pr[p].m2 * std::min(pr[p].m2, cmax);
+    }
     DevBuf zbuf(std::max<int64_t>(zoff[np], 1) * sizeof(double));
+    DevBuf qbuf(std::max<int64_t>(qoff[np], 1) * sizeof(double));
     double* Z = zbuf.as<double>();
-    std::vector<int> cols(np, 0);
+    double* Qe = qbuf.as<double>();
+    std::vector<int> cols(np, 0), qc(np, 0);
     std::vector<char> frozen(np, 0);
     om_buf.reserve((size_t)n * b * sizeof(double));
     y_buf.reserve((size_t)n * b * sizeof(double));
@@ -272,52 +283,84 @@ std::unique_ptr<h2_matrix> build_h2(const h2_tree* t, Sampler& S, const BuildPar
       H2_LAUNCH_CHECK();
       S.apply(c, b, om, y);
       subtract_levels(c, t, lv, l, om, y, b);
+      if (r == 0) check_finite(c, y, (int64_t)n * b, "samples");
       std::vector<int> newly(np, 0);
-      if (prm.adaptive && r >= 1) {
-        // HMT estimate with the orthonormal basis of the earlier rounds
-        std::vector<QRDesc> qrs;
-        std::vector<GemmDesc> g1, g2;
-        std::vector<CopyDesc> res_blocks, pre;
-        std::vector<int> idx;
-        for (int p = 0; p < np; ++p) {
-          if (frozen[p]) continue;
-          const int m2 = pr[p].m2, cp = cols[p], kq = std::min(m2, cp);
-          double* Zc = c.scratch.get((size_t)m2 * cp);
-          double* Q = c.scratch.get((size_t)m2 * kq);
-          double* W = c.scratch.get((size_t)kq * b);
-          double* R = c.scratch.get((size_t)m2 * b);
-          // QR destroys its input: work on a copy of the samples
-          pre.push_back({Z + zoff[p], m2, Zc, m2, m2, cp, 1.0, 0.0, 0});
-          qrs.push_back({Zc, m2, m2, cp, Q, m2, nullptr, 0});
-          g1.push_back({Q, y + pr[p].a2, W, kq, b, m2, m2, n, kq, 1, 0, 1.0, 0.0});
-          // residual = Y[t2] - Q W
-          res_blocks.push_back({R, m2, nullptr, 0, m2, b, 1.0, 0.0, 0});
-          g2.push_back({Q, W, R, m2, b, kq, m2, kq, m2, 0, 0, -1.0, 1.0});
-          pre.push_back({y + pr[p].a2, n, R, m2, m2, b, 1.0, 0.0, 0});
-          idx.push_back(p);
+      std::vector<int> act;                    // pairs that take this round's samples
+      for (int p = 0; p < np; ++p)
+        if (!frozen[p]) act.push_back(p);
+      // projected samples Yp'' = (I - Qe Qe^T)^2 Y[t2] (round 0: the samples)
+      std::vector<double*> Yproj(np, nullptr);
+      {
+        std::vector<CopyDesc> cp;
+        std::vector<GemmDesc> g1, g2, g3, g4;
+        for (int p : act) {
+          const int m2 = pr[p].m2;
+          Yproj[p] = c.scratch.get((size_t)m2 * b);
+          cp.push_back({y + pr[p].a2, n, Yproj[p], m2, m2, b, 1.0, 0.0, 0});
+          const int q = qc[p];
+          if (q == 0) continue;
+          double* W1 = c.scratch.get((size_t)q * b);
+          double* W2 = c.scratch.get((size_t)q * b);
+          double* Qp_ = Qe + qoff[p];
+          g1.push_back({Qp_, Yproj[p], W1, q, b, m2, m2, m2, q, 1, 0, 1.0, 0.0});
+          g2.push_back({Qp_, W1, Yproj[p], m2, b, q, m2, q, m2, 0, 0, -1.0, 1.0});
+          g3.push_back({Qp_, Yproj[p], W2, q, b, m2, m2, m2, q, 1, 0, 1.0, 0.0});
+          g4.push_back({Qp_, W2, Yproj[p], m2, b, q, m2, q, m2, 0, 0, -1.0, 1.0});
         }
-        copy_batched(c, pre);
-        qr_batched(c, qrs);
+        copy_batched(c, cp);
         gemm_batched(c, g1);
         gemm_batched(c, g2);
+        gemm_batched(c, g3);
+        gemm_batched(c, g4);
+      }
+      if (prm.adaptive && r >= 1) {
+        std::vector<CopyDesc> res_blocks;
+        for (int p : act) res_blocks.push_back({Yproj[p], pr[p].m2, nullptr, 0, pr[p].m2, b, 1.0, 0.0, 0});
         colnorm_max_batched(c, res_blocks, ebuf.as<double>());
         auto e = to_host(ebuf.as<double>(), res_blocks.size(), c.s);
-        for (size_t q = 0; q < idx.size(); ++q) {
+        for (size_t q = 0; q < act.size(); ++q) {
           H2_CHECK(std::isfinite(e[q]), H2_ENUMERIC, "non-finite samples");
-          if (kHMT * e[q] <= tau) newly[idx[q]] = 1;
+          if (kHMT * e[q] <= tau) newly[act[q]] = 1;
         }
-      } else if (r == 0) {
-        check_finite(c, y, (int64_t)n * b, "samples");
       }
       // append this round's samples
       std::vector<CopyDesc> app;
-      for (int p = 0; p < np; ++p) {
-        if (frozen[p]) continue;
+      for (int p : act) {
         app.push_back({y + pr[p].a2, n, Z + zoff[p] + (size_t)cols[p] * pr[p].m2, pr[p].m2,
                        pr[p].m2, b, 1.0, 0.0, 0});
         cols[p] += b;
       }
       copy_batched(c, app);
+      // extend Qe with the projected block: QR, one more projection, QR again
+      {
+        std::vector<QRDesc> q1, q2;
+        std::vector<GemmDesc> g1, g2;
+        std::vector<CopyDesc> put;
+        for (int p : act) {
+          const int m2 = pr[p].m2, q = qc[p];
+          if (q >= m2) continue;
+          const int kn = std::min(m2, b);
+          const int take = std::min(kn, m2 - q);
+          double* Qn = c.scratch.get((size_t)m2 * kn);
+          double* Qn2 = c.scratch.get((size_t)m2 * kn);
+          q1.push_back({Yproj[p], m2, m2, b, Qn, m2, nullptr, 0});
+          if (q > 0) {
+            double* Wq = c.scratch.get((size_t)q * kn);
+            g1.push_back({Qe + qoff[p], Qn, Wq, q, kn, m2, m2, m2, q, 1, 0, 1.0, 0.0});
+            g2.push_back({Qe + qoff[p], Wq, Qn, m2, kn, q, m2, q, m2, 0, 0, -1.0, 1.0});
+            q2.push_back({Qn, m2, m2, kn, Qn2, m2, nullptr, 0});
+            put.push_back({Qn2, m2, Qe + qoff[p] + (size_t)q * m2, m2, m2, take, 1.0, 0.0, 0});
+          } else {
+            put.push_back({Qn, m2, Qe + qoff[p], m2, m2, take, 1.0, 0.0, 0});
+          }
+          qc[p] = q + take;
+        }
+        qr_batched(c, q1);
+        gemm_batched(c, g1);
+        gemm_batched(c, g2);
+        qr_batched(c, q2);
+        copy_batched(c, put);
+      }
       for (int p = 0; p < np; ++p)
         if (newly[p]) frozen[p] = 1;
       ++r;
@@ -328,37 +371,34 @@ std::unique_ptr<h2_matrix> build_h2(const h2_tree* t, Sampler& S, const BuildPar
       bool all = true;
       for (int p = 0; p < np; ++p) all = all && frozen[p];
       if (r >= 2 && all) break;
-      if (r >= prm.max_rounds) { converged = false; break; }
+      if (r >= max_rounds) { converged = false; break; }
     }
     stats.rounds[l] = r;
     stats.time_ms[1] += now_ms() - t0;
 
-    // ---- range basis: Householder QR of the samples + SVD of R, cut 1e-13
+    // ---- range basis: Z = Qe (Qe^T Z); SVD of Qe^T Z, singular values above
+    // 1e-13 sigma_1 (the left singular vectors of the samples)
     t0 = now_ms();
     std::vector<int> kq(np), k0(np, 0);
-    std::vector<double*> Qp(np), Vp(np), sig(np);
+    std::vector<double*> Vp(np), sig(np);
     std::vector<int64_t> soff(np + 1, 0);
-    for (int p = 0; p < np; ++p) soff[p + 1] = soff[p] + std::min(pr[p].m2, cols[p]);
+    for (int p = 0; p < np; ++p) soff[p + 1] = soff[p] + qc[p];
     double* sig_all = c.scratch.get(std::max<int64_t>(soff[np], 1));
     {
-      std::vector<QRDesc> qrs;
-      std::vector<CopyDesc> tr;
+      std::vector<GemmDesc> g;
       std::vector<SVDDesc> svs;
       for (int p = 0; p < np; ++p) {
         const int m2 = pr[p].m2, cp = cols[p];
-        kq[p] = std::min(m2, cp);
-        Qp[p] = c.scratch.get((size_t)m2 * kq[p]);
-        double* R = c.scratch.get((size_t)kq[p] * cp);
+        kq[p] = qc[p];
+        // Rt = Z^T Qe (cp x kq) = (Qe^T Z)^T
         double* Rt = c.scratch.get((size_t)cp * kq[p]);
         Vp[p] = c.scratch.get((size_t)kq[p] * kq[p]);
         sig[p] = sig_all + soff[p];
-        qrs.push_back({Z + zoff[p], m2, m2, cp, Qp[p], m2, R, kq[p]});
-        // left singular vectors of R = right singular vectors of R^T (cp x kq)
-        tr.push_back({R, kq[p], Rt, cp, cp, kq[p], 1.0, 0.0, 1});
+        g.push_back({Z + zoff[p], Qe + qoff[p], Rt, cp, kq[p], m2, m2, m2, cp, 1, 0, 1.0, 0.0});
+        // left singular vectors of R = right singular vectors of R^T
         svs.push_back({Rt, cp, cp, kq[p], sig[p], nullptr, 0, Vp[p], kq[p]});
       }
-      qr_batched(c, qrs);
-      copy_batched(c, tr);
+      gemm_batched(c, g);
       svd_batched(c, svs);
     }
     std::vector<double*> Q0(np);
@@ -376,7 +416,7 @@ std::unique_ptr<h2_matrix> build_h2(const h2_tree* t, Sampler& S, const BuildPar
         k0[p] = k;
         K0 = std::max(K0, k);
         Q0[p] = c.scratch.get((size_t)pr[p].m2 * std::max(k, 1));
-        if (k > 0) g.push_back({Qp[p], Vp[p], Q0[p], pr[p].m2, k, kq[p], pr[p].m2, kq[p], pr[p].m2, 0, 0, 1.0, 0.0});
+        if (k > 0) g.push_back({Qe + qoff[p], Vp[p], Q0[p], pr[p].m2, k, kq[p], pr[p].m2, kq[p], pr[p].m2, 0, 0, 1.0, 0.0});
       }
       gemm_batched(c, g);
       // canonical column signs: the projection below carries every pair's
@@ -387,7 +427,9 @@ std::unique_ptr<h2_matrix> build_h2(const h2_tree* t, Sampler& S, const BuildPar
       canonical_signs(c, cs);
     }
     stats.range_cols[l] = K0;
+    H2_HIP(hipStreamSynchronize(c.s));
     zbuf.release();
+    qbuf.release();
     stats.time_ms[2] += now_ms() - t0;
 
     // ---- projection B0 = (A [0; Q0])[t1] and truncation
@@ -406,35 +448,32 @@ std::unique_ptr<h2_matrix> build_h2(const h2_tree* t, Sampler& S, const BuildPar
       copy_batched(c, put);
       S.apply(c, K0, om, y);
       subtract_levels(c, t, lv, l, om, y, K0);
-      // B0 = Q_B R_B;  Jacobi on R_B^T:  R_B^T V' = U' S  =>  R_B = V' S U'^T
-      std::vector<QRDesc> qrs;
-      std::vector<CopyDesc> tr;
+      // truncated SVD of B0 (m1 x k0) by one-sided Jacobi on its tall side:
+      //   m1 >= k0:  B0 V = U S          ->  Q = Q0 V_k,  B = U_k S_k
+      //   m1 <  k0:  B0^T V = U S, B0 = V S U^T  ->  Q = Q0 U_k,  B = V_k S_k
+      std::vector<CopyDesc> b0c;
       std::vector<SVDDesc> svs;
       std::vector<int> kb(np, 0);
-      std::vector<double*> QB(np), Vb(np), Ub(np), sb(np);
-      std::vector<CopyDesc> b0c;
+      std::vector<double*> Ub(np), Vb(np), sb(np);
       std::vector<int64_t> boff(np + 1, 0);
       for (int p = 0; p < np; ++p) boff[p + 1] = boff[p] + std::min(pr[p].m1, k0[p]);
       double* sb_all = c.scratch.get(std::max<int64_t>(boff[np], 1));
       for (int p = 0; p < np; ++p) {
         if (k0[p] == 0) continue;
-        const int m1 = pr[p].m1;
-        kb[p] = std::min(m1, k0[p]);
-        double* B0 = c.scratch.get((size_t)m1 * k0[p]);
-        b0c.push_back({y + pr[p].a1, n, B0, m1, m1, k0[p], 1.0, 0.0, 0});
-        QB[p] = c.scratch.get((size_t)m1 * kb[p]);
-        double* RB = c.scratch.get((size_t)kb[p] * k0[p]);
-        double* RBt = c.scratch.get((size_t)k0[p] * kb[p]);
-        Vb[p] = c.scratch.get((size_t)kb[p] * kb[p]);
-        Ub[p] = c.scratch.get((size_t)k0[p] * kb[p]);
+        const int m1 = pr[p].m1, kk = k0[p];
+        kb[p] = std::min(m1, kk);
+        const bool tall = m1 >= kk;
+        const int mm = tall ? m1 : kk, nn = tall ? kk : m1;
+        double* X = c.scratch.get((size_t)mm * nn);
+        b0c.push_back({y + pr[p].a1, n, X, mm, mm, nn, 1.0, 0.0, tall ? 0 : 1});
+        Ub[p] = c.scratch.get((size_t)mm * nn);
+        Vb[p] = c.scratch.get((size_t)nn * nn);
         sb[p] = sb_all + boff[p];
-        qrs.push_back({B0, m1, m1, k0[p], QB[p], m1, RB, kb[p]});
-        tr.push_back({RB, kb[p], RBt, k0[p], k0[p], kb[p], 1.0, 0.0, 1});
-        svs.push_back({RBt, k0[p], k0[p], kb[p], sb[p], Ub[p], k0[p], Vb[p], kb[p]});
+        svs.push_back({X, mm, mm, nn, sb[p], Ub[p], mm, Vb[p], nn});
       }
+      // the transposed copies read B0 from y (n x K0, ld n): src of a
+      // transposed copy is (cols x rows) = (m1 x k0) at y + a1 with lds = n
       copy_batched(c, b0c);
-      qr_batched(c, qrs);
-      copy_batched(c, tr);
       svd_batched(c, svs);
       auto sbh = to_host(sb_all, boff[np], c.s);
       for (int p = 0; p < np; ++p) {
@@ -449,20 +488,25 @@ std::unique_ptr<h2_matrix> build_h2(const h2_tree* t, Sampler& S, const BuildPar
       LV.F.alloc((size_t)n * std::max(LV.K, 1) * sizeof(double));
       double* F = LV.F.as<double>();
       zero_block(c, F, n, std::max(LV.K, 1), n);
-      // Q = Q0 U'_k (t2 rows);  B = Q_B V'_k S_k (t1 rows)
       std::vector<GemmDesc> g;
-      std::vector<CopyDesc> scalecols;
+      std::vector<CopyDesc> cb;
+      std::vector<ScaleDesc> sc;
       for (int p = 0; p < np; ++p) {
         const int k = LV.k[p];
         if (k == 0) continue;
-        g.push_back({Q0[p], Ub[p], F + pr[p].a2, pr[p].m2, k, k0[p], pr[p].m2, k0[p], n, 0, 0, 1.0, 0.0});
-        g.push_back({QB[p], Vb[p], F + pr[p].a1, pr[p].m1, k, kb[p], pr[p].m1, kb[p], n, 0, 0, 1.0, 0.0});
+        const int m1 = pr[p].m1, m2 = pr[p].m2, kk = k0[p];
+        const bool tall = m1 >= kk;
+        // right singular vectors of B0 (k0 x kb) and left ones (m1 x kb)
+        const double* Rv = tall ? Vb[p] : Ub[p];
+        const int ldr = tall ? kb[p] : kk;
+        const double* Lv = tall ? Ub[p] : Vb[p];
+        const int ldl = tall ? m1 : kb[p];
+        g.push_back({Q0[p], Rv, F + pr[p].a2, m2, k, kk, m2, ldr, n, 0, 0, 1.0, 0.0});
+        cb.push_back({Lv, ldl, F + pr[p].a1, n, m1, k, 1.0, 0.0, 0});
+        sc.push_back({F + pr[p].a1, n, m1, k, sb[p]});
       }
       gemm_batched(c, g);
-      // scale the B columns by sigma
-      std::vector<ScaleDesc> sc;
-      for (int p = 0; p < np; ++p)
-        if (LV.k[p] > 0) sc.push_back({F + pr[p].a1, n, pr[p].m1, LV.k[p], sb[p]});
+      copy_batched(c, cb);
       scale_columns(c, sc);
     } else {
       LV.K = 0;
@@ -470,6 +514,9 @@ std::unique_ptr<h2_matrix> build_h2(const h2_tree* t, Sampler& S, const BuildPar
     }
     stats.weak_rank[l] = LV.K;
     H2_HIP(hipStreamSynchronize(c.s));
+    if (verbose())
+      std::fprintf(stderr, "  [h2_build] level %d: rounds %d, range cols %d, rank %d, %.1f ms so far\n",
+                   l, r, K0, LV.K, now_ms() - t_start);
     keep_factors(l, LV.k, LV.K, LV.F.as<double>(), n);
     c.scratch.clear();
     c.stage.reset();
@@ -766,6 +813,10 @@ std::unique_ptr<h2_matrix> build_h2(const h2_tree* t, Sampler& S, const BuildPar
   stats.applies = S.applies - applies1;
   stats.converged = converged;
   stats.time_ms[7] = now_ms() - t_start;
+  if (verbose())
+    std::fprintf(stderr, "  [h2_build] done: applies %lld, ms norm %.1f sample %.1f range %.1f proj %.1f diag %.1f recompress %.1f total %.1f\n",
+                 (long long)stats.applies, stats.time_ms[0], stats.time_ms[1], stats.time_ms[2],
+                 stats.time_ms[3], stats.time_ms[4], stats.time_ms[5], stats.time_ms[7]);
   if (converged_out) *converged_out = converged;
   return A;
 }

@@ -2,6 +2,7 @@
 // converts internal exceptions into an h2_status and records the message.
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <functional>
 #include <vector>
@@ -13,6 +14,13 @@ namespace h2 {
 
 static thread_local std::string g_last_error;
 void set_last_error(const std::string& msg) { g_last_error = msg; }
+bool verbose() {
+  static const bool v = [] {
+    const char* e = std::getenv("H2_VERBOSE");
+    return e && e[0] == '1';
+  }();
+  return v;
+}
 
 template <class F>
 static h2_status guarded(F&& f) {

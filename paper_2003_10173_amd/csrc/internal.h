@@ -22,6 +22,8 @@ struct Error : std::runtime_error {
 };
 
 void set_last_error(const std::string& msg);
+// progress trace to stderr when the environment sets H2_VERBOSE=1
+bool verbose();
 
 #define H2_HIP(call)                                                                     \
   do {                                                                                   \

@@ -10,6 +10,8 @@
 #include <cmath>
 #include <cstring>
 
+#include <hip/hip_cooperative_groups.h>
+
 #include "kernels_common.h"
 #include "linalg.h"
 
@@ -320,71 +322,138 @@ void qr_batched(Ctx& c, const std::vector<QRDesc>& ds) {
 }
 
 // ------------------------------------------------------------------ Jacobi SVD
-__global__ __launch_bounds__(256) void k_svd(const SVDDesc* __restrict__ descs) {
+// One-sided (Hestenes) Jacobi: columns a, b of A (m rows) are rotated until
+// every pair is orthogonal to 1e-15 relative; V accumulates the rotations.
+// Pairs follow the round-robin tournament (np = n rounded up to even; np - 1
+// rounds per sweep, np / 2 disjoint pairs per round).
+__device__ inline void tournament_pair(int np, int r, int k, int& a, int& b) {
+  if (k == 0) { a = np - 1; b = r; }
+  else { a = (r + k) % (np - 1); b = (r - k + (np - 1)) % (np - 1); }
+  if (a > b) { const int t = a; a = b; b = t; }
+}
+
+// rotate columns a < b of A (and V) by one wave; returns true if rotated
+__device__ inline bool jacobi_rotate(double* A, int lda, int m, double* V, int ldv, int n, int a,
+                                     int b, int lane) {
+  double* ca = A + (size_t)a * lda;
+  double* cb = A + (size_t)b * lda;
+  double al = 0, be = 0, ga = 0;
+  for (int i = lane; i < m; i += 64) {
+    const double x = ca[i], y = cb[i];
+    al += x * x;
+    be += y * y;
+    ga += x * y;
+  }
+  al = wave_sum(al);
+  be = wave_sum(be);
+  ga = wave_sum(ga);
+  if (ga == 0.0 || !(fabs(ga) > 1e-15 * sqrt(al) * sqrt(be))) return false;
+  const double zeta = (be - al) / (2.0 * ga);
+  double t;
+  if (fabs(zeta) > 1e150) t = 0.5 / zeta;
+  else t = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+  const double cs = 1.0 / sqrt(1.0 + t * t), sn = cs * t;
+  for (int i = lane; i < m; i += 64) {
+    const double x = ca[i], y = cb[i];
+    ca[i] = cs * x - sn * y;
+    cb[i] = sn * x + cs * y;
+  }
+  if (V) {
+    double* va = V + (size_t)a * ldv;
+    double* vb = V + (size_t)b * ldv;
+    for (int i = lane; i < n; i += 64) {
+      const double x = va[i], y = vb[i];
+      va[i] = cs * x - sn * y;
+      vb[i] = sn * x + cs * y;
+    }
+  }
+  return true;
+}
+
+__global__ void k_svd_init_v(const SVDDesc* __restrict__ descs) {
+  const SVDDesc d = descs[blockIdx.x];
+  if (!d.V) return;
+  for (int e = threadIdx.x; e < d.n * d.n; e += blockDim.x)
+    d.V[(size_t)(e / d.n) * d.ldv + e % d.n] = (e / d.n == e % d.n) ? 1.0 : 0.0;
+}
+
+// single workgroup per matrix (small n)
+__global__ __launch_bounds__(256) void k_svd_sweeps(const SVDDesc* __restrict__ descs) {
   const SVDDesc d = descs[blockIdx.x];
   const int n = d.n, m = d.m;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   __shared__ int rotated;
-  __shared__ double sig[1024];
-  __shared__ int order[1024];
-  double* A = d.A;
-  const int lda = d.lda;
-  double* V = d.V;
-  const int ldv = d.ldv;
-  const bool wantV = V != nullptr;
-  if (wantV)
-    for (int e = tid; e < n * n; e += 256) V[(size_t)(e / n) * ldv + e % n] = (e / n == e % n) ? 1.0 : 0.0;
   const int np = n + (n & 1);
   for (int sweep = 0; sweep < 60; ++sweep) {
-    if (tid == 0) rotated = 0;
+    if (threadIdx.x == 0) rotated = 0;
     __syncthreads();
     for (int r = 0; r < np - 1; ++r) {
       for (int k = wave; k < np / 2; k += 4) {
         int a, b;
-        if (k == 0) { a = np - 1; b = r; }
-        else { a = (r + k) % (np - 1); b = (r - k + (np - 1)) % (np - 1); }
-        if (a >= n || b >= n) continue;
-        if (a > b) { int tmp = a; a = b; b = tmp; }
-        double* ca = A + (size_t)a * lda;
-        double* cb = A + (size_t)b * lda;
-        double al = 0, be = 0, ga = 0;
-        for (int i = lane; i < m; i += 64) {
-          const double x = ca[i], y = cb[i];
-          al += x * x;
-          be += y * y;
-          ga += x * y;
-        }
-        al = wave_sum(al);
-        be = wave_sum(be);
-        ga = wave_sum(ga);
-        if (ga == 0.0 || !(fabs(ga) > 1e-15 * sqrt(al) * sqrt(be))) continue;
-        const double zeta = (be - al) / (2.0 * ga);
-        double t;
-        if (fabs(zeta) > 1e150) t = 0.5 / zeta;
-        else t = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-        const double cs = 1.0 / sqrt(1.0 + t * t), sn = cs * t;
-        for (int i = lane; i < m; i += 64) {
-          const double x = ca[i], y = cb[i];
-          ca[i] = cs * x - sn * y;
-          cb[i] = sn * x + cs * y;
-        }
-        if (wantV) {
-          double* va = V + (size_t)a * ldv;
-          double* vb = V + (size_t)b * ldv;
-          for (int i = lane; i < n; i += 64) {
-            const double x = va[i], y = vb[i];
-            va[i] = cs * x - sn * y;
-            vb[i] = sn * x + cs * y;
-          }
-        }
-        if (lane == 0) rotated = 1;
+        tournament_pair(np, r, k, a, b);
+        if (b >= n) continue;
+        if (jacobi_rotate(d.A, d.lda, m, d.V, d.ldv, n, a, b, lane) && lane == 0) rotated = 1;
       }
       __syncthreads();
     }
     if (!rotated) break;
     __syncthreads();
   }
-  // singular values = column norms; sort descending (stable)
+}
+
+// many workgroups per matrix: the pairs of one round are spread over all
+// waves assigned to the matrix, with a grid-wide barrier between rounds.
+// Every workgroup executes the same number of barriers (rounds of the widest
+// matrix, identical termination decision from flags read after a barrier).
+__global__ __launch_bounds__(256) void k_svd_coop(const SVDDesc* __restrict__ descs,
+                                                  const int* __restrict__ wg_start, int nmat,
+                                                  int maxnp, int* flags) {
+  cooperative_groups::grid_group grid = cooperative_groups::this_grid();
+  int lo = 0, hi = nmat - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (wg_start[mid] <= (int)blockIdx.x) lo = mid; else hi = mid - 1;
+  }
+  const int mi = lo;
+  const SVDDesc d = descs[mi];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int nwg = wg_start[mi + 1] - wg_start[mi];
+  const int wv = ((int)blockIdx.x - wg_start[mi]) * 4 + wave;
+  const int stride = nwg * 4;
+  const int n = d.n, m = d.m;
+  const int np = n + (n & 1);
+  for (int sweep = 0; sweep < 60; ++sweep) {
+    int* fl = flags + (sweep & 1) * nmat;
+    for (int r = 0; r < maxnp - 1; ++r) {
+      if (r < np - 1) {
+        for (int k = wv; k < np / 2; k += stride) {
+          int a, b;
+          tournament_pair(np, r, k, a, b);
+          if (b >= n) continue;
+          if (jacobi_rotate(d.A, d.lda, m, d.V, d.ldv, n, a, b, lane) && lane == 0)
+            atomicOr(&fl[mi], 1);
+        }
+      }
+      grid.sync();
+      if (r == 0 && blockIdx.x == 0 && threadIdx.x == 0)
+        for (int i = 0; i < nmat; ++i) atomicExch(&flags[((sweep + 1) & 1) * nmat + i], 0);
+    }
+    int any = 0;
+    for (int i = 0; i < nmat; ++i) any |= atomicAdd(&fl[i], 0);
+    if (!any) break;
+  }
+}
+
+// singular values = column norms, sorted descending; U = normalised columns;
+// V columns permuted accordingly (through A, which is no longer needed)
+__global__ __launch_bounds__(256) void k_svd_final(const SVDDesc* __restrict__ descs) {
+  const SVDDesc d = descs[blockIdx.x];
+  const int n = d.n, m = d.m;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  __shared__ double sig[1024];
+  __shared__ int order[1024];
+  double* A = d.A;
+  const int lda = d.lda;
   for (int col = wave; col < n; col += 4) {
     const double* ca = A + (size_t)col * lda;
     double s = 0;
@@ -413,32 +482,89 @@ __global__ __launch_bounds__(256) void k_svd(const SVDDesc* __restrict__ descs) 
     }
   }
   __syncthreads();
-  if (wantV) {
-    // permute V columns in place through A (A is no longer needed)
+  if (d.V) {
     for (int e = tid; e < n * n; e += 256) {
       const int i = e % n, c = e / n;
-      A[(size_t)c * lda + i] = V[(size_t)c * ldv + i];
+      A[(size_t)c * lda + i] = d.V[(size_t)c * d.ldv + i];
     }
     __syncthreads();
     for (int e = tid; e < n * n; e += 256) {
       const int i = e % n, r = e / n;
-      V[(size_t)r * ldv + i] = A[(size_t)order[r] * lda + i];
+      d.V[(size_t)r * d.ldv + i] = A[(size_t)order[r] * lda + i];
     }
   }
 }
 
+constexpr int SVD_COOP_MIN_N = 96;
+
 void svd_batched(Ctx& c, const std::vector<SVDDesc>& ds) {
-  std::vector<SVDDesc> v;
+  std::vector<SVDDesc> all, small, big;
   for (auto& d : ds) {
     if (d.n <= 0) continue;
     H2_CHECK(d.n <= 1024, H2_EINVAL, "SVD: more than 1024 columns");
     H2_CHECK(d.m >= d.n, H2_EINVAL, "SVD: needs m >= n");
     H2_CHECK(d.sigma != nullptr, H2_EINVAL, "SVD: sigma output required");
-    v.push_back(d);
+    all.push_back(d);
+    (d.n >= SVD_COOP_MIN_N ? big : small).push_back(d);
   }
-  if (v.empty()) return;
-  auto* dd = (SVDDesc*)c.stage.put(v.data(), v.size() * sizeof(SVDDesc), c.s);
-  k_svd<<<(unsigned)v.size(), 256, 0, c.s>>>(dd);
+  if (all.empty()) return;
+  auto* dall = (SVDDesc*)c.stage.put(all.data(), all.size() * sizeof(SVDDesc), c.s);
+  k_svd_init_v<<<(unsigned)all.size(), 256, 0, c.s>>>(dall);
+  H2_LAUNCH_CHECK();
+  if (!small.empty()) {
+    auto* dd = (SVDDesc*)c.stage.put(small.data(), small.size() * sizeof(SVDDesc), c.s);
+    k_svd_sweeps<<<(unsigned)small.size(), 256, 0, c.s>>>(dd);
+    H2_LAUNCH_CHECK();
+  }
+  if (!big.empty()) {
+    static int capacity = 0;
+    if (capacity == 0) {
+      int dev = 0, ncu = 0, per = 0;
+      H2_HIP(hipGetDevice(&dev));
+      H2_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+      H2_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_svd_coop, 256, 0));
+      capacity = std::max(1, ncu * std::max(per, 1));
+    }
+    // launches of at most `capacity` co-resident workgroups
+    size_t i0 = 0;
+    while (i0 < big.size()) {
+      size_t i1 = i0;
+      int used = 0;
+      std::vector<int> want;
+      while (i1 < big.size() && used + 1 <= capacity) {
+        const int np = big[i1].n + (big[i1].n & 1);
+        const int w = std::max(1, std::min(64, (np / 2 + 3) / 4));
+        want.push_back(w);
+        used += w;
+        ++i1;
+      }
+      const int nm = (int)(i1 - i0);
+      int tot = 0;
+      for (int w : want) tot += w;
+      // scale down to capacity (at least one workgroup per matrix)
+      if (tot > capacity) {
+        const double f = (double)(capacity - nm) / std::max(1, tot - nm);
+        tot = 0;
+        for (auto& w : want) { w = 1 + (int)((w - 1) * f); tot += w; }
+      }
+      std::vector<int> start(nm + 1, 0);
+      int maxnp = 0;
+      for (int j = 0; j < nm; ++j) {
+        start[j + 1] = start[j] + want[j];
+        maxnp = std::max(maxnp, big[i0 + j].n + (big[i0 + j].n & 1));
+      }
+      auto* dd = (SVDDesc*)c.stage.put(big.data() + i0, nm * sizeof(SVDDesc), c.s);
+      auto* dstart = (int*)c.stage.put(start.data(), start.size() * sizeof(int), c.s);
+      int* flags = (int*)c.scratch.get((size_t)nm);  // 2 * nm ints fit in nm doubles
+      H2_HIP(hipMemsetAsync(flags, 0, 2 * nm * sizeof(int), c.s));
+      int nmi = nm;
+      void* args[] = {&dd, &dstart, &nmi, &maxnp, &flags};
+      H2_HIP(hipLaunchCooperativeKernel((const void*)k_svd_coop, dim3(start[nm]), dim3(256), args, 0,
+                                        c.s));
+      i0 = i1;
+    }
+  }
+  k_svd_final<<<(unsigned)all.size(), 256, 0, c.s>>>(dall);
   H2_LAUNCH_CHECK();
 }
 

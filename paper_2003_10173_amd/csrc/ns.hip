@@ -12,6 +12,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
 #include <functional>
 
 #include "build.h"
@@ -139,6 +140,9 @@ std::unique_ptr<h2_matrix> ns_iterate(const h2_matrix* A, const h2_ns_opts& o, h
     for (int l = 0; l <= t->L; ++l) mr = std::max(mr, bst.strong_rank[l]);
     stats.max_rank[k] = mr;
     X = std::move(Xn);
+    if (verbose())
+      std::fprintf(stderr, "[h2_ns] iteration %d: E %.3e eps_k %.1e applies %lld max rank %d build %.1f ms\n",
+                   k, E, eps_k, (long long)bst.applies, mr, now_ms2() - t0);
     ++k;
   }
   stats.iterations = k;
