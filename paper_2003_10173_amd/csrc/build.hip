@@ -33,6 +33,8 @@
 
 namespace h2 {
 
+constexpr int TSQR_MIN_ROWS = 96;
+
 void keep_factors(int l, const std::vector<int>& k, int K, const double* F_dev, int n);
 void reset_factors();
 
@@ -332,8 +334,9 @@ std::unique_ptr<h2_matrix> build_h2(const h2_tree* t, Sampler& S, const BuildPar
       }
       copy_batched(c, app);
       // extend Qe with the projected block: QR, one more projection, QR again
+      // (tall panels by TSQR over many workgroups, short ones in one workgroup)
       {
-        std::vector<QRDesc> q1, q2;
+        std::vector<QRDesc> q1, q2, t1, t2;
         std::vector<GemmDesc> g1, g2;
         std::vector<CopyDesc> put;
         for (int p : act) {
@@ -341,14 +344,15 @@ std::unique_ptr<h2_matrix> build_h2(const h2_tree* t, Sampler& S, const BuildPar
           if (q >= m2) continue;
           const int kn = std::min(m2, b);
           const int take = std::min(kn, m2 - q);
+          const bool tall = m2 >= 2 * TSQR_MIN_ROWS && b <= 96;
           double* Qn = c.scratch.get((size_t)m2 * kn);
           double* Qn2 = c.scratch.get((size_t)m2 * kn);
-          q1.push_back({Yproj[p], m2, m2, b, Qn, m2, nullptr, 0});
+          (tall ? t1 : q1).push_back({Yproj[p], m2, m2, b, Qn, m2, nullptr, 0});
           if (q > 0) {
             double* Wq = c.scratch.get((size_t)q * kn);
             g1.push_back({Qe + qoff[p], Qn, Wq, q, kn, m2, m2, m2, q, 1, 0, 1.0, 0.0});
             g2.push_back({Qe + qoff[p], Wq, Qn, m2, kn, q, m2, q, m2, 0, 0, -1.0, 1.0});
-            q2.push_back({Qn, m2, m2, kn, Qn2, m2, nullptr, 0});
+            (tall ? t2 : q2).push_back({Qn, m2, m2, kn, Qn2, m2, nullptr, 0});
             put.push_back({Qn2, m2, Qe + qoff[p] + (size_t)q * m2, m2, m2, take, 1.0, 0.0, 0});
           } else {
             put.push_back({Qn, m2, Qe + qoff[p], m2, m2, take, 1.0, 0.0, 0});
@@ -356,9 +360,11 @@ std::unique_ptr<h2_matrix> build_h2(const h2_tree* t, Sampler& S, const BuildPar
           qc[p] = q + take;
         }
         qr_batched(c, q1);
+        qr_tall_batched(c, t1);
         gemm_batched(c, g1);
         gemm_batched(c, g2);
         qr_batched(c, q2);
+        qr_tall_batched(c, t2);
         copy_batched(c, put);
       }
       for (int p = 0; p < np; ++p)
@@ -448,13 +454,16 @@ std::unique_ptr<h2_matrix> build_h2(const h2_tree* t, Sampler& S, const BuildPar
       copy_batched(c, put);
       S.apply(c, K0, om, y);
       subtract_levels(c, t, lv, l, om, y, K0);
-      // truncated SVD of B0 (m1 x k0) by one-sided Jacobi on its tall side:
-      //   m1 >= k0:  B0 V = U S          ->  Q = Q0 V_k,  B = U_k S_k
-      //   m1 <  k0:  B0^T V = U S, B0 = V S U^T  ->  Q = Q0 U_k,  B = V_k S_k
-      std::vector<CopyDesc> b0c;
+      // truncated SVD of B0 (m1 x k0) by one-sided Jacobi:
+      //   mode 0 (m1 >= k0, small k0): B0 V = U S         -> Q = Q0 V_k, B = U_k S_k
+      //   mode 1 (m1 <  k0):  B0^T V = U S, B0 = V S U^T  -> Q = Q0 U_k, B = V_k S_k
+      //   mode 2 (m1 >= k0, large k0): B0 = Q_B R (blocked QR), R^T V = U S,
+      //          B0 = (Q_B V) S U^T                        -> Q = Q0 U_k, B = Q_B V_k S_k
+      std::vector<CopyDesc> b0c, rtc;
+      std::vector<CholQRDesc> bqr;
       std::vector<SVDDesc> svs;
-      std::vector<int> kb(np, 0);
-      std::vector<double*> Ub(np), Vb(np), sb(np);
+      std::vector<int> kb(np, 0), mode(np, 0);
+      std::vector<double*> Ub(np), Vb(np), sb(np), QB(np, nullptr);
       std::vector<int64_t> boff(np + 1, 0);
       for (int p = 0; p < np; ++p) boff[p + 1] = boff[p] + std::min(pr[p].m1, k0[p]);
       double* sb_all = c.scratch.get(std::max<int64_t>(boff[np], 1));
@@ -462,18 +471,33 @@ std::unique_ptr<h2_matrix> build_h2(const h2_tree* t, Sampler& S, const BuildPar
         if (k0[p] == 0) continue;
         const int m1 = pr[p].m1, kk = k0[p];
         kb[p] = std::min(m1, kk);
+        sb[p] = sb_all + boff[p];
+        if (m1 >= kk && kk >= 96 && m1 >= 128) {
+          mode[p] = 2;
+          QB[p] = c.scratch.get((size_t)m1 * kk);
+          double* RB = c.scratch.get((size_t)kk * kk);
+          double* RBt = c.scratch.get((size_t)kk * kk);
+          b0c.push_back({y + pr[p].a1, n, QB[p], m1, m1, kk, 1.0, 0.0, 0});
+          bqr.push_back({QB[p], m1, m1, kk, RB, kk});
+          rtc.push_back({RB, kk, RBt, kk, kk, kk, 1.0, 0.0, 1});
+          Ub[p] = c.scratch.get((size_t)kk * kk);
+          Vb[p] = c.scratch.get((size_t)kk * kk);
+          svs.push_back({RBt, kk, kk, kk, sb[p], Ub[p], kk, Vb[p], kk});
+          continue;
+        }
         const bool tall = m1 >= kk;
+        mode[p] = tall ? 0 : 1;
         const int mm = tall ? m1 : kk, nn = tall ? kk : m1;
         double* X = c.scratch.get((size_t)mm * nn);
+        // a transposed copy reads B0 (m1 x k0 at y + a1, ld n) as its source
         b0c.push_back({y + pr[p].a1, n, X, mm, mm, nn, 1.0, 0.0, tall ? 0 : 1});
         Ub[p] = c.scratch.get((size_t)mm * nn);
         Vb[p] = c.scratch.get((size_t)nn * nn);
-        sb[p] = sb_all + boff[p];
         svs.push_back({X, mm, mm, nn, sb[p], Ub[p], mm, Vb[p], nn});
       }
-      // the transposed copies read B0 from y (n x K0, ld n): src of a
-      // transposed copy is (cols x rows) = (m1 x k0) at y + a1 with lds = n
       copy_batched(c, b0c);
+      qr_blocked(c, bqr);
+      copy_batched(c, rtc);
       svd_batched(c, svs);
       auto sbh = to_host(sb_all, boff[np], c.s);
       for (int p = 0; p < np; ++p) {
@@ -495,14 +519,19 @@ std::unique_ptr<h2_matrix> build_h2(const h2_tree* t, Sampler& S, const BuildPar
         const int k = LV.k[p];
         if (k == 0) continue;
         const int m1 = pr[p].m1, m2 = pr[p].m2, kk = k0[p];
-        const bool tall = m1 >= kk;
-        // right singular vectors of B0 (k0 x kb) and left ones (m1 x kb)
-        const double* Rv = tall ? Vb[p] : Ub[p];
-        const int ldr = tall ? kb[p] : kk;
-        const double* Lv = tall ? Ub[p] : Vb[p];
-        const int ldl = tall ? m1 : kb[p];
-        g.push_back({Q0[p], Rv, F + pr[p].a2, m2, k, kk, m2, ldr, n, 0, 0, 1.0, 0.0});
-        cb.push_back({Lv, ldl, F + pr[p].a1, n, m1, k, 1.0, 0.0, 0});
+        if (mode[p] == 2) {
+          g.push_back({Q0[p], Ub[p], F + pr[p].a2, m2, k, kk, m2, kk, n, 0, 0, 1.0, 0.0});
+          g.push_back({QB[p], Vb[p], F + pr[p].a1, m1, k, kk, m1, kk, n, 0, 0, 1.0, 0.0});
+        } else {
+          const bool tall = mode[p] == 0;
+          // right singular vectors of B0 (k0 x kb) and left ones (m1 x kb)
+          const double* Rv = tall ? Vb[p] : Ub[p];
+          const int ldr = tall ? kb[p] : kk;
+          const double* Lv = tall ? Ub[p] : Vb[p];
+          const int ldl = tall ? m1 : kb[p];
+          g.push_back({Q0[p], Rv, F + pr[p].a2, m2, k, kk, m2, ldr, n, 0, 0, 1.0, 0.0});
+          cb.push_back({Lv, ldl, F + pr[p].a1, n, m1, k, 1.0, 0.0, 0});
+        }
         sc.push_back({F + pr[p].a1, n, m1, k, sb[p]});
       }
       gemm_batched(c, g);

@@ -77,6 +77,14 @@ struct CopyDesc {
   int trans;  // 1: dst = alpha src^T (src is cols x rows)
 };
 
+// In-place QR request: P (m x n, ld) is replaced by Q; R (n x n, upper) to R.
+struct CholQRDesc {
+  double* P;
+  int ld, m, n;
+  double* R;
+  int ldr;
+};
+
 struct Ctx {
   hipStream_t s = 0;
   Staging stage;
@@ -99,6 +107,12 @@ void scale_columns(Ctx& c, const std::vector<ScaleDesc>& d);
 void qr_batched(Ctx& c, const std::vector<QRDesc>& d);
 void svd_batched(Ctx& c, const std::vector<SVDDesc>& d);
 void copy_batched(Ctx& c, const std::vector<CopyDesc>& d);
+// tall-skinny Householder QR by a TSQR tree (n <= 96, m >= n): explicit Q and R
+void qr_tall_batched(Ctx& c, const std::vector<QRDesc>& d);
+// blocked QR of tall matrices (m >= n): 64-column panels, two block
+// Gram-Schmidt projections per panel by GEMM, TSQR per panel; P is
+// replaced by Q (m x n) and R (n x n, upper) is written to R
+void qr_blocked(Ctx& c, const std::vector<CholQRDesc>& d);
 // out[i] = max_j || X_i[:, j] || for blocks X_i (rows_i x cols_i, ld_i)
 void colnorm_max_batched(Ctx& c, const std::vector<CopyDesc>& blocks, double* out);
 // zero a column-major block

@@ -568,6 +568,312 @@ void svd_batched(Ctx& c, const std::vector<SVDDesc>& ds) {
   H2_LAUNCH_CHECK();
 }
 
+// ------------------------------------------------------------------ TSQR
+// Tall-skinny Householder QR (n <= 96 columns): row chunks of 96..191 rows are
+// factorised in LDS by one workgroup each, pairs of R factors are stacked and
+// factorised again up a binary tree, and the explicit Q is formed top-down by
+// batched GEMMs (Q = diag(Q_chunks) * ... * Q_root).  Backward stable for any
+// rank, like a single Householder QR.
+constexpr int TS_W = 96, TS_CH = 96, TS_LD = 193;
+
+struct TsqrNode {
+  const double* a;
+  int lda, ra;        // top rows
+  const double* b;
+  int ldb, rb;        // bottom rows (0: none)
+  int w;
+  double* Q;          // (ra + rb) x w explicit Q
+  int ldq;
+  double* R;          // w x w, zero below the diagonal
+  int ldr;
+};
+
+__global__ __launch_bounds__(256) void k_tsqr_node(const TsqrNode* __restrict__ nodes) {
+  const TsqrNode d = nodes[blockIdx.x];
+  __shared__ double A[TS_LD * TS_W];
+  __shared__ double taus[TS_W];
+  __shared__ double red[8];
+  __shared__ double bc[2];
+  const int m = d.ra + d.rb, w = d.w;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int e = tid; e < m * w; e += 256) {
+    const int i = e % m, j = e / m;
+    A[j * TS_LD + i] = i < d.ra ? d.a[(size_t)j * d.lda + i] : d.b[(size_t)j * d.ldb + (i - d.ra)];
+  }
+  __syncthreads();
+  const int kmin = min(m, w);
+  for (int j = 0; j < kmin; ++j) {
+    double* aj = A + j * TS_LD;
+    double s = 0;
+    for (int i = j + 1 + tid; i < m; i += 256) s += aj[i] * aj[i];
+    s = block_sum256(s, red);
+    if (tid == 0) {
+      const double alpha = aj[j];
+      double tau = 0, scale = 0;
+      if (s != 0.0) {
+        const double norm = sqrt(alpha * alpha + s);
+        const double beta = alpha >= 0 ? -norm : norm;
+        tau = (beta - alpha) / beta;
+        scale = 1.0 / (alpha - beta);
+        aj[j] = beta;
+      }
+      bc[0] = tau;
+      bc[1] = scale;
+      taus[j] = tau;
+    }
+    __syncthreads();
+    const double tau = bc[0], scale = bc[1];
+    for (int i = j + 1 + tid; i < m; i += 256) aj[i] *= scale;
+    __syncthreads();
+    if (tau != 0.0) {
+      for (int col = j + 1 + wave; col < w; col += 4) {
+        double* ac = A + col * TS_LD;
+        double t = 0;
+        for (int i = j + lane; i < m; i += 64) t += (i == j ? 1.0 : aj[i]) * ac[i];
+        t = wave_sum(t) * tau;
+        for (int i = j + lane; i < m; i += 64) ac[i] -= (i == j ? 1.0 : aj[i]) * t;
+      }
+    }
+    __syncthreads();
+  }
+  for (int e = tid; e < w * w; e += 256) {
+    const int i = e % w, c = e / w;
+    d.R[(size_t)c * d.ldr + i] = (i <= c && i < kmin) ? A[c * TS_LD + i] : 0.0;
+  }
+  __syncthreads();
+  // explicit Q in place (columns j = kmin-1 .. 0): Q_j = H_j Q_{j+1}
+  for (int j = kmin - 1; j >= 0; --j) {
+    const double tau = taus[j];
+    double* aj = A + j * TS_LD;
+    if (j < w - 1 && tau != 0.0) {
+      for (int col = j + 1 + wave; col < w; col += 4) {
+        double* ac = A + col * TS_LD;
+        double t = 0;
+        for (int i = j + lane; i < m; i += 64) t += (i == j ? 1.0 : aj[i]) * (i == j ? 0.0 : ac[i]);
+        t = wave_sum(t) * tau;
+        for (int i = j + lane; i < m; i += 64) {
+          const double cur = i == j ? 0.0 : ac[i];
+          ac[i] = cur - (i == j ? 1.0 : aj[i]) * t;
+        }
+      }
+    }
+    __syncthreads();
+    for (int i = tid; i < m; i += 256) {
+      if (i < j) aj[i] = 0.0;
+      else if (i == j) aj[i] = 1.0 - tau;
+      else aj[i] = -tau * aj[i];
+    }
+    __syncthreads();
+  }
+  // columns beyond kmin (only when m < w, not used by callers) stay as factorised
+  for (int e = tid; e < m * w; e += 256) {
+    const int i = e % m, j = e / m;
+    d.Q[(size_t)j * d.ldq + i] = j < kmin ? A[j * TS_LD + i] : 0.0;
+  }
+}
+
+static void launch_nodes(Ctx& c, const std::vector<TsqrNode>& v) {
+  if (v.empty()) return;
+  auto* dd = (TsqrNode*)c.stage.put(v.data(), v.size() * sizeof(TsqrNode), c.s);
+  k_tsqr_node<<<(unsigned)v.size(), 256, 0, c.s>>>(dd);
+  H2_LAUNCH_CHECK();
+}
+
+void qr_tall_batched(Ctx& c, const std::vector<QRDesc>& ds) {
+  // per matrix: the tree of nodes (level 0 = chunks)
+  struct Mat {
+    QRDesc d;
+    std::vector<std::vector<int>> lvl_rows;   // rows of each node per level
+    std::vector<std::vector<double*>> Qs, Rs;
+    std::vector<std::vector<int>> pass;       // 1: node passes its R through (no QR)
+  };
+  std::vector<Mat> mats;
+  for (auto& d : ds) {
+    if (d.m <= 0 || d.n <= 0) continue;
+    H2_CHECK(d.n <= TS_W && d.m >= d.n && d.Q != nullptr, H2_EINVAL, "TSQR: needs n <= 96, m >= n, Q");
+    Mat M;
+    M.d = d;
+    const int nch = std::max(1, d.m / TS_CH);
+    std::vector<int> rows(nch, TS_CH);
+    rows.back() += d.m - nch * TS_CH;
+    M.lvl_rows.push_back(rows);
+    mats.push_back(std::move(M));
+  }
+  if (mats.empty()) return;
+  // upward: level 0 chunks
+  {
+    std::vector<TsqrNode> nodes;
+    for (auto& M : mats) {
+      const int w = M.d.n;
+      auto& rows = M.lvl_rows[0];
+      M.Qs.push_back({});
+      M.Rs.push_back({});
+      M.pass.push_back(std::vector<int>(rows.size(), 0));
+      int r0 = 0;
+      for (size_t i = 0; i < rows.size(); ++i) {
+        double* Q = c.scratch.get((size_t)rows[i] * w);
+        double* R = c.scratch.get((size_t)w * w);
+        M.Qs[0].push_back(Q);
+        M.Rs[0].push_back(R);
+        nodes.push_back({M.d.A + r0, M.d.lda, rows[i], nullptr, 0, 0, w, Q, rows[i], R, w});
+        r0 += rows[i];
+      }
+    }
+    launch_nodes(c, nodes);
+  }
+  // upward: pairs of R factors until one remains
+  for (int lev = 1;; ++lev) {
+    std::vector<TsqrNode> nodes;
+    bool any = false;
+    for (auto& M : mats) {
+      const int w = M.d.n;
+      // this matrix's tree may already be complete
+      if ((int)M.Rs.size() < lev || M.Rs[lev - 1].size() == 1) continue;
+      const std::vector<double*> prevR = M.Rs[lev - 1];   // copy: Rs grows below
+      any = true;
+      const int cnt = ((int)prevR.size() + 1) / 2;
+      M.Qs.push_back({});
+      M.Rs.push_back({});
+      M.pass.push_back(std::vector<int>(cnt, 0));
+      for (int i = 0; i < cnt; ++i) {
+        if (2 * i + 1 < (int)prevR.size()) {
+          double* Q = c.scratch.get((size_t)2 * w * w);
+          double* R = c.scratch.get((size_t)w * w);
+          M.Qs[lev].push_back(Q);
+          M.Rs[lev].push_back(R);
+          nodes.push_back({prevR[2 * i], w, w, prevR[2 * i + 1], w, w, w, Q, 2 * w, R, w});
+        } else {
+          M.Qs[lev].push_back(nullptr);
+          M.Rs[lev].push_back(prevR[2 * i]);
+          M.pass[lev][i] = 1;
+        }
+      }
+    }
+    if (!any) break;
+    launch_nodes(c, nodes);
+  }
+  // R of the whole matrix
+  {
+    std::vector<CopyDesc> cp;
+    for (auto& M : mats)
+      if (M.d.R) cp.push_back({M.Rs.back()[0], M.d.n, M.d.R, M.d.ldr, M.d.n, M.d.n, 1.0, 0.0, 0});
+    copy_batched(c, cp);
+  }
+  // downward: X (w x w) per node, starting from the identity at the root
+  int maxlev = 0;
+  for (auto& M : mats) maxlev = std::max(maxlev, (int)M.Rs.size() - 1);
+  std::vector<std::vector<std::vector<const double*>>> X(mats.size());
+  std::vector<std::vector<std::vector<int>>> ldx(mats.size());
+  std::vector<double> eye;
+  for (size_t mi = 0; mi < mats.size(); ++mi) {
+    auto& M = mats[mi];
+    const int top = (int)M.Rs.size() - 1, w = M.d.n;
+    X[mi].assign(top + 1, {});
+    ldx[mi].assign(top + 1, {});
+    eye.assign((size_t)w * w, 0.0);
+    for (int i = 0; i < w; ++i) eye[(size_t)i * w + i] = 1.0;
+    X[mi][top] = {(const double*)c.stage.put(eye.data(), eye.size() * sizeof(double), c.s)};
+    ldx[mi][top] = {w};
+  }
+  for (int lev = maxlev; lev >= 1; --lev) {
+    std::vector<GemmDesc> g;
+    for (size_t mi = 0; mi < mats.size(); ++mi) {
+      auto& M = mats[mi];
+      const int top = (int)M.Rs.size() - 1, w = M.d.n;
+      if (lev > top) continue;
+      const size_t cnt = M.Rs[lev].size();
+      X[mi][lev - 1].assign(M.Rs[lev - 1].size(), nullptr);
+      ldx[mi][lev - 1].assign(M.Rs[lev - 1].size(), w);
+      for (size_t i = 0; i < cnt; ++i) {
+        if (M.pass[lev][i]) {  // R passed through: the child keeps this X
+          X[mi][lev - 1][2 * i] = X[mi][lev][i];
+          ldx[mi][lev - 1][2 * i] = ldx[mi][lev][i];
+          continue;
+        }
+        double* Y = c.scratch.get((size_t)2 * w * w);
+        g.push_back({M.Qs[lev][i], X[mi][lev][i], Y, 2 * w, w, w, 2 * w, ldx[mi][lev][i], 2 * w, 0, 0, 1.0, 0.0});
+        X[mi][lev - 1][2 * i] = Y;
+        X[mi][lev - 1][2 * i + 1] = Y + w;
+        ldx[mi][lev - 1][2 * i] = 2 * w;
+        ldx[mi][lev - 1][2 * i + 1] = 2 * w;
+      }
+    }
+    gemm_batched(c, g);
+  }
+  // level 0: Q rows of each chunk = Q_chunk X
+  std::vector<GemmDesc> g;
+  for (size_t mi = 0; mi < mats.size(); ++mi) {
+    auto& M = mats[mi];
+    const int w = M.d.n;
+    int r0 = 0;
+    for (size_t i = 0; i < M.lvl_rows[0].size(); ++i) {
+      const int rows = M.lvl_rows[0][i];
+      g.push_back({M.Qs[0][i], X[mi][0][i], M.d.Q + r0, rows, w, w, rows, ldx[mi][0][i], M.d.ldq, 0, 0, 1.0, 0.0});
+      r0 += rows;
+    }
+  }
+  gemm_batched(c, g);
+}
+
+void qr_blocked(Ctx& c, const std::vector<CholQRDesc>& ds) {
+  // block Gram-Schmidt with reorthogonalisation of the normalised block
+  // (BCGS2):  S1 = Q^T P, P -= Q S1, P = Q1 R1;  S2 = Q^T Q1, Q1 -= Q S2,
+  // Q1 = Q2 R2;  R_jj = R2 R1,  R[0:j0, j] = S1 + S2 R1.  Stable when the
+  // panel is numerically dependent on the previous ones.
+  constexpr int W = 64;
+  int maxp = 0;
+  std::vector<CholQRDesc> v;
+  for (auto& d : ds)
+    if (d.m > 0 && d.n > 0) {
+      H2_CHECK(d.m >= d.n && d.R != nullptr, H2_EINVAL, "blocked QR needs m >= n and R");
+      v.push_back(d);
+      maxp = std::max(maxp, (d.n + W - 1) / W);
+    }
+  if (v.empty()) return;
+  for (auto& d : v) zero_block(c, d.R, d.n, d.n, d.ldr);
+  for (int j = 0; j < maxp; ++j) {
+    std::vector<GemmDesc> p1, p2, p3, p4, rr, rs;
+    std::vector<QRDesc> tq1, tq2;
+    std::vector<CopyDesc> back;
+    for (auto& d : v) {
+      const int j0 = j * W;
+      if (j0 >= d.n) continue;
+      const int w = std::min(W, d.n - j0);
+      double* Pj = d.P + (size_t)j0 * d.ld;
+      double* Rj = d.R + (size_t)j0 * d.ldr;      // R[0:j0, j0:j0+w]
+      double* Rjj = Rj + j0;
+      double* Q1 = c.scratch.get((size_t)d.m * w);
+      if (j0 == 0) {
+        tq1.push_back({Pj, d.ld, d.m, w, Q1, d.m, Rjj, d.ldr});
+        back.push_back({Q1, d.m, Pj, d.ld, d.m, w, 1.0, 0.0, 0});
+        continue;
+      }
+      double* R1 = c.scratch.get((size_t)w * w);
+      double* R2 = c.scratch.get((size_t)w * w);
+      double* S2 = c.scratch.get((size_t)j0 * w);
+      double* Q2 = c.scratch.get((size_t)d.m * w);
+      p1.push_back({d.P, Pj, Rj, j0, w, d.m, d.ld, d.ld, d.ldr, 1, 0, 1.0, 0.0});      // S1
+      p2.push_back({d.P, Rj, Pj, d.m, w, j0, d.ld, d.ldr, d.ld, 0, 0, -1.0, 1.0});     // P -= Q S1
+      tq1.push_back({Pj, d.ld, d.m, w, Q1, d.m, R1, w});                                // P = Q1 R1
+      p3.push_back({d.P, Q1, S2, j0, w, d.m, d.ld, d.m, j0, 1, 0, 1.0, 0.0});          // S2
+      p4.push_back({d.P, S2, Q1, d.m, w, j0, d.ld, j0, d.m, 0, 0, -1.0, 1.0});         // Q1 -= Q S2
+      tq2.push_back({Q1, d.m, d.m, w, Q2, d.m, R2, w});                                 // Q1 = Q2 R2
+      rr.push_back({R2, R1, Rjj, w, w, w, w, w, d.ldr, 0, 0, 1.0, 0.0});                // R_jj
+      rs.push_back({S2, R1, Rj, j0, w, w, j0, w, d.ldr, 0, 0, 1.0, 1.0});               // S1 += S2 R1
+      back.push_back({Q2, d.m, Pj, d.ld, d.m, w, 1.0, 0.0, 0});
+    }
+    gemm_batched(c, p1);
+    gemm_batched(c, p2);
+    qr_tall_batched(c, tq1);
+    gemm_batched(c, p3);
+    gemm_batched(c, p4);
+    qr_tall_batched(c, tq2);
+    gemm_batched(c, rr);
+    gemm_batched(c, rs);
+    copy_batched(c, back);
+  }
+}
+
 // ------------------------------------------------------------------ copies, norms
 __global__ void k_copy(const CopyDesc* __restrict__ ds) {
   const CopyDesc d = ds[blockIdx.y];

@@ -69,6 +69,27 @@ h2_status h2_test_qr(int m, int n, const double* A, double* Q, double* R) {
   });
 }
 
+h2_status h2_test_cholqr(int m, int n, const double* A, double* Q, double* R, int blocked) {
+  return guarded_status([&] {
+    DevBuf a((size_t)m * n * 8), r((size_t)n * n * 8);
+    H2_HIP(hipMemcpy(a.p, A, (size_t)m * n * 8, hipMemcpyHostToDevice));
+    Ctx ctx;
+    std::vector<CholQRDesc> d{{a.as<double>(), m, m, n, r.as<double>(), n}};
+    if (blocked) {
+      qr_blocked(ctx, d);
+    } else {
+      DevBuf q((size_t)m * n * 8);
+      std::vector<QRDesc> t{{a.as<double>(), m, m, n, q.as<double>(), m, r.as<double>(), n}};
+      qr_tall_batched(ctx, t);
+      H2_HIP(hipDeviceSynchronize());
+      H2_HIP(hipMemcpy(a.p, q.p, (size_t)m * n * 8, hipMemcpyDeviceToDevice));
+    }
+    H2_HIP(hipDeviceSynchronize());
+    if (Q) H2_HIP(hipMemcpy(Q, a.p, (size_t)m * n * 8, hipMemcpyDeviceToHost));
+    if (R) H2_HIP(hipMemcpy(R, r.p, (size_t)n * n * 8, hipMemcpyDeviceToHost));
+  });
+}
+
 h2_status h2_test_svd(int m, int n, const double* A, double* sigma, double* U, double* V) {
   return guarded_status([&] {
     DevBuf a((size_t)m * n * 8), s((size_t)n * 8), u((size_t)m * n * 8), v((size_t)n * n * 8);
