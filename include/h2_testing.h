@@ -26,6 +26,12 @@ h2_status h2_test_qr(int m, int n, const double* A, double* Q, double* R);
 h2_status h2_test_cholqr(int m, int n, const double* A, double* Q, double* R, int blocked);
 /* one-sided Jacobi SVD of A (m x n, m >= n): sigma (n), U (m x n), V (n x n) */
 h2_status h2_test_svd(int m, int n, const double* A, double* sigma, double* U, double* V);
+// The same for `count` matrices in one batched call: matrix i is m[i] x n[i]
+// (m[i] >= n[i]); A and U are the column-major matrices stored one after the
+// other, sigma the n[i] values one after the other, V the n[i] x n[i] factors
+// one after the other.
+h2_status h2_test_svd_batch(int count, const int* m, const int* n, const double* A, double* sigma,
+                            double* U, double* V);
 /* keep the weak factors of subsequent h2_build calls on this thread (1) or not (0) */
 void h2_test_keep_factors(int on);
 /* factors of level l of the last kept build: ranks (2^(l-1)) and F (n x K, K = max rank) */

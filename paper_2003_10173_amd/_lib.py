@@ -92,6 +92,7 @@ SIGNATURES = {
                                C.c_int, dbl, vp, C.c_int]),
     "h2_test_qr": (C.c_int, [C.c_int, C.c_int, vp, vp, vp]),
     "h2_test_svd": (C.c_int, [C.c_int, C.c_int, vp, vp, vp, vp]),
+    "h2_test_svd_batch": (C.c_int, [C.c_int, vp, vp, vp, vp, vp, vp]),
     "h2_test_cholqr": (C.c_int, [C.c_int, C.c_int, vp, vp, vp, C.c_int]),
     "h2_test_keep_factors": (None, [C.c_int]),
     "h2_test_factors": (C.c_int, [C.c_int, vp, vp, vp]),

@@ -8,6 +8,7 @@
 // a fixed order, so results are deterministic.
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 
 #include <hip/hip_cooperative_groups.h>
@@ -332,6 +333,11 @@ __device__ inline void tournament_pair(int np, int r, int k, int& a, int& b) {
   if (a > b) { const int t = a; a = b; b = t; }
 }
 
+// Rotation threshold: columns count as orthogonal once |a.b| <= tol |a| |b|
+// with tol at the rounding level of an m-term dot product, so that no sweep
+// is spent on rotations that only move rounding noise around.
+__device__ inline double jacobi_tol(int m) { return fmax(1e-15, (double)m * 0x1p-53); }
+
 // rotate columns a < b of A (and V) by one wave; returns true if rotated
 __device__ inline bool jacobi_rotate(double* A, int lda, int m, double* V, int ldv, int n, int a,
                                      int b, int lane) {
@@ -347,7 +353,7 @@ __device__ inline bool jacobi_rotate(double* A, int lda, int m, double* V, int l
   al = wave_sum(al);
   be = wave_sum(be);
   ga = wave_sum(ga);
-  if (ga == 0.0 || !(fabs(ga) > 1e-15 * sqrt(al) * sqrt(be))) return false;
+  if (ga == 0.0 || !(fabs(ga) > jacobi_tol(m) * sqrt(al) * sqrt(be))) return false;
   const double zeta = (be - al) / (2.0 * ga);
   double t;
   if (fabs(zeta) > 1e150) t = 0.5 / zeta;
@@ -401,14 +407,25 @@ __global__ __launch_bounds__(256) void k_svd_sweeps(const SVDDesc* __restrict__ 
   }
 }
 
-// many workgroups per matrix: the pairs of one round are spread over all
-// waves assigned to the matrix, with a grid-wide barrier between rounds.
-// Every workgroup executes the same number of barriers (rounds of the widest
-// matrix, identical termination decision from flags read after a barrier).
-__global__ __launch_bounds__(256) void k_svd_coop(const SVDDesc* __restrict__ descs,
-                                                  const int* __restrict__ wg_start, int nmat,
-                                                  int maxnp, int* flags) {
+// Block one-sided Jacobi over many workgroups: columns are grouped in blocks
+// of SVD_BS; each round of the block tournament gives every workgroup one
+// pair of blocks, whose 2*SVD_BS columns are rotated pairwise in LDS (one
+// cyclic inner sweep), with the accumulated rotation applied to the matching
+// columns of V.  A grid-wide barrier
+// separates rounds; every workgroup executes the same number of barriers
+// (rounds of the widest matrix, identical termination decision from flags read
+// after a barrier).
+constexpr int SVD_BS = 8, SVD_PC = 2 * SVD_BS, SVD_MMAX = 1024;
+
+__global__ __launch_bounds__(512) void k_svd_block(const SVDDesc* __restrict__ descs,
+                                                   const int* __restrict__ wg_start, int nmat,
+                                                   int maxnpb, int* flags, int* sweeps_out) {
   cooperative_groups::grid_group grid = cooperative_groups::this_grid();
+  __shared__ double L[SVD_PC * SVD_MMAX];
+  __shared__ double Vl[SVD_PC * SVD_PC];
+  __shared__ double Gl[SVD_PC * SVD_PC];
+  __shared__ int cols[SVD_PC];
+  __shared__ int rot_any;
   int lo = 0, hi = nmat - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
@@ -416,23 +433,119 @@ __global__ __launch_bounds__(256) void k_svd_coop(const SVDDesc* __restrict__ de
   }
   const int mi = lo;
   const SVDDesc d = descs[mi];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int nwg = wg_start[mi + 1] - wg_start[mi];
-  const int wv = ((int)blockIdx.x - wg_start[mi]) * 4 + wave;
-  const int stride = nwg * 4;
+  const int wl = (int)blockIdx.x - wg_start[mi];
   const int n = d.n, m = d.m;
-  const int np = n + (n & 1);
+  const int nb = (n + SVD_BS - 1) / SVD_BS;
+  const int npb = nb + (nb & 1);
   for (int sweep = 0; sweep < 60; ++sweep) {
     int* fl = flags + (sweep & 1) * nmat;
-    for (int r = 0; r < maxnp - 1; ++r) {
-      if (r < np - 1) {
-        for (int k = wv; k < np / 2; k += stride) {
-          int a, b;
-          tournament_pair(np, r, k, a, b);
-          if (b >= n) continue;
-          if (jacobi_rotate(d.A, d.lda, m, d.V, d.ldv, n, a, b, lane) && lane == 0)
-            atomicOr(&fl[mi], 1);
+    for (int r = 0; r < maxnpb - 1; ++r) {
+      for (int k = wl; r < npb - 1 && k < npb / 2; k += nwg) {
+        int bi, bj;
+        tournament_pair(npb, r, k, bi, bj);
+        // gather the columns of both blocks (the dummy block has none)
+        if (tid == 0) {
+          int c = 0;
+          for (int q = 0; q < SVD_BS; ++q) {
+            const int ci = bi * SVD_BS + q;
+            if (bi < nb && ci < n) cols[c++] = ci;
+          }
+          for (int q = 0; q < SVD_BS; ++q) {
+            const int cj = bj * SVD_BS + q;
+            if (bj < nb && cj < n) cols[c++] = cj;
+          }
+          for (; c < SVD_PC; ++c) cols[c] = -1;
+          rot_any = 0;
         }
+        __syncthreads();
+        int nc = 0;
+        for (int q = 0; q < SVD_PC; ++q) nc += cols[q] >= 0;
+        for (int e = tid; e < SVD_PC * m; e += 512) {
+          const int q = e / m, i = e % m;
+          L[q * m + i] = q < nc ? d.A[(size_t)cols[q] * d.lda + i] : 0.0;
+        }
+        for (int e = tid; e < SVD_PC * SVD_PC; e += 512) Vl[e] = (e / SVD_PC == e % SVD_PC) ? 1.0 : 0.0;
+        __syncthreads();
+        // one cyclic inner sweep over the nc columns: every pair of the two
+        // blocks is met once per visit, as often as in the scalar cyclic order
+        const int npc = nc + (nc & 1);
+        for (int rr = 0; rr < npc - 1; ++rr) {
+          for (int kk = wave; kk < npc / 2; kk += 8) {
+            int a, b;
+            tournament_pair(npc, rr, kk, a, b);
+            if (b >= nc) continue;
+            double* ca = L + a * m;
+            double* cb = L + b * m;
+            double al = 0, be = 0, ga = 0;
+            for (int i = lane; i < m; i += 64) {
+              const double x = ca[i], y = cb[i];
+              al += x * x;
+              be += y * y;
+              ga += x * y;
+            }
+            al = wave_sum(al);
+            be = wave_sum(be);
+            ga = wave_sum(ga);
+            if (ga == 0.0 || !(fabs(ga) > jacobi_tol(m) * sqrt(al) * sqrt(be))) continue;
+            const double zeta = (be - al) / (2.0 * ga);
+            double t;
+            if (fabs(zeta) > 1e150) t = 0.5 / zeta;
+            else t = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+            const double cs = 1.0 / sqrt(1.0 + t * t), sn = cs * t;
+            for (int i = lane; i < m; i += 64) {
+              const double x = ca[i], y = cb[i];
+              ca[i] = cs * x - sn * y;
+              cb[i] = sn * x + cs * y;
+            }
+            if (lane < SVD_PC) {
+              const double x = Vl[a * SVD_PC + lane], y = Vl[b * SVD_PC + lane];
+              Vl[a * SVD_PC + lane] = cs * x - sn * y;
+              Vl[b * SVD_PC + lane] = sn * x + cs * y;
+            }
+            if (lane == 0) rot_any = 1;
+          }
+          __syncthreads();
+        }
+        // restore the orthogonality of the accumulated rotation lost to
+        // rounding (one Newton-Schulz polar step Q <- Q (3I - Q^T Q) / 2) so
+        // that the many block products applied to V do not drift
+        if (rot_any && d.V) {
+          if (tid < SVD_PC * SVD_PC) {
+            const int i = tid / SVD_PC, j = tid % SVD_PC;
+            double g = 0;
+            for (int p = 0; p < SVD_PC; ++p) g += Vl[i * SVD_PC + p] * Vl[j * SVD_PC + p];
+            Gl[j * SVD_PC + i] = ((i == j ? 3.0 : 0.0) - g) * 0.5;
+          }
+          __syncthreads();
+          double qn = 0;
+          if (tid < SVD_PC * SVD_PC) {
+            const int q = tid / SVD_PC, p = tid % SVD_PC;
+            for (int r2 = 0; r2 < SVD_PC; ++r2) qn += Vl[r2 * SVD_PC + p] * Gl[q * SVD_PC + r2];
+          }
+          __syncthreads();
+          if (tid < SVD_PC * SVD_PC) Vl[tid] = qn;
+          __syncthreads();
+        }
+        // write back the columns and update V(:, cols) <- V(:, cols) Vl
+        for (int e = tid; e < nc * m; e += 512) {
+          const int q = e / m, i = e % m;
+          d.A[(size_t)cols[q] * d.lda + i] = L[q * m + i];
+        }
+        if (d.V) {
+          for (int i = tid; i < n; i += 512) {
+            double row[SVD_PC];
+            for (int q = 0; q < nc; ++q) row[q] = d.V[(size_t)cols[q] * d.ldv + i];
+            for (int q = 0; q < nc; ++q) {
+              double acc = 0;
+              for (int p = 0; p < nc; ++p) acc += row[p] * Vl[q * SVD_PC + p];
+              d.V[(size_t)cols[q] * d.ldv + i] = acc;
+            }
+          }
+        }
+        if (tid == 0 && rot_any) atomicOr(&fl[mi], 1);
+        __syncthreads();
       }
       grid.sync();
       if (r == 0 && blockIdx.x == 0 && threadIdx.x == 0)
@@ -440,7 +553,10 @@ __global__ __launch_bounds__(256) void k_svd_coop(const SVDDesc* __restrict__ de
     }
     int any = 0;
     for (int i = 0; i < nmat; ++i) any |= atomicAdd(&fl[i], 0);
-    if (!any) break;
+    if (!any || sweep == 59) {
+      if (blockIdx.x == 0 && threadIdx.x == 0) atomicExch(sweeps_out, sweep + 1);
+      break;
+    }
   }
 }
 
@@ -505,7 +621,7 @@ void svd_batched(Ctx& c, const std::vector<SVDDesc>& ds) {
     H2_CHECK(d.m >= d.n, H2_EINVAL, "SVD: needs m >= n");
     H2_CHECK(d.sigma != nullptr, H2_EINVAL, "SVD: sigma output required");
     all.push_back(d);
-    (d.n >= SVD_COOP_MIN_N ? big : small).push_back(d);
+    (d.n >= SVD_COOP_MIN_N && d.m <= SVD_MMAX ? big : small).push_back(d);
   }
   if (all.empty()) return;
   auto* dall = (SVDDesc*)c.stage.put(all.data(), all.size() * sizeof(SVDDesc), c.s);
@@ -522,45 +638,58 @@ void svd_batched(Ctx& c, const std::vector<SVDDesc>& ds) {
       int dev = 0, ncu = 0, per = 0;
       H2_HIP(hipGetDevice(&dev));
       H2_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
-      H2_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_svd_coop, 256, 0));
+      H2_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_svd_block, 512, 0));
       capacity = std::max(1, ncu * std::max(per, 1));
     }
-    // launches of at most `capacity` co-resident workgroups
+    // launches of at most `capacity` co-resident workgroups, one block pair each
     size_t i0 = 0;
     while (i0 < big.size()) {
       size_t i1 = i0;
       int used = 0;
       std::vector<int> want;
-      while (i1 < big.size() && used + 1 <= capacity) {
-        const int np = big[i1].n + (big[i1].n & 1);
-        const int w = std::max(1, std::min(64, (np / 2 + 3) / 4));
-        want.push_back(w);
-        used += w;
+      while (i1 < big.size()) {
+        const int nb = (big[i1].n + SVD_BS - 1) / SVD_BS;
+        const int w = (nb + (nb & 1)) / 2;
+        if (used > 0 && used + w > capacity) break;
+        want.push_back(std::min(w, capacity));
+        used += want.back();
         ++i1;
       }
       const int nm = (int)(i1 - i0);
-      int tot = 0;
-      for (int w : want) tot += w;
-      // scale down to capacity (at least one workgroup per matrix)
-      if (tot > capacity) {
-        const double f = (double)(capacity - nm) / std::max(1, tot - nm);
-        tot = 0;
-        for (auto& w : want) { w = 1 + (int)((w - 1) * f); tot += w; }
-      }
       std::vector<int> start(nm + 1, 0);
-      int maxnp = 0;
+      int maxnpb = 0;
       for (int j = 0; j < nm; ++j) {
         start[j + 1] = start[j] + want[j];
-        maxnp = std::max(maxnp, big[i0 + j].n + (big[i0 + j].n & 1));
+        const int nb = (big[i0 + j].n + SVD_BS - 1) / SVD_BS;
+        maxnpb = std::max(maxnpb, nb + (nb & 1));
       }
       auto* dd = (SVDDesc*)c.stage.put(big.data() + i0, nm * sizeof(SVDDesc), c.s);
       auto* dstart = (int*)c.stage.put(start.data(), start.size() * sizeof(int), c.s);
-      int* flags = (int*)c.scratch.get((size_t)nm);  // 2 * nm ints fit in nm doubles
-      H2_HIP(hipMemsetAsync(flags, 0, 2 * nm * sizeof(int), c.s));
+      int* flags = (int*)c.scratch.get((size_t)nm + 1);  // 2 * nm + 1 ints
+      H2_HIP(hipMemsetAsync(flags, 0, (2 * nm + 1) * sizeof(int), c.s));
+      int* sweeps = flags + 2 * nm;
       int nmi = nm;
-      void* args[] = {&dd, &dstart, &nmi, &maxnp, &flags};
-      H2_HIP(hipLaunchCooperativeKernel((const void*)k_svd_coop, dim3(start[nm]), dim3(256), args, 0,
-                                        c.s));
+      void* args[] = {&dd, &dstart, &nmi, &maxnpb, &flags, &sweeps};
+      hipEvent_t e0 = nullptr, e1 = nullptr;
+      if (verbose()) {
+        H2_HIP(hipEventCreate(&e0));
+        H2_HIP(hipEventCreate(&e1));
+        H2_HIP(hipEventRecord(e0, c.s));
+      }
+      H2_HIP(hipLaunchCooperativeKernel((const void*)k_svd_block, dim3(start[nm]), dim3(512), args,
+                                        0, c.s));
+      if (verbose()) {
+        H2_HIP(hipEventRecord(e1, c.s));
+        H2_HIP(hipEventSynchronize(e1));
+        float ms = 0;
+        H2_HIP(hipEventElapsedTime(&ms, e0, e1));
+        int sw = 0;
+        H2_HIP(hipMemcpy(&sw, sweeps, sizeof(int), hipMemcpyDeviceToHost));
+        std::fprintf(stderr, "    [svd] %d matrices, n %d..%d, m %d, %d workgroups: %d sweeps, %.2f ms\n",
+                     nm, big[i0].n, big[i1 - 1].n, big[i0].m, start[nm], sw, ms);
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+      }
       i0 = i1;
     }
   }

@@ -104,6 +104,37 @@ h2_status h2_test_svd(int m, int n, const double* A, double* sigma, double* U, d
   });
 }
 
+h2_status h2_test_svd_batch(int count, const int* m, const int* n, const double* A, double* sigma,
+                            double* U, double* V) {
+  return guarded_status([&] {
+    H2_CHECK(count >= 0 && m && n && A && sigma && U && V, H2_EINVAL, "null argument");
+    size_t na = 0, ns = 0, nv = 0;
+    for (int i = 0; i < count; ++i) {
+      H2_CHECK(m[i] >= n[i] && n[i] >= 0, H2_EINVAL, "needs m >= n >= 0");
+      na += (size_t)m[i] * n[i];
+      ns += n[i];
+      nv += (size_t)n[i] * n[i];
+    }
+    DevBuf a(na * 8 + 8), s(ns * 8 + 8), u(na * 8 + 8), v(nv * 8 + 8);
+    H2_HIP(hipMemcpy(a.p, A, na * 8, hipMemcpyHostToDevice));
+    std::vector<SVDDesc> d;
+    size_t oa = 0, os = 0, ov = 0;
+    for (int i = 0; i < count; ++i) {
+      d.push_back({a.as<double>() + oa, m[i], m[i], n[i], s.as<double>() + os, u.as<double>() + oa,
+                   m[i], v.as<double>() + ov, n[i]});
+      oa += (size_t)m[i] * n[i];
+      os += n[i];
+      ov += (size_t)n[i] * n[i];
+    }
+    Ctx ctx;
+    svd_batched(ctx, d);
+    H2_HIP(hipDeviceSynchronize());
+    H2_HIP(hipMemcpy(sigma, s.p, ns * 8, hipMemcpyDeviceToHost));
+    H2_HIP(hipMemcpy(U, u.p, na * 8, hipMemcpyDeviceToHost));
+    H2_HIP(hipMemcpy(V, v.p, nv * 8, hipMemcpyDeviceToHost));
+  });
+}
+
 void h2_test_keep_factors(int on) { g_keep_factors = on != 0; }
 
 h2_status h2_test_factors(int level, int32_t* ranks_out, int* K_out, double* F_out) {

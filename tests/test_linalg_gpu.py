@@ -74,7 +74,8 @@ def svd(A):
 
 
 @pytest.mark.parametrize("m,n,decay", [(40, 40, 0.0), (102, 64, 0.3), (200, 64, 0.6),
-                                       (256, 256, 0.1), (70, 70, 1.0)])
+                                       (256, 256, 0.1), (70, 70, 1.0), (665, 104, 0.2),
+                                       (600, 600, 0.02), (1100, 100, 0.1), (97, 97, 0.0)])
 def test_jacobi_svd_matches_lapack(m, n, decay):
     g = np.random.default_rng(m * n)
     U0 = np.linalg.qr(g.standard_normal((m, n)))[0]
@@ -89,6 +90,41 @@ def test_jacobi_svd_matches_lapack(m, n, decay):
     assert np.abs(U[:, keep].T @ U[:, keep] - np.eye(keep.sum())).max() <= 1e-12
     assert np.abs(V.T @ V - np.eye(n)).max() <= 1e-12
     assert np.abs(U[:, keep] * s[keep] @ V[:, keep].T - A).max() <= 1e-12 * sl[0] * n
+
+
+def test_jacobi_svd_batch_uneven():
+    """Several matrices of uneven sizes in one call (small and multi-workgroup
+    ones mixed, odd block counts, a ragged last block)."""
+    g = np.random.default_rng(7)
+    shapes = [(665, 111), (96, 96), (300, 250), (50, 30), (130, 97), (400, 399), (64, 64)]
+    mats, svs = [], []
+    for (m, n) in shapes:
+        U0 = np.linalg.qr(g.standard_normal((m, n)))[0]
+        V0 = np.linalg.qr(g.standard_normal((n, n)))[0]
+        sv = np.exp(-0.05 * np.arange(n)) * g.uniform(0.5, 2.0)
+        mats.append(U0 @ np.diag(sv) @ V0.T)
+        svs.append(sv)
+    ms = np.array([m for m, _ in shapes], dtype=np.int32)
+    ns = np.array([n for _, n in shapes], dtype=np.int32)
+    A = np.concatenate([F(a).ravel(order="F") for a in mats])
+    S = np.zeros(int(ns.sum()))
+    U = np.zeros(A.size)
+    V = np.zeros(int((ns.astype(np.int64) ** 2).sum()))
+    h2.check(L().h2_test_svd_batch(len(shapes), ms.ctypes.data, ns.ctypes.data, A.ctypes.data,
+                                   S.ctypes.data, U.ctypes.data, V.ctypes.data), "svd batch")
+    oa = os_ = ov = 0
+    for (m, n), a in zip(shapes, mats):
+        s = S[os_:os_ + n]
+        u = U[oa:oa + m * n].reshape((m, n), order="F")
+        v = V[ov:ov + n * n].reshape((n, n), order="F")
+        sl = np.linalg.svd(a, compute_uv=False)
+        assert np.abs(s - sl).max() <= 1e-14 * sl[0] * n, (m, n)
+        assert np.abs(u.T @ u - np.eye(n)).max() <= 1e-12, (m, n)
+        assert np.abs(v.T @ v - np.eye(n)).max() <= 1e-12, (m, n)
+        assert np.abs(u * s @ v.T - a).max() <= 1e-12 * sl[0] * n, (m, n)
+        oa += m * n
+        os_ += n
+        ov += n * n
 
 
 def cholqr(A, blocked):
