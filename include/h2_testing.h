@@ -21,9 +21,10 @@ h2_status h2_test_gemm(int ta, int tb, int M, int N, int K, double alpha, const 
                        const double* B, int ldb, double beta, double* C, int ldc);
 /* Householder QR of A (m x n): Q (m x min(m,n)), R (min(m,n) x n); either may be NULL */
 h2_status h2_test_qr(int m, int n, const double* A, double* Q, double* R);
-/* tall QR, m >= n: Q (m x n) and R (n x n); blocked = 1: block Gram-Schmidt
-   over 64-column panels with TSQR panels; blocked = 0: one TSQR (n <= 96) */
-h2_status h2_test_cholqr(int m, int n, const double* A, double* Q, double* R, int blocked);
+/* tall QR, m >= n: Q (m x n) and R (n x n); mode 0: one TSQR (n <= 96);
+   1: block Gram-Schmidt over 64-column panels with TSQR panels; 2: the
+   kernel chosen by shape (Q and R); 3: the same, R only (Q is not written) */
+h2_status h2_test_cholqr(int m, int n, const double* A, double* Q, double* R, int mode);
 /* one-sided Jacobi SVD of A (m x n, m >= n): sigma (n), U (m x n), V (n x n) */
 h2_status h2_test_svd(int m, int n, const double* A, double* sigma, double* U, double* V);
 // The same for `count` matrices in one batched call: matrix i is m[i] x n[i]

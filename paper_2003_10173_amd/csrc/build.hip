@@ -201,7 +201,7 @@ void left_svd_batched(Ctx& c, const std::vector<LsvTask>& tasks) {
       back.push_back({Q, V, tk.U, tk.M, tk.K, tk.K, tk.M, tk.K, tk.M, 0, 0, 1.0, 0.0});
     }
   }
-  qr_batched(c, qrs);
+  qr_auto(c, qrs);
   copy_batched(c, tr);
   svd_batched(c, svs);
   gemm_batched(c, back);
@@ -654,7 +654,7 @@ std::unique_ptr<h2_matrix> build_h2(const h2_tree* t, Sampler& S, const BuildPar
     copy_batched(c, cps);
     // R of a stack with fewer rows than k is min(rows,k) x k: ldr = k keeps the
     // zero rows below it (zeroed above)
-    qr_batched(c, qrs);
+    qr_auto(c, qrs);
     H2_HIP(hipStreamSynchronize(c.s));
     c.stage.reset();
   }

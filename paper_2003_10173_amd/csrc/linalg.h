@@ -113,6 +113,11 @@ void qr_tall_batched(Ctx& c, const std::vector<QRDesc>& d);
 // Gram-Schmidt projections per panel by GEMM, TSQR per panel; P is
 // replaced by Q (m x n) and R (n x n, upper) is written to R
 void qr_blocked(Ctx& c, const std::vector<CholQRDesc>& d);
+// QR of each matrix by the fastest applicable kernel: TSQR for m >= 192 and
+// n <= 96, blocked QR for m >= 192 and n > 96, one workgroup otherwise.  A is
+// overwritten; Q (thin, optional) and R (optional, min(m,n) x n upper) as in
+// QRDesc.
+void qr_auto(Ctx& c, const std::vector<QRDesc>& d);
 // out[i] = max_j || X_i[:, j] || for blocks X_i (rows_i x cols_i, ld_i)
 void colnorm_max_batched(Ctx& c, const std::vector<CopyDesc>& blocks, double* out);
 // zero a column-major block

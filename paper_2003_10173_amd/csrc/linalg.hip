@@ -210,7 +210,31 @@ void gemm_batched(Ctx& c, const std::vector<GemmDesc>& ds) {
 }
 
 // ------------------------------------------------------------------ Householder QR
-constexpr int QR_VCACHE = 8192;  // rows of the current reflector kept in LDS
+constexpr int QR_VCACHE = 8192;
+
+// stream-ordered timing of a section, active only with verbose output
+struct VTimer {
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipStream_t s;
+  explicit VTimer(hipStream_t st) : s(st) {
+    if (!verbose()) return;
+    H2_HIP(hipEventCreate(&e0));
+    H2_HIP(hipEventCreate(&e1));
+    H2_HIP(hipEventRecord(e0, s));
+  }
+  bool on() const { return e0 != nullptr; }
+  float stop() {
+    float ms = 0;
+    H2_HIP(hipEventRecord(e1, s));
+    H2_HIP(hipEventSynchronize(e1));
+    H2_HIP(hipEventElapsedTime(&ms, e0, e1));
+    return ms;
+  }
+  ~VTimer() {
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+  }
+};  // rows of the current reflector kept in LDS
 
 __global__ __launch_bounds__(256) void k_qr(const QRDesc* __restrict__ descs) {
   const QRDesc d = descs[blockIdx.x];
@@ -717,94 +741,178 @@ struct TsqrNode {
   int ldr;
 };
 
-__global__ __launch_bounds__(256) void k_tsqr_node(const TsqrNode* __restrict__ nodes) {
+// One node = Householder QR of a stacked (ra + rb) x w block, rows <= 192,
+// w <= 96, held in registers: wave v owns columns v, v + 16, ... (at most 6),
+// lane l holds rows l, l + 64, l + 128.  Per column j the owner wave forms the
+// reflector and publishes it through LDS (double-buffered), after one barrier
+// every wave applies it to its own columns.  The explicit Q (when requested)
+// is accumulated backwards the same way: Q = H_0 ... H_{w-1} [I; 0].
+constexpr int TS_WAVES = 16, TS_CPW = (TS_W + TS_WAVES - 1) / TS_WAVES, TS_RS = 3;
+static_assert(TS_RS * 64 >= 2 * TS_W && TS_RS * 64 >= 2 * TS_CH - 1, "node rows must fit the lanes");
+
+__global__ __launch_bounds__(1024) void k_tsqr_node(const TsqrNode* __restrict__ nodes) {
   const TsqrNode d = nodes[blockIdx.x];
-  __shared__ double A[TS_LD * TS_W];
-  __shared__ double taus[TS_W];
-  __shared__ double red[8];
-  __shared__ double bc[2];
+  __shared__ double vbuf[2][TS_RS * 64];
+  __shared__ double tbuf[2];
   const int m = d.ra + d.rb, w = d.w;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  for (int e = tid; e < m * w; e += 256) {
-    const int i = e % m, j = e / m;
-    A[j * TS_LD + i] = i < d.ra ? d.a[(size_t)j * d.lda + i] : d.b[(size_t)j * d.ldb + (i - d.ra)];
-  }
-  __syncthreads();
-  const int kmin = min(m, w);
-  for (int j = 0; j < kmin; ++j) {
-    double* aj = A + j * TS_LD;
-    double s = 0;
-    for (int i = j + 1 + tid; i < m; i += 256) s += aj[i] * aj[i];
-    s = block_sum256(s, red);
-    if (tid == 0) {
-      const double alpha = aj[j];
-      double tau = 0, scale = 0;
-      if (s != 0.0) {
-        const double norm = sqrt(alpha * alpha + s);
-        const double beta = alpha >= 0 ? -norm : norm;
-        tau = (beta - alpha) / beta;
-        scale = 1.0 / (alpha - beta);
-        aj[j] = beta;
-      }
-      bc[0] = tau;
-      bc[1] = scale;
-      taus[j] = tau;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  double a[TS_CPW][TS_RS];
+#pragma unroll
+  for (int q = 0; q < TS_CPW; ++q) {
+    const int c = wave + TS_WAVES * q;
+#pragma unroll
+    for (int r = 0; r < TS_RS; ++r) {
+      const int i = r * 64 + lane;
+      double x = 0.0;
+      if (c < w && i < m) x = i < d.ra ? d.a[(size_t)c * d.lda + i] : d.b[(size_t)c * d.ldb + (i - d.ra)];
+      a[q][r] = x;
     }
-    __syncthreads();
-    const double tau = bc[0], scale = bc[1];
-    for (int i = j + 1 + tid; i < m; i += 256) aj[i] *= scale;
-    __syncthreads();
-    if (tau != 0.0) {
-      for (int col = j + 1 + wave; col < w; col += 4) {
-        double* ac = A + col * TS_LD;
-        double t = 0;
-        for (int i = j + lane; i < m; i += 64) t += (i == j ? 1.0 : aj[i]) * ac[i];
-        t = wave_sum(t) * tau;
-        for (int i = j + lane; i < m; i += 64) ac[i] -= (i == j ? 1.0 : aj[i]) * t;
-      }
-    }
-    __syncthreads();
   }
-  for (int e = tid; e < w * w; e += 256) {
-    const int i = e % w, c = e / w;
-    d.R[(size_t)c * d.ldr + i] = (i <= c && i < kmin) ? A[c * TS_LD + i] : 0.0;
-  }
-  __syncthreads();
-  // explicit Q in place (columns j = kmin-1 .. 0): Q_j = H_j Q_{j+1}
-  for (int j = kmin - 1; j >= 0; --j) {
-    const double tau = taus[j];
-    double* aj = A + j * TS_LD;
-    if (j < w - 1 && tau != 0.0) {
-      for (int col = j + 1 + wave; col < w; col += 4) {
-        double* ac = A + col * TS_LD;
-        double t = 0;
-        for (int i = j + lane; i < m; i += 64) t += (i == j ? 1.0 : aj[i]) * (i == j ? 0.0 : ac[i]);
-        t = wave_sum(t) * tau;
-        for (int i = j + lane; i < m; i += 64) {
-          const double cur = i == j ? 0.0 : ac[i];
-          ac[i] = cur - (i == j ? 1.0 : aj[i]) * t;
+  double taus_own[TS_CPW];
+#pragma unroll
+  for (int q = 0; q < TS_CPW; ++q) taus_own[q] = 0.0;
+  // ---- factorisation
+  for (int j = 0; j < w; ++j) {
+    const int owner = j % TS_WAVES, qj = j / TS_WAVES, buf = j & 1;
+    if (wave == owner) {
+#pragma unroll
+      for (int q = 0; q < TS_CPW; ++q) {
+        if (q != qj) continue;
+        double s = 0.0, alpha = 0.0;
+#pragma unroll
+        for (int r = 0; r < TS_RS; ++r) {
+          const int i = r * 64 + lane;
+          if (i > j) s += a[q][r] * a[q][r];
+          if (i == j) alpha = a[q][r];
         }
+        s = wave_sum(s);
+        alpha = __shfl(alpha, j & 63, 64);
+        double tau = 0.0, scale = 0.0, beta = alpha;
+        if (s != 0.0) {
+          const double norm = sqrt(alpha * alpha + s);
+          beta = alpha >= 0 ? -norm : norm;
+          tau = (beta - alpha) / beta;
+          scale = 1.0 / (alpha - beta);
+        }
+#pragma unroll
+        for (int r = 0; r < TS_RS; ++r) {
+          const int i = r * 64 + lane;
+          double v = 0.0;
+          if (i > j) {
+            if (s != 0.0) a[q][r] *= scale;
+            v = a[q][r];
+          } else if (i == j) {
+            a[q][r] = beta;
+            v = 1.0;
+          }
+          vbuf[buf][i] = v;
+        }
+        taus_own[q] = tau;
+        if (lane == 0) tbuf[buf] = tau;
       }
     }
     __syncthreads();
-    for (int i = tid; i < m; i += 256) {
-      if (i < j) aj[i] = 0.0;
-      else if (i == j) aj[i] = 1.0 - tau;
-      else aj[i] = -tau * aj[i];
+    const double tau = tbuf[buf];
+    if (tau == 0.0) continue;
+    double v[TS_RS];
+#pragma unroll
+    for (int r = 0; r < TS_RS; ++r) v[r] = vbuf[buf][r * 64 + lane];
+    double dot[TS_CPW];
+#pragma unroll
+    for (int q = 0; q < TS_CPW; ++q) {
+      double t = 0.0;
+#pragma unroll
+      for (int r = 0; r < TS_RS; ++r) t += v[r] * a[q][r];
+      dot[q] = t;
+    }
+#pragma unroll
+    for (int q = 0; q < TS_CPW; ++q) {
+      const int c = wave + TS_WAVES * q;
+      if (c > j && c < w) {
+        const double t = wave_sum(dot[q]) * tau;
+#pragma unroll
+        for (int r = 0; r < TS_RS; ++r) a[q][r] -= v[r] * t;
+      }
+    }
+  }
+  // R (w x w, upper triangular)
+#pragma unroll
+  for (int q = 0; q < TS_CPW; ++q) {
+    const int c = wave + TS_WAVES * q;
+    if (c >= w) continue;
+    for (int i = lane; i < w; i += 64) {
+      double x = 0.0;
+#pragma unroll
+      for (int r = 0; r < TS_RS; ++r)
+        if (r * 64 + lane == i) x = a[q][r];
+      d.R[(size_t)c * d.ldr + i] = i <= c ? x : 0.0;
+    }
+  }
+  if (!d.Q) return;
+  __syncthreads();  // the last reflector's buffer is reused below
+  // ---- explicit Q, backwards: column j becomes H_j e_j, columns > j get H_j
+  for (int j = w - 1; j >= 0; --j) {
+    const int owner = j % TS_WAVES, qj = j / TS_WAVES, buf = j & 1;
+    if (wave == owner) {
+#pragma unroll
+      for (int q = 0; q < TS_CPW; ++q) {
+        if (q != qj) continue;
+        const double tau = taus_own[q];
+#pragma unroll
+        for (int r = 0; r < TS_RS; ++r) {
+          const int i = r * 64 + lane;
+          double v = 0.0;
+          if (i > j) v = a[q][r];
+          else if (i == j) v = 1.0;
+          vbuf[buf][i] = v;
+          a[q][r] = (i == j ? 1.0 : 0.0) - tau * v;
+        }
+        if (lane == 0) tbuf[buf] = tau;
+      }
     }
     __syncthreads();
+    const double tau = tbuf[buf];
+    if (tau == 0.0) continue;
+    double v[TS_RS];
+#pragma unroll
+    for (int r = 0; r < TS_RS; ++r) v[r] = vbuf[buf][r * 64 + lane];
+    double dot[TS_CPW];
+#pragma unroll
+    for (int q = 0; q < TS_CPW; ++q) {
+      double t = 0.0;
+#pragma unroll
+      for (int r = 0; r < TS_RS; ++r) t += v[r] * a[q][r];
+      dot[q] = t;
+    }
+#pragma unroll
+    for (int q = 0; q < TS_CPW; ++q) {
+      const int c = wave + TS_WAVES * q;
+      if (c > j && c < w) {
+        const double t = wave_sum(dot[q]) * tau;
+#pragma unroll
+        for (int r = 0; r < TS_RS; ++r) a[q][r] -= v[r] * t;
+      }
+    }
   }
-  // columns beyond kmin (only when m < w, not used by callers) stay as factorised
-  for (int e = tid; e < m * w; e += 256) {
-    const int i = e % m, j = e / m;
-    d.Q[(size_t)j * d.ldq + i] = j < kmin ? A[j * TS_LD + i] : 0.0;
+#pragma unroll
+  for (int q = 0; q < TS_CPW; ++q) {
+    const int c = wave + TS_WAVES * q;
+    if (c >= w) continue;
+#pragma unroll
+    for (int r = 0; r < TS_RS; ++r) {
+      const int i = r * 64 + lane;
+      if (i < m) d.Q[(size_t)c * d.ldq + i] = a[q][r];
+    }
   }
 }
 
 static void launch_nodes(Ctx& c, const std::vector<TsqrNode>& v) {
   if (v.empty()) return;
+  for (auto& nd : v)
+    H2_CHECK(nd.w <= TS_W && nd.ra + nd.rb <= TS_RS * 64 && nd.ra + nd.rb >= nd.w, H2_EINVAL,
+             "TSQR node shape out of range");
   auto* dd = (TsqrNode*)c.stage.put(v.data(), v.size() * sizeof(TsqrNode), c.s);
-  k_tsqr_node<<<(unsigned)v.size(), 256, 0, c.s>>>(dd);
+  k_tsqr_node<<<(unsigned)v.size(), 1024, 0, c.s>>>(dd);
   H2_LAUNCH_CHECK();
 }
 
@@ -819,7 +927,8 @@ void qr_tall_batched(Ctx& c, const std::vector<QRDesc>& ds) {
   std::vector<Mat> mats;
   for (auto& d : ds) {
     if (d.m <= 0 || d.n <= 0) continue;
-    H2_CHECK(d.n <= TS_W && d.m >= d.n && d.Q != nullptr, H2_EINVAL, "TSQR: needs n <= 96, m >= n, Q");
+    H2_CHECK(d.n <= TS_W && d.m >= d.n && (d.Q != nullptr || d.R != nullptr), H2_EINVAL,
+             "TSQR: needs n <= 96, m >= n, Q or R");
     Mat M;
     M.d = d;
     const int nch = std::max(1, d.m / TS_CH);
@@ -840,7 +949,7 @@ void qr_tall_batched(Ctx& c, const std::vector<QRDesc>& ds) {
       M.pass.push_back(std::vector<int>(rows.size(), 0));
       int r0 = 0;
       for (size_t i = 0; i < rows.size(); ++i) {
-        double* Q = c.scratch.get((size_t)rows[i] * w);
+        double* Q = M.d.Q ? c.scratch.get((size_t)rows[i] * w) : nullptr;
         double* R = c.scratch.get((size_t)w * w);
         M.Qs[0].push_back(Q);
         M.Rs[0].push_back(R);
@@ -866,7 +975,7 @@ void qr_tall_batched(Ctx& c, const std::vector<QRDesc>& ds) {
       M.pass.push_back(std::vector<int>(cnt, 0));
       for (int i = 0; i < cnt; ++i) {
         if (2 * i + 1 < (int)prevR.size()) {
-          double* Q = c.scratch.get((size_t)2 * w * w);
+          double* Q = M.d.Q ? c.scratch.get((size_t)2 * w * w) : nullptr;
           double* R = c.scratch.get((size_t)w * w);
           M.Qs[lev].push_back(Q);
           M.Rs[lev].push_back(R);
@@ -889,6 +998,9 @@ void qr_tall_batched(Ctx& c, const std::vector<QRDesc>& ds) {
     copy_batched(c, cp);
   }
   // downward: X (w x w) per node, starting from the identity at the root
+  mats.erase(std::remove_if(mats.begin(), mats.end(), [](const Mat& M) { return M.d.Q == nullptr; }),
+             mats.end());
+  if (mats.empty()) return;
   int maxlev = 0;
   for (auto& M : mats) maxlev = std::max(maxlev, (int)M.Rs.size() - 1);
   std::vector<std::vector<std::vector<const double*>>> X(mats.size());
@@ -1000,6 +1112,46 @@ void qr_blocked(Ctx& c, const std::vector<CholQRDesc>& ds) {
     gemm_batched(c, rr);
     gemm_batched(c, rs);
     copy_batched(c, back);
+  }
+}
+
+void qr_auto(Ctx& c, const std::vector<QRDesc>& ds) {
+  std::vector<QRDesc> small, tall;
+  std::vector<CholQRDesc> blocked;
+  std::vector<CopyDesc> toq;
+  for (auto d : ds) {
+    if (d.m <= 0 || d.n <= 0) continue;
+    if (d.m < 2 * TS_CH || d.m < d.n) {
+      small.push_back(d);
+    } else if (d.n <= TS_W) {
+      tall.push_back(d);
+    } else {
+      double* P = d.A;
+      int ld = d.lda;
+      if (d.Q && d.Q != d.A) {
+        toq.push_back({d.A, d.lda, d.Q, d.ldq, d.m, d.n, 1.0, 0.0, 0});
+        P = d.Q;
+        ld = d.ldq;
+      }
+      double* R = d.R;
+      int ldr = d.ldr;
+      if (!R) {
+        R = c.scratch.get((size_t)d.n * d.n);
+        ldr = d.n;
+      }
+      blocked.push_back({P, ld, d.m, d.n, R, ldr});
+    }
+  }
+  VTimer vt(c.s);
+  qr_batched(c, small);
+  qr_tall_batched(c, tall);
+  copy_batched(c, toq);
+  qr_blocked(c, blocked);
+  if (vt.on() && !(small.empty() && tall.empty() && blocked.empty())) {
+    int mm = 0, mn = 0;
+    for (auto& d : ds) { mm = std::max(mm, d.m); mn = std::max(mn, d.n); }
+    std::fprintf(stderr, "    [qr] %zu one-wg, %zu tsqr, %zu blocked; max %d x %d: %.2f ms\n",
+                 small.size(), tall.size(), blocked.size(), mm, mn, vt.stop());
   }
 }
 

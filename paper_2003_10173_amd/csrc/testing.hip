@@ -69,14 +69,23 @@ h2_status h2_test_qr(int m, int n, const double* A, double* Q, double* R) {
   });
 }
 
-h2_status h2_test_cholqr(int m, int n, const double* A, double* Q, double* R, int blocked) {
+h2_status h2_test_cholqr(int m, int n, const double* A, double* Q, double* R, int mode) {
   return guarded_status([&] {
+    H2_CHECK(mode >= 0 && mode <= 3, H2_EINVAL, "mode must be 0..3");
     DevBuf a((size_t)m * n * 8), r((size_t)n * n * 8);
     H2_HIP(hipMemcpy(a.p, A, (size_t)m * n * 8, hipMemcpyHostToDevice));
+    H2_HIP(hipMemset(r.p, 0, (size_t)n * n * 8));
     Ctx ctx;
     std::vector<CholQRDesc> d{{a.as<double>(), m, m, n, r.as<double>(), n}};
-    if (blocked) {
+    if (mode == 1) {
       qr_blocked(ctx, d);
+    } else if (mode >= 2) {
+      DevBuf q((size_t)m * n * 8);
+      std::vector<QRDesc> t{{a.as<double>(), m, m, n, mode == 2 ? q.as<double>() : nullptr, m,
+                             r.as<double>(), n}};
+      qr_auto(ctx, t);
+      H2_HIP(hipDeviceSynchronize());
+      if (mode == 2) H2_HIP(hipMemcpy(a.p, q.p, (size_t)m * n * 8, hipMemcpyDeviceToDevice));
     } else {
       DevBuf q((size_t)m * n * 8);
       std::vector<QRDesc> t{{a.as<double>(), m, m, n, q.as<double>(), m, r.as<double>(), n}};

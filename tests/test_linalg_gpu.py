@@ -127,12 +127,12 @@ def test_jacobi_svd_batch_uneven():
         ov += n * n
 
 
-def cholqr(A, blocked):
+def cholqr(A, mode):
     A = F(A)
     m, n = A.shape
     Q = np.zeros((m, n), order="F")
     R = np.zeros((n, n), order="F")
-    h2.check(L().h2_test_cholqr(m, n, A.ctypes.data, Q.ctypes.data, R.ctypes.data, blocked),
+    h2.check(L().h2_test_cholqr(m, n, A.ctypes.data, Q.ctypes.data, R.ctypes.data, mode),
              "cholqr")
     return Q, R
 
@@ -159,3 +159,21 @@ def test_tall_qr_orthonormal_and_backward_stable(m, n, rank, blocked):
     s1 = np.linalg.svd(A, compute_uv=False)
     s2 = np.linalg.svd(R, compute_uv=False)
     assert np.abs(s1 - s2).max() <= 1e-13 * s1[0]
+
+
+@pytest.mark.parametrize("m,n,rank", [(191, 96, 96), (192, 96, 60), (1700, 88, 88), (3000, 150, 150),
+                                      (900, 130, 40), (150, 140, 140), (400, 7, 7)])
+def test_qr_by_shape_r_only_matches_gram(m, n, rank):
+    """The shape-dispatched QR: R alone satisfies R^T R = A^T A (Gram factor
+    use) and matches the full factorisation's R up to row signs."""
+    g = np.random.default_rng(11 * m + n)
+    U = np.linalg.qr(g.standard_normal((m, rank)))[0]
+    sv = np.logspace(0, -10, rank)
+    A = (U * sv) @ g.standard_normal((rank, n))
+    Q, R = cholqr(A, 2)
+    _, R3 = cholqr(A, 3)
+    nA = np.linalg.norm(A, 2)
+    assert np.linalg.norm(Q @ R - A) <= 1e-13 * np.linalg.norm(A)
+    assert np.allclose(np.triu(R), R) and np.allclose(np.triu(R3), R3)
+    assert np.abs(R3.T @ R3 - A.T @ A).max() <= 1e-13 * nA * nA
+    assert np.abs(np.abs(R3) - np.abs(R)).max() <= 1e-12 * nA
