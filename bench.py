@@ -21,7 +21,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0           # MI355X HBM3E, GB/s
-FP64_PEAK_TFLOPS = 78.6         # MI355X FP64 vector / matrix, TFLOP/s
+FP64_PEAK_TFLOPS = 78.6         # MI355X FP64 vector: 256 CU x 128 flop/clk x 2.4 GHz
+DOMINANT = "k_svd_block"        # largest share of the step's kernel time (rocprofv3)
+PMC_SUMMARY = os.path.join(ROOT, "profiles", "k_svd_block_diffusion64_pmc.md")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2003_10173_amd", "csrc", "linalg.hip")
 
 
 def parse():
@@ -47,6 +50,29 @@ def hip_events_time(fn, reps, stream):
     stop.record(stream)
     stop.synchronize()
     return start.elapsed_time(stop) / reps
+
+
+def source_digest(path):
+    import hashlib
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def traffic_per_launch():
+    """HBM bytes per launch of the dominant kernel from the committed rocprofv3
+    counter summary (FETCH_SIZE and WRITE_SIZE runs, each scaled by the same
+    counter's reading for a plain copy of known size), or None when the summary
+    is missing or the kernel source changed since the counters were taken."""
+    try:
+        with open(PMC_SUMMARY) as f:
+            line = next(l for l in f if l.startswith("traffic: "))
+        t = json.loads(line[len("traffic: "):])
+    except (OSError, StopIteration, ValueError):
+        return None
+    if t.get("kernel") != DOMINANT or t.get("source_digest") != source_digest(KERNEL_SOURCE):
+        return None
+    kib = t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"]
+    return int(kib * 1024)
 
 
 def cpu_baseline(cfg, gpu_iters):
@@ -79,14 +105,18 @@ def cpu_baseline(cfg, gpu_iters):
     t_it = time.perf_counter() - t0
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     try:
-        import numpy.__config__  # noqa: F401
+        from threadpoolctl import threadpool_info
+        blas = [i["num_threads"] for i in threadpool_info() if i.get("user_api") == "blas"]
+        if blas:
+            threads = max(blas)
     except Exception:  # noqa: BLE001
         pass
     est = t_build + t_it * gpu_iters
     return {"value": est, "unit": "s", "cores": threads, "kind": "oracle",
             "sample": "full FP64 oracle build of the diffusion2d Hessian (%.1f s) + one "
                       "Newton-Schulz iteration at the loosest dynamic threshold (%.1f s), "
-                      "extrapolated to %d iterations" % (t_build, t_it, gpu_iters)}
+                      "extrapolated to %d iterations (a lower bound: later iterations "
+                      "build at tighter thresholds)" % (t_build, t_it, gpu_iters)}
 
 
 def main():
@@ -119,9 +149,11 @@ def main():
 
     for i in range(args.warmup):
         _, b0, _, n0 = step()
+        torch.cuda.synchronize()
         print("warmup step %d: build %.1f ms, NS %d iterations %.1f ms" % (
             i, b0["time_ms"][7], n0["iterations"], n0["time_ms"][3]), file=sys.stderr, flush=True)
     torch.cuda.synchronize()
+    h2.timing_enable(True)
     t0 = time.perf_counter()
     for i in range(args.steps):
         A, bst, X, nst = step()
@@ -131,8 +163,19 @@ def main():
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     ms_per_step = 1e3 * elapsed / args.steps
+    # dominant kernel, timed live by HIP events on the stream it ran on
+    launches, k_ms, k_flops = h2.timing_read(DOMINANT)
+    h2.timing_enable(False)
+    k_avg = k_ms / max(launches, 1)
+    k_tflops = k_flops / max(k_ms, 1e-9) / 1e9
+    roofline = {"bound": "alu", "achieved": round(k_tflops, 4), "peak": FP64_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(k_tflops / FP64_PEAK_TFLOPS, 6),
+                "traffic": traffic_per_launch(), "kernel": DOMINANT,
+                "launches": launches, "avg_launch_ms": round(k_avg, 4),
+                "flops_per_launch": k_flops / max(launches, 1),
+                "share_of_step": round(k_ms / elapsed / 1e3, 4)}
 
-    # ---- dominant kernel: HGEMV of the built Hessian (the NS sampler is all HGEMVs)
+    # ---- HGEMV of the built Hessian (the NS sampler is all HGEMVs), all stages
     nv = args.hgemv_nv
     n = tree.n
     x = torch.randn(nv, n, dtype=torch.float64, device="cuda")
@@ -141,13 +184,20 @@ def main():
     ms = hip_events_time(lambda: A.gemv(x, y), args.hgemv_reps, stream)
     alg_bytes = mbytes + 2 * 8 * n * nv
     gbs = alg_bytes / (ms * 1e-3) / 1e9
-    roofline = {"bound": "hbm", "achieved": round(gbs, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(gbs / HBM_PEAK_GBS, 5), "traffic": None,
-                "kernel": "hgemv (all stages, FP64, nv=%d)" % nv,
-                "alg_bytes_per_call": int(alg_bytes), "ms_per_call": round(ms, 5)}
+    hgemv = {"bound": "hbm", "achieved": round(gbs, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+             "frac": round(gbs / HBM_PEAK_GBS, 5), "nv": nv,
+             "alg_bytes_per_call": int(alg_bytes), "ms_per_call": round(ms, 5)}
+    # reference copy of known size (512 MiB each way) for scaling byte counters
+    src = torch.ones(1 << 26, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        h2.stream_copy(src, dst)
+    torch.cuda.synchronize()
+    del src, dst
 
     cpu = None
     if not args.no_cpu_baseline:
+        print("cpu baseline (oracle) ...", file=sys.stderr, flush=True)
         cpu = cpu_baseline(cfg, nst["iterations"])
 
     out = {
@@ -174,6 +224,7 @@ def main():
         "ns_ms": round(nst["time_ms"][3], 2),
         "hgemv_gbs": round(gbs, 2),
         "roofline": roofline,
+        "hgemv": hgemv,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))

@@ -252,6 +252,21 @@ int h2_sampler_h2_apply(void* ctx, int n, int ncols, const double* omega, int ld
                         double* y, int ld_y, hipStream_t stream);
 void h2_sampler_destroy(void* ctx);
 
+/* Launch timing for roofline reporting (no paper counterpart; a measurement
+ * aid).  h2_timing_enable(1) clears the totals and starts bracketing every
+ * launch of the library's timed kernels by HIP events recorded on the stream
+ * the kernel runs on; h2_timing_enable(0) stops.  h2_timing_read waits for
+ * the recorded launches of `kernel` (its name without namespace, e.g.
+ * "k_svd_block") and returns their number, summed duration (ms) and summed
+ * algorithmic work (flops for the Jacobi SVD: sweeps * n(n-1)/2 * (12m + 6n)
+ * per m x n matrix).  Unknown names read as zero launches. */
+h2_status h2_timing_enable(int on);
+h2_status h2_timing_read(const char* kernel, int64_t* launches, double* total_ms, double* work);
+/* dst[0:n] = src[0:n] (device FP64 arrays) by a plain grid-stride kernel
+ * (k_stream_copy): the reference transfer of known size used to scale
+ * hardware byte counters */
+h2_status h2_stream_copy(const double* src, double* dst, int64_t n, hipStream_t stream);
+
 const char* h2_status_string(h2_status s);
 /* last error message of this thread (for diagnostics) */
 const char* h2_last_error(void);

@@ -368,3 +368,29 @@ def residual_norm(A, X, rel=1e-2, max_iter=30, seed=1, iteration=0, stream=None)
     check(lib().h2_residual_norm(A.handle, X.handle, rel, max_iter, seed, iteration,
                                  _stream(stream), C.byref(out)), "h2_residual_norm")
     return out.value
+
+
+def timing_enable(on=True):
+    """Start (clearing totals) or stop bracketing the library's timed kernel
+    launches with HIP events on their own streams."""
+    check(lib().h2_timing_enable(1 if on else 0), "h2_timing_enable")
+
+
+def timing_read(kernel):
+    """(launches, total ms, algorithmic work) of a timed kernel since enable."""
+    n = C.c_int64()
+    ms = C.c_double()
+    w = C.c_double()
+    check(lib().h2_timing_read(kernel.encode(), C.byref(n), C.byref(ms), C.byref(w)),
+          "h2_timing_read")
+    return n.value, ms.value, w.value
+
+
+def stream_copy(src, dst):
+    """dst[:] = src[:] for contiguous CUDA float64 tensors by the library's
+    plain copy kernel, on torch's current stream."""
+    import torch
+    assert src.dtype == torch.float64 and dst.dtype == torch.float64
+    assert src.is_contiguous() and dst.is_contiguous() and src.numel() == dst.numel()
+    s = torch.cuda.current_stream().cuda_stream
+    check(lib().h2_stream_copy(src.data_ptr(), dst.data_ptr(), src.numel(), s), "h2_stream_copy")

@@ -75,6 +75,9 @@ SIGNATURES = {
     "h2_matrix_export": (C.c_int, [vp, vp, vp, vp, vp]),
     "h2_matrix_words": (C.c_int, [vp, P(i64), P(i64)]),
     "h2_ns_opts_default": (None, [P(H2NSOpts)]),
+    "h2_timing_enable": (C.c_int, [C.c_int]),
+    "h2_stream_copy": (C.c_int, [vp, vp, i64, vp]),
+    "h2_timing_read": (C.c_int, [C.c_char_p, P(i64), P(dbl), P(dbl)]),
     "h2_newton_schulz": (C.c_int, [vp, P(H2NSOpts), vp, P(vp), P(H2NSStats)]),
     "h2_residual_norm": (C.c_int, [vp, vp, dbl, C.c_int, u64, u32, vp, P(dbl)]),
     "h2_sampler_kernel_create": (C.c_int, [vp, C.c_int, C.c_int, dbl, dbl, P(vp)]),

@@ -27,6 +27,7 @@ SOURCES = [
     "samplers.hip",
     "mlp.hip",
     "testing.hip",
+    "timing.hip",
 ]
 
 # host geometry code is compiled without contraction so that admissibility

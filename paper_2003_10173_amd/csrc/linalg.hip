@@ -15,6 +15,7 @@
 
 #include "kernels_common.h"
 #include "linalg.h"
+#include "timing.h"
 
 namespace h2 {
 
@@ -700,8 +701,15 @@ void svd_batched(Ctx& c, const std::vector<SVDDesc>& ds) {
         H2_HIP(hipEventCreate(&e1));
         H2_HIP(hipEventRecord(e0, c.s));
       }
+      double per_sweep = 0;
+      for (int j = 0; j < nm; ++j) {
+        const double n = big[i0 + j].n, m = big[i0 + j].m;
+        per_sweep += 0.5 * n * (n - 1) * (12.0 * m + 6.0 * n);
+      }
+      const int tok = timing_begin(c.s);
       H2_HIP(hipLaunchCooperativeKernel((const void*)k_svd_block, dim3(start[nm]), dim3(512), args,
                                         0, c.s));
+      timing_end(tok, "k_svd_block", c.s, 0.0, sweeps, per_sweep);
       if (verbose()) {
         H2_HIP(hipEventRecord(e1, c.s));
         H2_HIP(hipEventSynchronize(e1));
