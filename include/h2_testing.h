@@ -31,6 +31,10 @@ h2_status h2_test_svd(int m, int n, const double* A, double* sigma, double* U, d
 // (m[i] >= n[i]); A and U are the column-major matrices stored one after the
 // other, sigma the n[i] values one after the other, V the n[i] x n[i] factors
 // one after the other.
+/* raw accumulator of one 16x16 matrix-core product (kind 0: f64 16x16x4,
+   1: f32 16x16x4, 2: bf16 16x16x16) of known operands; out[lane*4 + reg]
+   (256 values) -- pins the operand and result lane layouts the kernels use */
+h2_status h2_test_mfma_layout(int kind, double* out);
 h2_status h2_test_svd_batch(int count, const int* m, const int* n, const double* A, double* sigma,
                             double* U, double* V);
 /* keep the weak factors of subsequent h2_build calls on this thread (1) or not (0) */

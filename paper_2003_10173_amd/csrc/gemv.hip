@@ -12,6 +12,7 @@
 //   multivectors: tree order, column-major (ld >= n)
 #include <algorithm>
 #include <cstring>
+#include <type_traits>
 
 #include "internal.h"
 #include "kernels_common.h"
@@ -234,6 +235,254 @@ __global__ __launch_bounds__(256) void k_leaf_out(
   }
 }
 
+// Matrix-core version of the leaf stage for FP64 x FP64, FP32 x FP32 and
+// BF16 x FP32 (BF16 operands, FP32 accumulation): y_leaf = alpha (U_t y^_t +
+// sum_near D_ts x_s) + beta y_leaf as a block-sparse product.  One workgroup
+// per (leaf, 16*NT vectors); wave w owns rows 16w..16w+15 and NT 16x16 output
+// tiles.  Each source block (a near D_ts with x_s, or U_t with y^_t) is staged
+// in LDS with coalesced loads (A row-major, zero-padded in k), then consumed
+// by 16x16xK MFMAs: K = 4 for f64 and f32, 16 for bf16.
+typedef double mf_d4 __attribute__((ext_vector_type(4)));
+typedef float mf_f4 __attribute__((ext_vector_type(4)));
+typedef short mf_s4 __attribute__((ext_vector_type(4)));
+
+template <class M> struct MfmaTraits;
+template <> struct MfmaTraits<double> {
+  using SA = double; using SB = double; using Acc = mf_d4;
+  static constexpr int KS = 4, ALD = 64 + 2, PADB = 2;
+};
+template <> struct MfmaTraits<float> {
+  using SA = float; using SB = float; using Acc = mf_f4;
+  static constexpr int KS = 4, ALD = 64 + 4, PADB = 4;
+};
+template <> struct MfmaTraits<bf16_t> {
+  using SA = uint16_t; using SB = uint16_t; using Acc = mf_f4;
+  static constexpr int KS = 16, ALD = 64 + 8, PADB = 8;
+};
+
+__device__ inline double mf_a(double x) { return x; }
+__device__ inline float mf_a(float x) { return x; }
+__device__ inline uint16_t mf_a(bf16_t x) { return x.bits; }
+template <class SB, class V> __device__ inline SB mf_b(V x);
+template <> __device__ inline double mf_b<double, double>(double x) { return x; }
+template <> __device__ inline float mf_b<float, float>(float x) { return x; }
+template <> __device__ inline uint16_t mf_b<uint16_t, float>(float x) { return float_to_bf16(x).bits; }
+
+// Block-row product on matrix cores: out (rows x nvc) = sum over sources q of
+// A_q (rows x K_q) B_q (K_q x nvc); A_q row-major (or, transA, the transpose
+// of a row-major K_q x rows block), B_q column-major with leading dimension
+// ldb_q.  The workgroup's 4 waves own 16 rows each (rows <= 64), NT 16-column
+// output tiles each; the result stays in acc (register layout as described
+// at the epilogues).
+template <class M, class V, int NT, class Src>
+__device__ inline void blockrow_mfma(int rows, int nsrc, const Src& src, int nvc,
+                                     typename MfmaTraits<M>::Acc (&acc)[NT],
+                                     typename MfmaTraits<M>::SA* As,
+                                     typename MfmaTraits<M>::SB* Bs) {
+  using T = MfmaTraits<M>;
+  using SA = typename T::SA;
+  using SB = typename T::SB;
+  constexpr bool BF = T::KS == 16;
+  constexpr int NC = 16 * NT;
+  constexpr int ALD = T::ALD;
+  constexpr int BLD = BF ? 64 + T::PADB : NC + T::PADB;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+#pragma unroll
+  for (int ct = 0; ct < NT; ++ct)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) acc[ct][r] = 0;
+  for (int q = 0; q < nsrc; ++q) {
+    const M* Ap;
+    const V* Bp;
+    int K, ldb;
+    bool transA;
+    src(q, Ap, K, transA, Bp, ldb);
+    if (K == 0) continue;
+    const int KP = (K + T::KS - 1) / T::KS * T::KS;
+    if (transA) {
+      for (int e = tid; e < K * rows; e += 256) {
+        const int kk = e / rows, r = e - kk * rows;
+        As[r * ALD + kk] = mf_a(Ap[e]);
+      }
+      for (int e = tid; e < rows * (KP - K); e += 256) {
+        const int r = e / (KP - K), kk = K + e - r * (KP - K);
+        As[r * ALD + kk] = SA(0);
+      }
+    } else {
+      for (int e = tid; e < rows * KP; e += 256) {
+        const int r = e / KP, kk = e - r * KP;
+        As[r * ALD + kk] = kk < K ? mf_a(Ap[(size_t)r * K + kk]) : SA(0);
+      }
+    }
+    for (int e = tid; e < KP * NC; e += 256) {
+      const int v = e / KP, kk = e - v * KP;
+      const SB val = (kk < K && v < nvc) ? mf_b<SB, V>(Bp[(size_t)v * ldb + kk]) : SB(0);
+      if (BF) Bs[v * BLD + kk] = val;
+      else Bs[kk * BLD + v] = val;
+    }
+    __syncthreads();
+    if (16 * wave < rows) {
+      const int ar = (16 * wave + (lane & 15)) * ALD;
+      for (int k0 = 0; k0 < KP; k0 += T::KS) {
+        if constexpr (BF) {
+          const mf_s4 a = *reinterpret_cast<const mf_s4*>(&As[ar + k0 + 4 * (lane >> 4)]);
+#pragma unroll
+          for (int ct = 0; ct < NT; ++ct) {
+            const mf_s4 b = *reinterpret_cast<const mf_s4*>(
+                &Bs[(ct * 16 + (lane & 15)) * BLD + k0 + 4 * (lane >> 4)]);
+            acc[ct] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[ct], 0, 0, 0);
+          }
+        } else {
+          const SA a = As[ar + k0 + (lane >> 4)];
+#pragma unroll
+          for (int ct = 0; ct < NT; ++ct) {
+            const SB b = Bs[(k0 + (lane >> 4)) * BLD + ct * 16 + (lane & 15)];
+            if constexpr (sizeof(SA) == 8)
+              acc[ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[ct], 0, 0, 0);
+            else
+              acc[ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[ct], 0, 0, 0);
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// row of output tile element held in register r: column lane % 16, row
+// 4 (lane / 16) + r for the f32 products, 4 r + lane / 16 for the f64 product
+template <class M>
+__device__ inline int mf_row(int r, int lane) {
+  return sizeof(typename MfmaTraits<M>::SA) == 8 ? 4 * r + (lane >> 4) : 4 * (lane >> 4) + r;
+}
+
+#define MF_SHARED(M, NT)                                                                    \
+  using T_ = MfmaTraits<M>;                                                                 \
+  constexpr int NC_ = 16 * (NT);                                                            \
+  constexpr int BLD_ = T_::KS == 16 ? 64 + T_::PADB : NC_ + T_::PADB;                       \
+  __shared__ __align__(16) typename T_::SA As[LEAF_MAX * T_::ALD];                          \
+  __shared__ __align__(16) typename T_::SB Bs[T_::KS == 16 ? NC_ * BLD_ : LEAF_MAX * BLD_]; \
+  typename T_::Acc acc[NT];
+
+// leaf stage: y_t = alpha (U_t y^_t + sum_near D_ts x_s) + beta y_t
+template <class M, class V, int NT>
+__global__ __launch_bounds__(256) void k_leaf_mfma(
+    int L, const int32_t* __restrict__ cstart, const int32_t* __restrict__ csize,
+    const int32_t* __restrict__ rank, const int64_t* __restrict__ kpre,
+    const int64_t* __restrict__ Uoff, const M* __restrict__ U,
+    const int32_t* __restrict__ near_ptr, const int32_t* __restrict__ near_col,
+    const int64_t* __restrict__ Doff, const M* __restrict__ D, int nv, const V* __restrict__ yh,
+    const V* __restrict__ x, int ldx, V alpha, V beta, V* __restrict__ y, int ldy) {
+  MF_SHARED(M, NT)
+  const int i = blockIdx.x;
+  const int leaf_base = (1 << L) - 1;
+  const int c = leaf_base + i;
+  const int r0 = cstart[c], m = csize[c];
+  const int v0 = blockIdx.y * NC_;
+  const int nvc = min(NC_, nv - v0);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int k = rank[c];
+  const int g0 = near_ptr[i], nnear = near_ptr[i + 1] - g0;
+  auto src = [&](int q, const M*& Ap, int& K, bool& tA, const V*& Bp, int& ldb) {
+    tA = false;
+    if (q < nnear) {
+      const int g = g0 + q;
+      const int sc = leaf_base + near_col[g];
+      Ap = D + Doff[g];
+      K = csize[sc];
+      Bp = x + (size_t)v0 * ldx + cstart[sc];
+      ldb = ldx;
+    } else {
+      Ap = U + Uoff[i];
+      K = k;
+      Bp = yh + kpre[c] * nv + (size_t)v0 * k;
+      ldb = k;
+    }
+  };
+  blockrow_mfma<M, V, NT>(m, nnear + (k > 0 ? 1 : 0), src, nvc, acc, As, Bs);
+#pragma unroll
+  for (int ct = 0; ct < NT; ++ct)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = 16 * wave + mf_row<M>(r, lane), col = ct * 16 + (lane & 15);
+      if (row < m && col < nvc) {
+        V* yp = y + (size_t)(v0 + col) * ldy + r0 + row;
+        const V val = alpha * (V)acc[ct][r];
+        *yp = beta == V(0) ? val : val + beta * *yp;
+      }
+    }
+}
+
+// upsweep at the leaves: x^_t = U_t^T x_t (k_t x nv)
+template <class M, class V, int NT>
+__global__ __launch_bounds__(256) void k_up_leaf_mfma(
+    int L, const int32_t* __restrict__ cstart, const int32_t* __restrict__ csize,
+    const int32_t* __restrict__ rank, const int64_t* __restrict__ kpre,
+    const int64_t* __restrict__ Uoff, const M* __restrict__ U, const V* __restrict__ x, int ldx,
+    int nv, V* __restrict__ xh) {
+  MF_SHARED(M, NT)
+  const int i = blockIdx.x;
+  const int c = (1 << L) - 1 + i;
+  const int k = rank[c];
+  if (k == 0) return;
+  const int v0 = blockIdx.y * NC_;
+  const int nvc = min(NC_, nv - v0);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  auto src = [&](int, const M*& Ap, int& K, bool& tA, const V*& Bp, int& ldb) {
+    Ap = U + Uoff[i];
+    K = csize[c];
+    tA = true;
+    Bp = x + (size_t)v0 * ldx + cstart[c];
+    ldb = ldx;
+  };
+  blockrow_mfma<M, V, NT>(k, 1, src, nvc, acc, As, Bs);
+  V* out = xh + kpre[c] * nv;
+#pragma unroll
+  for (int ct = 0; ct < NT; ++ct)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = 16 * wave + mf_row<M>(r, lane), col = ct * 16 + (lane & 15);
+      if (row < k && col < nvc) out[(size_t)(v0 + col) * k + row] = (V)acc[ct][r];
+    }
+}
+
+// couplings: y^_t = sum_{s in far(t)} S_ts x^_s for every non-root cluster
+template <class M, class V, int NT>
+__global__ __launch_bounds__(256) void k_coupling_mfma(
+    const int32_t* __restrict__ rank, const int64_t* __restrict__ kpre,
+    const int32_t* __restrict__ far_ptr, const int32_t* __restrict__ far_col,
+    const int64_t* __restrict__ Soff, const M* __restrict__ S, int nv, const V* __restrict__ xh,
+    V* __restrict__ yh) {
+  MF_SHARED(M, NT)
+  const int c = blockIdx.x + 1;
+  const int kt = rank[c];
+  if (kt == 0) return;
+  const int l = 31 - __clz(c + 1);
+  const int base = (1 << l) - 1;
+  const int pb = far_ptr[c + l], pe = far_ptr[c + l + 1];
+  const int v0 = blockIdx.y * NC_;
+  const int nvc = min(NC_, nv - v0);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  auto src = [&](int q, const M*& Ap, int& K, bool& tA, const V*& Bp, int& ldb) {
+    const int g = pb + q;
+    const int cs = base + far_col[g];
+    tA = false;
+    K = rank[cs];
+    Ap = S + Soff[g];
+    Bp = xh + kpre[cs] * nv + (size_t)v0 * K;
+    ldb = K;
+  };
+  blockrow_mfma<M, V, NT>(kt, pe - pb, src, nvc, acc, As, Bs);
+  V* out = yh + kpre[c] * nv;
+#pragma unroll
+  for (int ct = 0; ct < NT; ++ct)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = 16 * wave + mf_row<M>(r, lane), col = ct * 16 + (lane & 15);
+      if (row < kt && col < nvc) out[(size_t)(v0 + col) * kt + row] = (V)acc[ct][r];
+    }
+}
+
 template <class V>
 __global__ void k_gather(int n, int nv, const int32_t* __restrict__ perm, const V* __restrict__ x,
                          int ldx, V* __restrict__ xt, int ldt) {
@@ -256,6 +505,13 @@ __global__ void k_scatter(int n, int nv, const int32_t* __restrict__ perm, V alp
 
 // ------------------------------------------------------------------ drivers
 template <class M, class V>
+static constexpr bool has_mfma() {
+  return (std::is_same<M, double>::value && std::is_same<V, double>::value) ||
+         (std::is_same<M, float>::value && std::is_same<V, float>::value) ||
+         (std::is_same<M, bf16_t>::value && std::is_same<V, float>::value);
+}
+
+template <class M, class V>
 static void gemv_tree_impl(const h2_matrix* A, int nv, V alpha, const V* xt, int ldx, V beta,
                            V* yt, int ldy, hipStream_t s) {
   const h2_tree* t = A->tree;
@@ -271,25 +527,70 @@ static void gemv_tree_impl(const h2_matrix* A, int nv, V alpha, const V* xt, int
   const M* D = A->st.D.as<M>();
   const int32_t* rank = A->d_rank.as<int32_t>();
   const int64_t* kpre = A->d_kpre.as<int64_t>();
+  const int32_t* cstart = t->d_cstart.as<int32_t>();
+  const int32_t* csize = t->d_csize.as<int32_t>();
+  // matrix cores for the dense contractions when every block fits the 64 x 64 tiles
+  // (leaves are at most 64 points; ranks above 64 take the scalar kernels)
+  const bool mf = has_mfma<M, V>() && A->kmax <= LEAF_MAX;
+  const bool wide = nv > 32;
+  const unsigned gy = wide ? (unsigned)((nv + 63) / 64) : (unsigned)((nv + 31) / 32);
   if (ktot > 0 && L >= 1) {
-    k_up_leaf<M, V><<<1 << L, 256, 0, s>>>(L, t->d_cstart.as<int32_t>(), t->d_csize.as<int32_t>(),
-                                            rank, kpre, A->d_U_off.as<int64_t>(), U, xt, ldx, nv,
-                                            xh);
+    if constexpr (has_mfma<M, V>()) {
+      if (mf) {
+        if (wide)
+          k_up_leaf_mfma<M, V, 4><<<dim3(1 << L, gy), 256, 0, s>>>(
+              L, cstart, csize, rank, kpre, A->d_U_off.as<int64_t>(), U, xt, ldx, nv, xh);
+        else
+          k_up_leaf_mfma<M, V, 2><<<dim3(1 << L, gy), 256, 0, s>>>(
+              L, cstart, csize, rank, kpre, A->d_U_off.as<int64_t>(), U, xt, ldx, nv, xh);
+      }
+    }
+    if (!mf)
+      k_up_leaf<M, V><<<1 << L, 256, 0, s>>>(L, cstart, csize, rank, kpre,
+                                              A->d_U_off.as<int64_t>(), U, xt, ldx, nv, xh);
     for (int l = L - 1; l >= 1; --l)
       k_up_transfer<M, V><<<1 << l, 256, 0, s>>>(l, rank, kpre, A->d_E_off.as<int64_t>(), E, nv,
                                                   xh);
-    k_coupling<M, V><<<t->nclusters() - 1, 256, 0, s>>>(
-        rank, kpre, t->d_far_ptr.as<int32_t>(), t->d_far_col.as<int32_t>(),
-        A->d_S_off.as<int64_t>(), S, nv, xh, yh);
+    const int32_t* fp = t->d_far_ptr.as<int32_t>();
+    const int32_t* fc = t->d_far_col.as<int32_t>();
+    const int64_t* so = A->d_S_off.as<int64_t>();
+    if constexpr (has_mfma<M, V>()) {
+      if (mf) {
+        if (wide)
+          k_coupling_mfma<M, V, 4><<<dim3(t->nclusters() - 1, gy), 256, 0, s>>>(
+              rank, kpre, fp, fc, so, S, nv, xh, yh);
+        else
+          k_coupling_mfma<M, V, 2><<<dim3(t->nclusters() - 1, gy), 256, 0, s>>>(
+              rank, kpre, fp, fc, so, S, nv, xh, yh);
+      }
+    }
+    if (!mf)
+      k_coupling<M, V><<<t->nclusters() - 1, 256, 0, s>>>(rank, kpre, fp, fc, so, S, nv, xh, yh);
     for (int l = 2; l <= L; ++l)
       k_down_transfer<M, V><<<1 << l, 256, 0, s>>>(l, rank, kpre, A->d_E_off.as<int64_t>(), E, nv,
                                                     yh);
   }
-  dim3 grid(1 << L, (nv + NVC - 1) / NVC);
-  k_leaf_out<M, V><<<grid, 256, 0, s>>>(
-      L, t->d_cstart.as<int32_t>(), t->d_csize.as<int32_t>(), rank, kpre,
-      A->d_U_off.as<int64_t>(), U, t->d_near_ptr.as<int32_t>(), t->d_near_col.as<int32_t>(),
-      A->d_D_off.as<int64_t>(), D, nv, yh, xt, ldx, alpha, beta, yt, ldy);
+  const int32_t* np_ = t->d_near_ptr.as<int32_t>();
+  const int32_t* nc_ = t->d_near_col.as<int32_t>();
+  const int64_t* doff = A->d_D_off.as<int64_t>();
+  const int64_t* uoff = A->d_U_off.as<int64_t>();
+  if constexpr (has_mfma<M, V>()) {
+    if (mf) {
+      if (wide)
+        k_leaf_mfma<M, V, 4><<<dim3(1 << L, gy), 256, 0, s>>>(
+            L, cstart, csize, rank, kpre, uoff, U, np_, nc_, doff, D, nv, yh, xt, ldx, alpha, beta,
+            yt, ldy);
+      else
+        k_leaf_mfma<M, V, 2><<<dim3(1 << L, gy), 256, 0, s>>>(
+            L, cstart, csize, rank, kpre, uoff, U, np_, nc_, doff, D, nv, yh, xt, ldx, alpha, beta,
+            yt, ldy);
+    }
+  }
+  if (!mf) {
+    dim3 grid(1 << L, (nv + NVC - 1) / NVC);
+    k_leaf_out<M, V><<<grid, 256, 0, s>>>(L, cstart, csize, rank, kpre, uoff, U, np_, nc_, doff, D,
+                                          nv, yh, xt, ldx, alpha, beta, yt, ldy);
+  }
   H2_LAUNCH_CHECK();
 }
 

@@ -5,6 +5,7 @@
 
 #include "h2_testing.h"
 #include "internal.h"
+#include "kernels_common.h"
 #include "linalg.h"
 
 namespace h2 {
@@ -33,6 +34,39 @@ void reset_factors() {
   g_factor_ranks.clear();
   g_factor_K.clear();
 }
+// one 16x16 MFMA per kind (0: f64 16x16x4, 1: f32 16x16x4, 2: bf16 16x16x16)
+// with A[i][0] = i + 1, A[i][1] = 1, B[0][j] = 1, B[1][j] = 32 (j + 1) (exact in
+// bf16), every
+// other k zero, operands placed as A[i][k] in lane i + 16 (k / kpl), element
+// k % kpl, and B[k][j] in lane j + 16 (k / kpl), element k % kpl (kpl = k
+// values per lane); out[lane * 4 + reg] = raw accumulator register.
+typedef double t_d4 __attribute__((ext_vector_type(4)));
+typedef float t_f4 __attribute__((ext_vector_type(4)));
+typedef short t_s4 __attribute__((ext_vector_type(4)));
+__global__ void k_mfma_probe(int kind, double* out) {
+  const int l = threadIdx.x, i = l & 15, kg = l >> 4;
+  auto aval = [&](int k) { return k == 0 ? (double)(i + 1) : (k == 1 ? 1.0 : 0.0); };
+  auto bval = [&](int k) { return k == 0 ? 1.0 : (k == 1 ? 32.0 * (i + 1) : 0.0); };
+  if (kind == 0) {
+    t_d4 c = {0, 0, 0, 0};
+    c = __builtin_amdgcn_mfma_f64_16x16x4f64(aval(kg), bval(kg), c, 0, 0, 0);
+    for (int r = 0; r < 4; ++r) out[l * 4 + r] = c[r];
+  } else if (kind == 1) {
+    t_f4 c = {0, 0, 0, 0};
+    c = __builtin_amdgcn_mfma_f32_16x16x4f32((float)aval(kg), (float)bval(kg), c, 0, 0, 0);
+    for (int r = 0; r < 4; ++r) out[l * 4 + r] = c[r];
+  } else {
+    t_s4 a, b;
+    for (int e = 0; e < 4; ++e) {
+      a[e] = (short)float_to_bf16((float)aval(4 * kg + e)).bits;
+      b[e] = (short)float_to_bf16((float)bval(4 * kg + e)).bits;
+    }
+    t_f4 c = {0, 0, 0, 0};
+    c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+    for (int r = 0; r < 4; ++r) out[l * 4 + r] = c[r];
+  }
+}
+
 }  // namespace h2
 
 using namespace h2;
@@ -141,6 +175,17 @@ h2_status h2_test_svd_batch(int count, const int* m, const int* n, const double*
     H2_HIP(hipMemcpy(sigma, s.p, ns * 8, hipMemcpyDeviceToHost));
     H2_HIP(hipMemcpy(U, u.p, na * 8, hipMemcpyDeviceToHost));
     H2_HIP(hipMemcpy(V, v.p, nv * 8, hipMemcpyDeviceToHost));
+  });
+}
+
+h2_status h2_test_mfma_layout(int kind, double* out) {
+  return guarded_status([&] {
+    H2_CHECK(kind >= 0 && kind <= 2 && out, H2_EINVAL, "kind 0..2 and out needed");
+    DevBuf o(256 * 8);
+    k_mfma_probe<<<1, 64>>>(kind, o.as<double>());
+    H2_LAUNCH_CHECK();
+    H2_HIP(hipDeviceSynchronize());
+    H2_HIP(hipMemcpy(out, o.p, 256 * 8, hipMemcpyDeviceToHost));
   });
 }
 

@@ -107,3 +107,29 @@ def test_hgemv_reduced_precision_storage(kernel1d):
         y = Gp.gemv(xf)
         torch.cuda.synchronize()
         assert rel_err(y.cpu().numpy().T, want) <= tol, prec
+
+
+@pytest.mark.parametrize("nv", [5, 33, 70])
+def test_hgemv_reduced_precision_ragged_random(nv):
+    """FP32 (FP32 matrix cores) and BF16 (BF16 operands, FP32 accumulation)
+    on a random 2D H2 with ragged leaves of up to 64 and several vector
+    tiles.  Bounds from the arithmetic: FP32 storage and products carry
+    2^-24 relative rounding per term (sums of ~1.7k terms: 1e-5 relative);
+    BF16 rounds both operands to 2^-9 relative, so each product is off by at
+    most 2^-8 relative, 2e-2 on the result after cancellation in a
+    random-sign sum."""
+    pts = np.random.Generator(np.random.PCG64(99)).uniform(size=(2500, 2))
+    T = OTree(pts, 64, 0.7)
+    H = _random_h2(T, 10, 4)
+    gt = h2.Tree(pts, 64, 0.7)
+    G = h2.H2Matrix.from_host(gt, *oracle_to_packed(H))
+    x = si.gaussian_vectors(T.n, nv, 8)
+    want = H.matvec(x)
+    xf = torch.tensor(x.T.copy(), device="cuda", dtype=torch.float32)
+    for prec, tol in ((h2.H2_FP32, 1e-5), (h2.H2_BF16, 2e-2)):
+        y = G.convert(prec).gemv(xf)
+        torch.cuda.synchronize()
+        err = rel_err(y.cpu().numpy().T, want)
+        assert err <= tol, (prec, err)
+        if prec == h2.H2_BF16:
+            assert err >= 1e-5   # the BF16 path really rounds its operands
