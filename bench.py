@@ -36,6 +36,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--hgemv-nv", type=int, default=34)
     ap.add_argument("--hgemv-reps", type=int, default=50)
+    ap.add_argument("--no-forms", action="store_true",
+                    help="skip the mixed-precision form and the 256x256 precision ladder")
     return ap.parse_args()
 
 
@@ -73,6 +75,43 @@ def traffic_per_launch():
         return None
     kib = t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"]
     return int(kib * 1024)
+
+
+def precision_ladder(h2, torch, si, stream, reps=20):
+    """HGEMV of the 2D kernel Hessian on a 256 x 256 grid (N = 65536, leaf 64,
+    rank cap 32, built by peeling at 1e-4) on 64 vectors in FP64, FP32 and
+    BF16 storage (FP32 accumulation); errors against the FP64 product."""
+    cfg = si.config_kernel2d(256)
+    tree = h2.Tree(cfg["points"], cfg["leaf"], cfg["eta"])
+    S = h2.KernelSampler(cfg["points"], cfg["ell"], cfg["shift"])
+    o = h2.opts(rank_cap=cfg["cap"], oversample=cfg["p"], tol=cfg["tol"], adaptive=1,
+                max_rounds=16, seed=cfg["seed"])
+    t0 = time.perf_counter()
+    A, st = h2.build(tree, S, o)
+    torch.cuda.synchronize()
+    t_build = time.perf_counter() - t0
+    n, nv = tree.n, cfg["nv"]
+    x = torch.tensor(si.gaussian_vectors(n, nv, cfg["vec_seed"]).T.copy(), device="cuda")
+    y64 = A.gemv(x)
+    out = {"workload": "kernel2d 256x256 (N=65536), leaf 64, cap 32, eps 1e-4, nv=64",
+           "build_s": round(t_build, 3), "applies": st["applies"]}
+    forms = [("fp64", A, x, y64, 16)]
+    xf = x.float()
+    for prec, name in ((h2.H2_FP32, "fp32"), (h2.H2_BF16, "bf16")):
+        B = A.convert(prec)
+        forms.append((name, B, xf, B.gemv(xf), 8))
+    for name, M, xv, yv, vb in forms:
+        _, mbytes = M.words()
+        M.gemv(xv, yv)
+        ms = hip_events_time(lambda: M.gemv(xv, yv), reps, stream)
+        alg = mbytes + 2 * vb * n * nv
+        gbs = alg / (ms * 1e-3) / 1e9
+        err = float(torch.linalg.norm(yv.double() - y64) / torch.linalg.norm(y64))
+        out[name] = {"ms": round(ms, 4), "GB/s": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4),
+                     "alg_bytes": int(alg), "rel_err_vs_fp64": err}
+        print("precision %s: %.3f ms, %.0f GB/s, err %.2e" % (name, ms, gbs, err),
+              file=sys.stderr, flush=True)
+    return out
 
 
 def cpu_baseline(cfg, gpu_iters):
@@ -195,6 +234,27 @@ def main():
     torch.cuda.synchronize()
     del src, dst
 
+    forms = None
+    if not args.no_forms:
+        # mixed precision on the same workload: FP32 sampling, FP64 residual + refinement
+        mopts = h2.ns_opts(eps=1e-4, max_iter=60, x0=0, dynamic=1, rank_cap=0,
+                           oversample=cfg["p"], adaptive=1, max_rounds=16, seed=cfg["seed"],
+                           prec=h2.H2_FP32)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        Am, bm = h2.build(tree, sampler, bopts)
+        Xm, nm = h2.newton_schulz(Am, mopts)
+        torch.cuda.synchronize()
+        t_mixed = time.perf_counter() - t1
+        print("mixed step: %.1f ms, %d iterations (%d FP32), residual %.2e" % (
+            1e3 * t_mixed, nm["iterations"], nm["low_iterations"], nm["resid"][-1]),
+            file=sys.stderr, flush=True)
+        forms = {"plain_fp64_s": round(ms_per_step / 1e3, 4),
+                 "mixed_fp32_s": round(t_mixed, 4),
+                 "mixed_iterations": nm["iterations"], "mixed_fp32_iterations": nm["low_iterations"],
+                 "mixed_residual": nm["resid"][-1],
+                 "precision_ladder": precision_ladder(h2, torch, si, stream)}
+
     cpu = None
     if not args.no_cpu_baseline:
         print("cpu baseline (oracle) ...", file=sys.stderr, flush=True)
@@ -225,6 +285,7 @@ def main():
         "hgemv_gbs": round(gbs, 2),
         "roofline": roofline,
         "hgemv": hgemv,
+        "forms": forms,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))

@@ -188,7 +188,13 @@ typedef struct {
   int adaptive;
   int max_rounds;
   uint64_t seed;
-  h2_precision prec;   /* FP64, or FP32 sampling with an FP64 residual + refinement */
+  h2_precision prec;   /* H2_FP64: every sampler product in FP64.  H2_FP32: while
+                          E > sqrt(eps) the sampler's HGEMVs run on FP32 copies of
+                          A and X_k (FP32 matrix cores); the residual E is always
+                          FP64, and the iterations after the switch (the
+                          refinement) are FP64.  BF16 is refused: BF16 iterates
+                          carry 2^-9 relative rounding, a residual floor of about
+                          4e-3 cond(A). */
 } h2_ns_opts;
 
 #define H2_MAX_NS_ITERS 128
@@ -199,6 +205,7 @@ typedef struct {
   int64_t applies[H2_MAX_NS_ITERS]; /* sampler columns per iteration */
   int max_rank[H2_MAX_NS_ITERS];    /* largest basis rank of each iterate */
   double time_ms[4];                /* residual, build, refine, total */
+  int low_iterations;               /* iterations built from FP32 samples */
 } h2_ns_stats;
 
 void h2_ns_opts_default(h2_ns_opts* opts);

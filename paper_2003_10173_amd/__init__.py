@@ -359,7 +359,7 @@ def newton_schulz(A, o=None, stream=None):
     k = st.iterations
     info = dict(iterations=k, norm=st.norm, resid=list(st.resid[:k + 1]),
                 applies=list(st.applies[:k]), max_rank=list(st.max_rank[:k]),
-                time_ms=list(st.time_ms), status=rc)
+                time_ms=list(st.time_ms), status=rc, low_iterations=st.low_iterations)
     return H2Matrix(h, A.tree), info
 
 

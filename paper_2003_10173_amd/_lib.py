@@ -46,7 +46,7 @@ class H2NSOpts(C.Structure):
 class H2NSStats(C.Structure):
     _fields_ = [("iterations", C.c_int), ("norm", dbl), ("resid", dbl * (H2_MAX_NS_ITERS + 1)),
                 ("applies", i64 * H2_MAX_NS_ITERS), ("max_rank", C.c_int * H2_MAX_NS_ITERS),
-                ("time_ms", dbl * 4)]
+                ("time_ms", dbl * 4), ("low_iterations", C.c_int)]
 
 
 # name -> (restype, argtypes)

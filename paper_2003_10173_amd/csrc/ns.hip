@@ -50,6 +50,51 @@ struct NSSampler : Sampler {
   }
 };
 
+__global__ void k_d2f(int n, int ncols, const double* __restrict__ a, int lda, float* __restrict__ b,
+                      int ldb) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (int64_t)n * ncols) return;
+  const int r = (int)(e % n), c = (int)(e / n);
+  b[(size_t)c * ldb + r] = (float)a[(size_t)c * lda + r];
+}
+
+// y = 2 W - Z in FP64 from FP32 W, Z (n x ncols, ld n)
+__global__ void k_two_w_minus(int n, int ncols, const float* __restrict__ w,
+                              const float* __restrict__ z, double* __restrict__ y, int ldy) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (int64_t)n * ncols) return;
+  const int r = (int)(e % n), c = (int)(e / n);
+  y[(size_t)c * ldy + r] = 2.0 * (double)w[e] - (double)z[e];
+}
+
+// The same sampler with FP32 copies of X_k and A (FP32 HGEMVs on matrix
+// cores); Omega arrives and Y leaves in FP64 for the FP64 construction.
+struct NSSamplerF32 : Sampler {
+  const h2_matrix* X;
+  const h2_matrix* A;
+  DevBuf buf;
+  NSSamplerF32(const h2_matrix* x, const h2_matrix* a) : X(x), A(a) {}
+  void apply(Ctx& c, int ncols, const double* om, double* y) override {
+    if (ncols <= 0) return;
+    const int n = X->tree->n;
+    buf.reserve((size_t)4 * n * ncols * sizeof(float));
+    float* O = buf.as<float>();
+    float* W = O + (size_t)n * ncols;
+    float* T = W + (size_t)n * ncols;
+    float* Y = T + (size_t)n * ncols;
+    const int64_t tot = (int64_t)n * ncols;
+    const unsigned blocks = (unsigned)((tot + 255) / 256);
+    k_d2f<<<blocks, 256, 0, c.s>>>(n, ncols, om, n, O, n);
+    H2_LAUNCH_CHECK();
+    gemv_tree_f32(X, ncols, 1.0f, O, n, 0.0f, W, n, c.s);
+    gemv_tree_f32(A, ncols, 1.0f, W, n, 0.0f, T, n, c.s);
+    gemv_tree_f32(X, ncols, 1.0f, T, n, 0.0f, Y, n, c.s);
+    k_two_w_minus<<<blocks, 256, 0, c.s>>>(n, ncols, W, Y, y, n);
+    H2_LAUNCH_CHECK();
+    applies += ncols;
+  }
+};
+
 // Sampler that applies one H2 matrix (tree order)
 struct GemvSampler : Sampler {
   const h2_matrix* A;
@@ -112,6 +157,19 @@ std::unique_ptr<h2_matrix> ns_iterate(const h2_matrix* A, const h2_ns_opts& o, h
   bp.norm = 1.0 / nuA;
   Ctx c;
   c.s = s;
+  // mixed precision: FP32 copies of A and of each iterate feed the sampler
+  // until E <= sqrt(eps) (or the iteration stops contracting), then FP64
+  bool low = o.prec == H2_FP32;
+  std::unique_ptr<h2_matrix> A32, X32;
+  auto to_f32 = [&](const h2_matrix* M) {
+    auto B = std::make_unique<h2_matrix>();
+    matrix_layout(B.get(), t, M->rank);
+    matrix_alloc(B.get(), H2_FP32);
+    matrix_copy_convert(M, B.get(), 1.0, s);
+    return B;
+  };
+  if (low) A32 = to_f32(A);
+  const double switch_E = std::sqrt(std::max(o.eps, 0.0));
   *status = H2_ENOTCONVERGED;
   int k = 0;
   double prevE = -1;
@@ -125,15 +183,25 @@ std::unique_ptr<h2_matrix> ns_iterate(const h2_matrix* A, const h2_ns_opts& o, h
     if (o.eps > 0 && E <= o.eps) { *status = H2_OK; break; }
     if (k >= 1 && E > prevE && E > 1.0) { *status = H2_EDIVERGED; break; }
     if (k >= o.max_iter || k >= H2_MAX_NS_ITERS) break;
+    if (low && (E <= switch_E || (k >= 2 && E < 0.5 && E > 0.5 * prevE))) low = false;
     prevE = E;
     const double eps_k = o.dynamic ? std::min(std::max(0.1 * E * E, eps_build), 1e-2) : eps_build;
     bp.tol = eps_k;
     bp.iteration = (uint32_t)(k + 1);
-    NSSampler S(X.get(), A);
     h2_build_stats bst{};
     bool conv = true;
     t0 = now_ms2();
-    auto Xn = build_h2(t, S, bp, c, &bst, &conv);
+    std::unique_ptr<h2_matrix> Xn;
+    if (low) {
+      X32 = to_f32(X.get());
+      NSSamplerF32 S(X32.get(), A32.get());
+      Xn = build_h2(t, S, bp, c, &bst, &conv);
+      stats.low_iterations += 1;
+    } else {
+      NSSampler S(X.get(), A);
+      Xn = build_h2(t, S, bp, c, &bst, &conv);
+      if (o.prec == H2_FP32) stats.time_ms[2] += now_ms2() - t0;
+    }
     stats.time_ms[1] += now_ms2() - t0;
     stats.applies[k] = bst.applies;
     int mr = 0;
@@ -141,8 +209,8 @@ std::unique_ptr<h2_matrix> ns_iterate(const h2_matrix* A, const h2_ns_opts& o, h
     stats.max_rank[k] = mr;
     X = std::move(Xn);
     if (verbose())
-      std::fprintf(stderr, "[h2_ns] iteration %d: E %.3e eps_k %.1e applies %lld max rank %d build %.1f ms\n",
-                   k, E, eps_k, (long long)bst.applies, mr, now_ms2() - t0);
+      std::fprintf(stderr, "[h2_ns] iteration %d (%s): E %.3e eps_k %.1e applies %lld max rank %d build %.1f ms\n",
+                   k, low ? "fp32" : "fp64", E, eps_k, (long long)bst.applies, mr, now_ms2() - t0);
     ++k;
   }
   stats.iterations = k;
@@ -181,7 +249,8 @@ h2_status h2_newton_schulz(const h2_matrix* A, const h2_ns_opts* opts, hipStream
     H2_CHECK(A && opts && X_out, H2_EINVAL, "null argument");
     H2_CHECK(A->st.prec == H2_FP64, H2_EINVAL, "Newton-Schulz needs an FP64 matrix");
     H2_CHECK(opts->max_iter >= 0, H2_EINVAL, "max_iter must be >= 0");
-    H2_CHECK(opts->prec == H2_FP64, H2_EINVAL, "Newton-Schulz precision must be FP64 here");
+    H2_CHECK(opts->prec == H2_FP64 || opts->prec == H2_FP32, H2_EINVAL,
+             "Newton-Schulz precision must be FP64 or FP32 (BF16 iterates cannot reach 1e-4)");
     auto X = ns_iterate(A, *opts, stream, stats, &result);
     *X_out = X.release();
   });

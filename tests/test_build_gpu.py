@@ -182,3 +182,32 @@ def test_newton_schulz_matches_oracle():
     assert ginfo["applies"] == info["applies"]
     assert op_err(X, Xo, T.n) <= 1e-9
     assert h2.residual_norm(G, X, rel=1e-6, max_iter=3000) <= 1e-4
+
+
+def test_newton_schulz_mixed_fp32_against_fp64_oracle():
+    """FP32 sampling (FP32 copies of A and X_k on FP32 matrix cores) until
+    E <= sqrt(eps), FP64 residuals throughout and FP64 refinement iterations
+    after the switch.  Two approximate inverses with residuals E_a, E_b
+    differ by at most ||A^-1|| (E_a + E_b), so against the FP64 oracle's
+    inverse the relative operator error is at most 2e-4 (+ the 1e-8 build)."""
+    pts = si.points_1d_cell_centres(256)
+    K = KernelHessian(pts, 0.1, 1e-2)
+    T = OTree(pts, 32, 0.7)
+    A = tree_order(K.apply, T.perm)
+    nu, _ = power_norm(A, T.n, 1)
+    H, _ = obuild(A, T, 1e-8, nu, 16, 10, adaptive=True, seed=1)
+    Xo, info = ons(H, 1e-4, 40, 32, 10, x0="identity", dynamic=True, adaptive=True, seed=2)
+    gt = h2.Tree(pts, 32, 0.7)
+    G, _ = h2.build(gt, h2.KernelSampler(pts, 0.1, 1e-2),
+                    h2.opts(rank_cap=16, oversample=10, tol=1e-8, adaptive=1, seed=1))
+    o = h2.ns_opts(eps=1e-4, max_iter=40, x0=0, dynamic=1, rank_cap=32, oversample=10,
+                   adaptive=1, seed=2, prec=h2.H2_FP32)
+    X, ginfo = h2.newton_schulz(G, o)
+    assert ginfo["status"] == 0
+    assert ginfo["low_iterations"] >= 1
+    assert ginfo["iterations"] > ginfo["low_iterations"]        # refinement ran in FP64
+    assert ginfo["resid"][-1] <= 1e-4
+    assert h2.residual_norm(G, X, rel=1e-6, max_iter=3000) <= 1e-4
+    assert op_err(X, Xo, T.n) <= 2.5e-4
+    with pytest.raises(h2.H2Error):
+        h2.newton_schulz(G, h2.ns_opts(eps=1e-4, prec=h2.H2_BF16))
