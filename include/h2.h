@@ -37,6 +37,7 @@ extern "C" {
 
 typedef struct h2_tree h2_tree;
 typedef struct h2_matrix h2_matrix;
+typedef struct h2_mlp h2_mlp;
 
 typedef enum {
   H2_OK = 0,
@@ -102,7 +103,10 @@ typedef struct {
   uint32_t iteration;  /* stream tag (Newton-Schulz iteration index) */
   double norm;         /* ||A||_2 if known (> 0); else estimated (power method) */
   h2_precision prec;   /* FP64 only for construction; see h2_matrix_convert */
-  int learned;         /* reserved: 0 */
+  const h2_mlp* learned; /* NULL: plain adaptive sampling.  Otherwise (adaptive
+                          mode) the network's predictions set the width of each
+                          level's first sampling round (see h2_mlp_create); the
+                          estimator still decides when sampling stops */
 } h2_opts;
 
 #define H2_MAX_LEVELS 32
@@ -118,6 +122,7 @@ typedef struct {
   int converged;                   /* 1 if every level met the estimator */
   int cap_hit;                     /* 1 if the rank cap truncated a basis */
   double time_ms[8];               /* norm, sample, range, project, diag, recompress, sampler, total */
+  int first_cols[H2_MAX_LEVELS];   /* width of the first sampling round at level l */
 } h2_build_stats;
 
 /* default options: cap 32, p 10, tol 1e-4, adaptive, 16 rounds, seed 1 */
@@ -258,6 +263,53 @@ int h2_sampler_advdiff_apply(void* ctx, int n, int ncols, const double* omega, i
 int h2_sampler_h2_apply(void* ctx, int n, int ncols, const double* omega, int ld_omega,
                         double* y, int ld_y, hipStream_t stream);
 void h2_sampler_destroy(void* ctx);
+
+/* ------------------------------------------------------------------ learned counts */
+/*
+ * Rank predictor for the adaptive range finder of Sec. 3.3 (not from the
+ * paper; the estimator stays the stopping rule).  For sibling pair p of
+ * level l (t2 = cluster 2p+1) the network maps 16 features to a predicted
+ * log(1 + k), k the rank the pair is truncated to; the first sampling round
+ * of the level takes max_p (expm1(y_p), rounded up) + oversample columns
+ * (at least rank_cap + oversample, at most 1024 - (rank_cap + oversample)).
+ * Features, in order:
+ *   l / L;  log2|t2| / 16;  the three box extents of t2, largest first, over
+ *   the largest root extent (0 for missing dimensions);  log10((e_max + d) /
+ *   (e_min + d)) / 4 over the dimensions, d = 1e-12 root extent (0 in 1D);
+ *   dim / 3;  log10(eps) / 10;  for i = 2, 4, ..., 128: max(log10(s_i /
+ *   s_1), -16) / 16 over the singular values s of the parent pair's block
+ *   (level l - 1, pair p / 2; -1 where it has fewer than i values; 0 at
+ *   level 1);  log2(1 + parent rank) / 10 (-1 at level 1).
+ * Network: 16 -> 64 -> 64 -> 1, ReLU after the hidden layers; products with
+ * BF16 copies of the weights (round to nearest even), FP32 activations and
+ * accumulation.  Packed FP32 parameters: W1 (64 x 16, row-major), b1 (64),
+ * W2 (64 x 64), b2 (64), W3 (64), b3 (1): H2_MLP_PARAMS floats.
+ */
+#define H2_MLP_FEATURES 16
+#define H2_MLP_HIDDEN 64
+#define H2_MLP_PARAMS 5313
+/* copies params_host (FP32 masters); Adam moments start at zero */
+h2_status h2_mlp_create(const float* params_host, h2_mlp** out);
+/* current FP32 master parameters (synchronises the device) */
+h2_status h2_mlp_params(const h2_mlp* m, float* params_host);
+/* y[0:batch] for X (batch x 16, row-major); device pointers */
+h2_status h2_mlp_forward(const h2_mlp* m, int batch, const float* X, float* y, hipStream_t stream);
+/* gradient (H2_MLP_PARAMS floats, packed like the parameters) and loss (1
+ * float) of the mean squared error against target[0:batch]; device pointers */
+h2_status h2_mlp_gradient(const h2_mlp* m, int batch, const float* X, const float* target,
+                          float* grad, float* loss, hipStream_t stream);
+/* one Adam step (beta 0.9 / 0.999, eps 1e-8, bias-corrected) on a batch */
+h2_status h2_mlp_train_step(h2_mlp* m, int batch, const float* X, const float* target, float lr,
+                            hipStream_t stream);
+/* loss of the last train step's batch (synchronises the device) */
+h2_status h2_mlp_last_loss(const h2_mlp* m, float* loss_host);
+void h2_mlp_destroy(h2_mlp* m);
+/* Training records: while enabled (h2_records_enable(1) also clears), every
+ * adaptive h2_build appends, for each sibling pair of each level, the 16
+ * features above and log(1 + k).  h2_records_read returns the count and, if
+ * the pointers are not NULL, copies count x 16 features and count targets. */
+h2_status h2_records_enable(int on);
+h2_status h2_records_read(int64_t* count, float* features, float* targets);
 
 /* Launch timing for roofline reporting (no paper counterpart; a measurement
  * aid).  h2_timing_enable(1) clears the totals and starts bracketing every

@@ -73,10 +73,10 @@ def residual_norm(A, X, seed, iteration, rel=1e-2, min_it=3, max_it=30):
 
 
 def build(apply_tree, tree, tol, nu, rank_cap, oversample, adaptive=True,
-          max_rounds=16, seed=1, iteration=0):
+          max_rounds=16, seed=1, iteration=0, first_cols=None):
     """Peeling followed by recompression: the oracle's buildH(S, eps)."""
     pr = peel(apply_tree, tree, tol, nu, rank_cap, oversample, adaptive,
-              max_rounds, seed, iteration)
+              max_rounds, seed, iteration, first_cols)
     H = recompress(tree, pr, tol, nu, rank_cap)
     return H, pr
 

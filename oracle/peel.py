@@ -31,6 +31,9 @@ Readings taken here (the paper gives no formulas for them):
   * tau = eps * nu / (4 L), nu the 2-norm estimate of the sampled operator
   * recompression once after all levels, at the same threshold, with the
     destination rank cap
+  * the round budget is clamped so that at most 1024 sample columns are kept
+    per pair (the first round may be wider than the others: a per-level
+    first-round width, e.g. from a learned rank prediction, is an input)
 """
 import math
 
@@ -72,6 +75,8 @@ class PeelResult:
         self.applies = 0
         self.rounds = {}     # level -> rounds taken
         self.k0 = {}         # level -> range-basis sizes
+        self.sig = {}        # level -> per pair singular values of B0 (descending)
+        self.first_cols = {} # level -> width of the first sampling round
         self.converged = True
 
 
@@ -90,9 +95,11 @@ def weak_apply(tree, l, F, Om):
 
 
 def peel(apply_tree, tree, tol, nu, rank_cap, oversample, adaptive=True,
-         max_rounds=16, seed=1, iteration=0):
+         max_rounds=16, seed=1, iteration=0, first_cols=None):
     """Weak-partition peeling of the operator `apply_tree` (tree-order columns).
 
+    first_cols: optional {level: width} of the first sampling round (the
+    other rounds take rank_cap + oversample columns).
     Returns a PeelResult with the factors of every level and the leaf diagonal.
     """
     N, L = tree.n, tree.L
@@ -113,13 +120,17 @@ def peel(apply_tree, tree, tol, nu, rank_cap, oversample, adaptive=True,
         npairs = 1 << (l - 1)
         Z = [np.zeros((tree.size(l, 2 * p + 1), 0)) for p in range(npairs)]
         frozen = [False] * npairs
+        b0 = max(b, int(first_cols.get(l, b))) if first_cols else b
+        res.first_cols[l] = b0
+        rounds_max = max(2, min(max_rounds, 1 + (1024 - b0) // b))
         r = 0
         while True:
             key = rng.stream_key(seed, rng.PHASE_RANGE, l, r, iteration)
-            Om = np.zeros((N, b))
+            width = b0 if r == 0 else b
+            Om = np.zeros((N, width))
             for p in range(npairs):
                 a1, b1 = tree.rng(l, 2 * p)
-                Om[a1:b1] = rng.gaussian(key, np.arange(a1, b1), np.arange(b))
+                Om[a1:b1] = rng.gaussian(key, np.arange(a1, b1), np.arange(width))
             Y = subtract(l, Om, A(Om))
             for p in range(npairs):
                 if frozen[p]:
@@ -140,7 +151,7 @@ def peel(apply_tree, tree, tol, nu, rank_cap, oversample, adaptive=True,
                 break
             if r >= 2 and all(frozen):
                 break
-            if r >= max_rounds:
+            if r >= rounds_max:
                 res.converged = False
                 break
         res.rounds[l] = r
@@ -149,6 +160,7 @@ def peel(apply_tree, tree, tol, nu, rank_cap, oversample, adaptive=True,
         res.k0[l] = k0
         K0 = int(k0.max())
         kw = np.zeros(npairs, dtype=np.int64)
+        res.sig[l] = [np.zeros(0) for _ in range(npairs)]
         Qs, Bs = [None] * npairs, [None] * npairs
         if K0 > 0:
             Om2 = np.zeros((N, K0))
@@ -164,6 +176,7 @@ def peel(apply_tree, tree, tol, nu, rank_cap, oversample, adaptive=True,
                     Bs[p] = np.zeros((b1 - a1, 0))
                     continue
                 W, s, Vt = np.linalg.svd(B0, full_matrices=False)
+                res.sig[l][p] = s
                 k = int(np.sum(s > tau))
                 kw[p] = k
                 Qs[p] = Q0[p] @ Vt[:k].T

@@ -314,6 +314,9 @@ def opts(**kw):
     o = H2Opts()
     lib().h2_opts_default(C.byref(o))
     for k, v in kw.items():
+        if k == "learned":
+            o._mlp = v                      # keep the network alive with the options
+            v = v.handle.value if v is not None else None
         setattr(o, k, v)
     return o
 
@@ -333,7 +336,7 @@ def stats_dict(st, levels):
                 strong_rank=list(st.strong_rank[:levels + 1]), applies=st.applies,
                 norm_applies=st.norm_applies,
                 norm=st.norm, converged=bool(st.converged), cap_hit=bool(st.cap_hit),
-                time_ms=list(st.time_ms))
+                time_ms=list(st.time_ms), first_cols=list(st.first_cols[1:levels + 1]))
 
 
 def build(tree, sampler, o=None, stream=None, allow_not_converged=True):
@@ -394,3 +397,87 @@ def stream_copy(src, dst):
     assert src.is_contiguous() and dst.is_contiguous() and src.numel() == dst.numel()
     s = torch.cuda.current_stream().cuda_stream
     check(lib().h2_stream_copy(src.data_ptr(), dst.data_ptr(), src.numel(), s), "h2_stream_copy")
+
+
+# ------------------------------------------------------------------ learned counts
+MLP_FEATURES = 16
+MLP_HIDDEN = 64
+MLP_PARAMS = 5313
+
+
+class MLP:
+    """Rank predictor (h2_mlp): 16 -> 64 -> 64 -> 1, BF16 weights in the
+    products, FP32 masters trained by Adam on the GPU."""
+
+    def __init__(self, params):
+        p = np.ascontiguousarray(np.asarray(params, dtype=np.float32))
+        if p.shape != (MLP_PARAMS,):
+            raise ValueError("expected %d packed parameters" % MLP_PARAMS)
+        self.handle = C.c_void_p()
+        check(lib().h2_mlp_create(p.ctypes.data, C.byref(self.handle)), "h2_mlp_create")
+
+    @staticmethod
+    def he_init(seed):
+        """Packed He-normal weights (FP32) and zero biases."""
+        g = np.random.Generator(np.random.PCG64(seed))
+        parts = [g.standard_normal((MLP_HIDDEN, MLP_FEATURES)) * np.sqrt(2.0 / MLP_FEATURES),
+                 np.zeros(MLP_HIDDEN),
+                 g.standard_normal((MLP_HIDDEN, MLP_HIDDEN)) * np.sqrt(2.0 / MLP_HIDDEN),
+                 np.zeros(MLP_HIDDEN),
+                 g.standard_normal(MLP_HIDDEN) * np.sqrt(2.0 / MLP_HIDDEN),
+                 np.zeros(1)]
+        return np.concatenate([a.ravel() for a in parts]).astype(np.float32)
+
+    def params(self):
+        out = np.zeros(MLP_PARAMS, dtype=np.float32)
+        check(lib().h2_mlp_params(self.handle, out.ctypes.data), "h2_mlp_params")
+        return out
+
+    def forward(self, X, stream=None):
+        import torch
+        X = X.contiguous()
+        y = torch.empty(X.shape[0], dtype=torch.float32, device=X.device)
+        check(lib().h2_mlp_forward(self.handle, X.shape[0], X.data_ptr(), y.data_ptr(),
+                                   _stream(stream)), "h2_mlp_forward")
+        return y
+
+    def gradient(self, X, T, stream=None):
+        import torch
+        X, T = X.contiguous(), T.contiguous()
+        g = torch.empty(MLP_PARAMS, dtype=torch.float32, device=X.device)
+        loss = torch.empty(1, dtype=torch.float32, device=X.device)
+        check(lib().h2_mlp_gradient(self.handle, X.shape[0], X.data_ptr(), T.data_ptr(),
+                                    g.data_ptr(), loss.data_ptr(), _stream(stream)),
+              "h2_mlp_gradient")
+        return g, loss
+
+    def train_step(self, X, T, lr, stream=None):
+        check(lib().h2_mlp_train_step(self.handle, X.shape[0], X.data_ptr(), T.data_ptr(),
+                                      C.c_float(lr), _stream(stream)), "h2_mlp_train_step")
+
+    def last_loss(self):
+        v = C.c_float()
+        check(lib().h2_mlp_last_loss(self.handle, C.byref(v)), "h2_mlp_last_loss")
+        return v.value
+
+    def __del__(self):
+        try:
+            if getattr(self, "handle", None) is not None and self.handle.value:
+                lib().h2_mlp_destroy(self.handle)
+                self.handle = None
+        except Exception:  # noqa: BLE001
+            pass
+
+
+def records_enable(on=True):
+    check(lib().h2_records_enable(1 if on else 0), "h2_records_enable")
+
+
+def records_read():
+    """(features (count x 16), targets (count,)) recorded since enable."""
+    n = C.c_int64()
+    check(lib().h2_records_read(C.byref(n), None, None), "h2_records_read")
+    F = np.zeros((n.value, MLP_FEATURES), dtype=np.float32)
+    T = np.zeros(n.value, dtype=np.float32)
+    check(lib().h2_records_read(C.byref(n), F.ctypes.data, T.ctypes.data), "h2_records_read")
+    return F, T

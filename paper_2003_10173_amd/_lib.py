@@ -25,7 +25,7 @@ SAMPLER_FN = C.CFUNCTYPE(C.c_int, vp, C.c_int, C.c_int, vp, C.c_int, vp, C.c_int
 class H2Opts(C.Structure):
     _fields_ = [("rank_cap", C.c_int), ("oversample", C.c_int), ("tol", dbl),
                 ("adaptive", C.c_int), ("max_rounds", C.c_int), ("seed", u64),
-                ("iteration", u32), ("norm", dbl), ("prec", C.c_int), ("learned", C.c_int)]
+                ("iteration", u32), ("norm", dbl), ("prec", C.c_int), ("learned", vp)]
 
 
 class H2BuildStats(C.Structure):
@@ -33,7 +33,8 @@ class H2BuildStats(C.Structure):
                 ("range_cols", C.c_int * H2_MAX_LEVELS), ("rounds", C.c_int * H2_MAX_LEVELS),
                 ("strong_rank", C.c_int * H2_MAX_LEVELS), ("applies", i64),
                 ("norm_applies", i64), ("norm", dbl),
-                ("converged", C.c_int), ("cap_hit", C.c_int), ("time_ms", dbl * 8)]
+                ("converged", C.c_int), ("cap_hit", C.c_int), ("time_ms", dbl * 8),
+                ("first_cols", C.c_int * H2_MAX_LEVELS)]
 
 
 class H2NSOpts(C.Structure):
@@ -76,6 +77,15 @@ SIGNATURES = {
     "h2_matrix_words": (C.c_int, [vp, P(i64), P(i64)]),
     "h2_ns_opts_default": (None, [P(H2NSOpts)]),
     "h2_timing_enable": (C.c_int, [C.c_int]),
+    "h2_mlp_create": (C.c_int, [vp, P(vp)]),
+    "h2_mlp_params": (C.c_int, [vp, vp]),
+    "h2_mlp_forward": (C.c_int, [vp, C.c_int, vp, vp, vp]),
+    "h2_mlp_gradient": (C.c_int, [vp, C.c_int, vp, vp, vp, vp, vp]),
+    "h2_mlp_train_step": (C.c_int, [vp, C.c_int, vp, vp, C.c_float, vp]),
+    "h2_mlp_last_loss": (C.c_int, [vp, P(C.c_float)]),
+    "h2_mlp_destroy": (None, [vp]),
+    "h2_records_enable": (C.c_int, [C.c_int]),
+    "h2_records_read": (C.c_int, [vp, vp, vp]),
     "h2_stream_copy": (C.c_int, [vp, vp, i64, vp]),
     "h2_timing_read": (C.c_int, [C.c_char_p, P(i64), P(dbl), P(dbl)]),
     "h2_newton_schulz": (C.c_int, [vp, P(H2NSOpts), vp, P(vp), P(H2NSStats)]),

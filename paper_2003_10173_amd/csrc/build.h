@@ -36,6 +36,7 @@ struct BuildParams {
   uint32_t iteration = 0;
   double norm = 0;        // > 0: use as ||A||_2; else estimate
   double norm_rel = 1e-2;
+  const h2_mlp* mlp = nullptr;  // rank predictor for the first round (adaptive mode)
 };
 
 // Peeling on the weak partition + recompression into the strong H2 of `t`.

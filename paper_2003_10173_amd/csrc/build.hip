@@ -28,6 +28,7 @@
 #include <tuple>
 
 #include "build.h"
+#include "mlp.h"
 #include "kernels_common.h"
 #include "vecops.h"
 
@@ -209,6 +210,50 @@ void left_svd_batched(Ctx& c, const std::vector<LsvTask>& tasks) {
 
 }  // namespace
 
+// Features of the sibling pairs of level l for the rank predictor (the list
+// is documented with h2_mlp_create): geometry of t2, tolerance, and the
+// singular-value decay and rank of the parent pair.
+std::vector<float> pair_features(const h2_tree* t, int l, double tol,
+                                 const std::vector<std::vector<double>>& psig,
+                                 const std::vector<int>& pk) {
+  const int np = 1 << (l - 1), D = t->dim;
+  double root = 0;
+  for (int d = 0; d < D; ++d) root = std::max(root, t->hi[0][d] - t->lo[0][d]);
+  if (!(root > 0)) root = 1.0;
+  static const int sidx[7] = {2, 4, 8, 16, 32, 64, 128};
+  std::vector<float> f((size_t)np * H2_MLP_FEATURES, 0.0f);
+  for (int p = 0; p < np; ++p) {
+    float* fp = f.data() + (size_t)p * H2_MLP_FEATURES;
+    const int c2 = 2 * p + 1;
+    std::vector<double> ext(D);
+    for (int d = 0; d < D; ++d) ext[d] = t->hi[l][(size_t)c2 * D + d] - t->lo[l][(size_t)c2 * D + d];
+    std::sort(ext.begin(), ext.end(), std::greater<double>());
+    fp[0] = (float)((double)l / t->L);
+    fp[1] = (float)(std::log2((double)t->csize[cid(l, c2)]) / 16.0);
+    for (int d = 0; d < std::min(D, 3); ++d) fp[2 + d] = (float)(ext[d] / root);
+    const double dd = 1e-12 * root;
+    fp[5] = D > 1 ? (float)(std::log10((ext[0] + dd) / (ext[D - 1] + dd)) / 4.0) : 0.0f;
+    fp[6] = (float)(D / 3.0);
+    fp[7] = (float)(std::log10(tol) / 10.0);
+    if (l == 1) {
+      fp[15] = -1.0f;
+      continue;
+    }
+    const std::vector<double>& s = psig[p / 2];
+    for (int q = 0; q < 7; ++q) {
+      const int i = sidx[q];
+      double v = -1.0;
+      if ((int)s.size() >= i && s[0] > 0) {
+        const double r = s[i - 1] / s[0];
+        v = r > 0 ? std::max(std::log10(r), -16.0) / 16.0 : -1.0;
+      }
+      fp[8 + q] = (float)v;
+    }
+    fp[15] = (float)(std::log2(1.0 + pk[p / 2]) / 10.0);
+  }
+  return f;
+}
+
 // ------------------------------------------------------------------ driver
 std::unique_ptr<h2_matrix> build_h2(const h2_tree* t, Sampler& S, const BuildParams& prm, Ctx& c,
                                     h2_build_stats* st, bool* converged_out) {
@@ -221,7 +266,6 @@ std::unique_ptr<h2_matrix> build_h2(const h2_tree* t, Sampler& S, const BuildPar
            "rank_cap + oversample must be <= 512 (adaptive) or 1024 (one round)");
   // the per-pair sample store holds at most 1024 columns (QR / SVD limit):
   // the round budget is clamped to what fits
-  const int max_rounds = std::max(2, std::min(prm.max_rounds, 1024 / b));
   h2_build_stats local{};
   h2_build_stats& stats = st ? *st : local;
   stats = h2_build_stats{};
@@ -247,6 +291,8 @@ std::unique_ptr<h2_matrix> build_h2(const h2_tree* t, Sampler& S, const BuildPar
   const double kHMT = 10.0 * std::sqrt(2.0 / M_PI);
 
   std::vector<Level> lv(L + 1);
+  std::vector<std::vector<double>> prev_sig;   // singular values of B0 per pair, previous level
+  std::vector<int> prev_k;
   DevBuf om_buf, y_buf;
   reset_factors();
   for (int l = 1; l <= L; ++l) {
@@ -255,7 +301,30 @@ std::unique_ptr<h2_matrix> build_h2(const h2_tree* t, Sampler& S, const BuildPar
     for (int p = 0; p < np; ++p)
       pr[p] = {t->cstart[cid(l, 2 * p)], t->csize[cid(l, 2 * p)], t->cstart[cid(l, 2 * p + 1)],
                t->csize[cid(l, 2 * p + 1)]};
-    const int cmax = prm.adaptive ? max_rounds * b : b;
+    // first-round width: learned prediction (adaptive mode) or the plain width
+    int b0 = b;
+    std::vector<float> feats;
+    if (prm.adaptive && (prm.mlp || records_on())) feats = pair_features(t, l, prm.tol, prev_sig, prev_k);
+    if (prm.adaptive && prm.mlp) {
+      auto* dX = (float*)c.stage.put(feats.data(), feats.size() * sizeof(float), c.s);
+      DevBuf dy((size_t)np * sizeof(float));
+      mlp_forward(prm.mlp, np, dX, dy.as<float>(), c.s);
+      std::vector<float> pred(np);
+      H2_HIP(hipMemcpyAsync(pred.data(), dy.p, np * sizeof(float), hipMemcpyDeviceToHost, c.s));
+      H2_HIP(hipStreamSynchronize(c.s));
+      c.stage.reset();
+      float ymax = -1e30f;
+      for (float v : pred) {
+        H2_CHECK(std::isfinite(v), H2_ENUMERIC, "non-finite rank prediction");
+        ymax = std::max(ymax, v);
+      }
+      const double kpred = std::max(0.0, std::expm1((double)ymax));
+      b0 = (int)std::min<double>(std::max<double>(b, std::ceil(kpred) + prm.oversample), 1024 - b);
+      b0 = std::max(b0, b);
+    }
+    stats.first_cols[l] = b0;
+    const int max_rounds = std::max(2, std::min(prm.max_rounds, 1 + (1024 - b0) / b));
+    const int cmax = prm.adaptive ? b0 + (max_rounds - 1) * b : b;
     // per-pair sample storage Z_p (m2 x cmax, ld m2) and an orthonormal basis
     // Qe_p of the samples kept so far (block Gram-Schmidt with two projections
     // per round), used by the estimator and by the final range basis
@@ -270,22 +339,23 @@ std::unique_ptr<h2_matrix> build_h2(const h2_tree* t, Sampler& S, const BuildPar
     double* Qe = qbuf.as<double>();
     std::vector<int> cols(np, 0), qc(np, 0);
     std::vector<char> frozen(np, 0);
-    om_buf.reserve((size_t)n * b * sizeof(double));
-    y_buf.reserve((size_t)n * b * sizeof(double));
+    om_buf.reserve((size_t)n * b0 * sizeof(double));
+    y_buf.reserve((size_t)n * b0 * sizeof(double));
     double* om = om_buf.as<double>();
     double* y = y_buf.as<double>();
     int r = 0;
     DevBuf ebuf(np * sizeof(double));
     t0 = now_ms();
     while (true) {
+      const int bw = r == 0 ? b0 : b;   // the first round may be wider (learned counts)
       const uint64_t key = stream_key(prm.seed, PHASE_RANGE, l, r, prm.iteration);
-      const int64_t tot = (int64_t)n * b;
+      const int64_t tot = (int64_t)n * bw;
       k_fill_left<<<(unsigned)((tot + 255) / 256), 256, 0, c.s>>>(
-          key, n, b, 1 << l, t->d_cstart.as<int32_t>() + cid(l, 0), om);
+          key, n, bw, 1 << l, t->d_cstart.as<int32_t>() + cid(l, 0), om);
       H2_LAUNCH_CHECK();
-      S.apply(c, b, om, y);
-      subtract_levels(c, t, lv, l, om, y, b);
-      if (r == 0) check_finite(c, y, (int64_t)n * b, "samples");
+      S.apply(c, bw, om, y);
+      subtract_levels(c, t, lv, l, om, y, bw);
+      if (r == 0) check_finite(c, y, (int64_t)n * bw, "samples");
       std::vector<int> newly(np, 0);
       std::vector<int> act;                    // pairs that take this round's samples
       for (int p = 0; p < np; ++p)
@@ -297,17 +367,17 @@ std::unique_ptr<h2_matrix> build_h2(const h2_tree* t, Sampler& S, const BuildPar
         std::vector<GemmDesc> g1, g2, g3, g4;
         for (int p : act) {
           const int m2 = pr[p].m2;
-          Yproj[p] = c.scratch.get((size_t)m2 * b);
-          cp.push_back({y + pr[p].a2, n, Yproj[p], m2, m2, b, 1.0, 0.0, 0});
+          Yproj[p] = c.scratch.get((size_t)m2 * bw);
+          cp.push_back({y + pr[p].a2, n, Yproj[p], m2, m2, bw, 1.0, 0.0, 0});
           const int q = qc[p];
           if (q == 0) continue;
-          double* W1 = c.scratch.get((size_t)q * b);
-          double* W2 = c.scratch.get((size_t)q * b);
+          double* W1 = c.scratch.get((size_t)q * bw);
+          double* W2 = c.scratch.get((size_t)q * bw);
           double* Qp_ = Qe + qoff[p];
-          g1.push_back({Qp_, Yproj[p], W1, q, b, m2, m2, m2, q, 1, 0, 1.0, 0.0});
-          g2.push_back({Qp_, W1, Yproj[p], m2, b, q, m2, q, m2, 0, 0, -1.0, 1.0});
-          g3.push_back({Qp_, Yproj[p], W2, q, b, m2, m2, m2, q, 1, 0, 1.0, 0.0});
-          g4.push_back({Qp_, W2, Yproj[p], m2, b, q, m2, q, m2, 0, 0, -1.0, 1.0});
+          g1.push_back({Qp_, Yproj[p], W1, q, bw, m2, m2, m2, q, 1, 0, 1.0, 0.0});
+          g2.push_back({Qp_, W1, Yproj[p], m2, bw, q, m2, q, m2, 0, 0, -1.0, 1.0});
+          g3.push_back({Qp_, Yproj[p], W2, q, bw, m2, m2, m2, q, 1, 0, 1.0, 0.0});
+          g4.push_back({Qp_, W2, Yproj[p], m2, bw, q, m2, q, m2, 0, 0, -1.0, 1.0});
         }
         copy_batched(c, cp);
         gemm_batched(c, g1);
@@ -317,7 +387,7 @@ std::unique_ptr<h2_matrix> build_h2(const h2_tree* t, Sampler& S, const BuildPar
       }
       if (prm.adaptive && r >= 1) {
         std::vector<CopyDesc> res_blocks;
-        for (int p : act) res_blocks.push_back({Yproj[p], pr[p].m2, nullptr, 0, pr[p].m2, b, 1.0, 0.0, 0});
+        for (int p : act) res_blocks.push_back({Yproj[p], pr[p].m2, nullptr, 0, pr[p].m2, bw, 1.0, 0.0, 0});
         colnorm_max_batched(c, res_blocks, ebuf.as<double>());
         auto e = to_host(ebuf.as<double>(), res_blocks.size(), c.s);
         for (size_t q = 0; q < act.size(); ++q) {
@@ -329,8 +399,8 @@ std::unique_ptr<h2_matrix> build_h2(const h2_tree* t, Sampler& S, const BuildPar
       std::vector<CopyDesc> app;
       for (int p : act) {
         app.push_back({y + pr[p].a2, n, Z + zoff[p] + (size_t)cols[p] * pr[p].m2, pr[p].m2,
-                       pr[p].m2, b, 1.0, 0.0, 0});
-        cols[p] += b;
+                       pr[p].m2, bw, 1.0, 0.0, 0});
+        cols[p] += bw;
       }
       copy_batched(c, app);
       // extend Qe with the projected block: QR, one more projection, QR again
@@ -342,12 +412,12 @@ std::unique_ptr<h2_matrix> build_h2(const h2_tree* t, Sampler& S, const BuildPar
         for (int p : act) {
           const int m2 = pr[p].m2, q = qc[p];
           if (q >= m2) continue;
-          const int kn = std::min(m2, b);
+          const int kn = std::min(m2, bw);
           const int take = std::min(kn, m2 - q);
-          const bool tall = m2 >= 2 * TSQR_MIN_ROWS && b <= 96;
+          const bool tall = m2 >= 2 * TSQR_MIN_ROWS && bw <= 96;  // else shape dispatch
           double* Qn = c.scratch.get((size_t)m2 * kn);
           double* Qn2 = c.scratch.get((size_t)m2 * kn);
-          (tall ? t1 : q1).push_back({Yproj[p], m2, m2, b, Qn, m2, nullptr, 0});
+          (tall ? t1 : q1).push_back({Yproj[p], m2, m2, bw, Qn, m2, nullptr, 0});
           if (q > 0) {
             double* Wq = c.scratch.get((size_t)q * kn);
             g1.push_back({Qe + qoff[p], Qn, Wq, q, kn, m2, m2, m2, q, 1, 0, 1.0, 0.0});
@@ -359,11 +429,11 @@ std::unique_ptr<h2_matrix> build_h2(const h2_tree* t, Sampler& S, const BuildPar
           }
           qc[p] = q + take;
         }
-        qr_batched(c, q1);
+        qr_auto(c, q1);
         qr_tall_batched(c, t1);
         gemm_batched(c, g1);
         gemm_batched(c, g2);
-        qr_batched(c, q2);
+        qr_auto(c, q2);
         qr_tall_batched(c, t2);
         copy_batched(c, put);
       }
@@ -442,6 +512,7 @@ std::unique_ptr<h2_matrix> build_h2(const h2_tree* t, Sampler& S, const BuildPar
     t0 = now_ms();
     Level& LV = lv[l];
     LV.k.assign(np, 0);
+    std::vector<std::vector<double>> cur_sig(np);
     if (K0 > 0) {
       om_buf.reserve((size_t)n * K0 * sizeof(double));
       y_buf.reserve((size_t)n * K0 * sizeof(double));
@@ -500,6 +571,7 @@ std::unique_ptr<h2_matrix> build_h2(const h2_tree* t, Sampler& S, const BuildPar
       copy_batched(c, rtc);
       svd_batched(c, svs);
       auto sbh = to_host(sb_all, boff[np], c.s);
+      for (int p = 0; p < np; ++p) cur_sig[p].assign(sbh.data() + boff[p], sbh.data() + boff[p] + kb[p]);
       for (int p = 0; p < np; ++p) {
         if (k0[p] == 0) continue;
         const double* s = sbh.data() + boff[p];
@@ -542,6 +614,13 @@ std::unique_ptr<h2_matrix> build_h2(const h2_tree* t, Sampler& S, const BuildPar
       LV.F.alloc(sizeof(double));
     }
     stats.weak_rank[l] = LV.K;
+    if (!feats.empty() && records_on()) {
+      std::vector<float> tg(np);
+      for (int p = 0; p < np; ++p) tg[p] = (float)std::log1p((double)LV.k[p]);
+      records_add(feats, tg);
+    }
+    prev_sig = std::move(cur_sig);
+    prev_k = LV.k;
     H2_HIP(hipStreamSynchronize(c.s));
     if (verbose())
       std::fprintf(stderr, "  [h2_build] level %d: rounds %d, range cols %d, rank %d, %.1f ms so far\n",
@@ -873,7 +952,7 @@ void h2_opts_default(h2_opts* o) {
   o->iteration = 0;
   o->norm = 0;
   o->prec = H2_FP64;
-  o->learned = 0;
+  o->learned = nullptr;
 }
 
 h2_status h2_build(const h2_tree* tree, h2_sampler_fn sampler, void* ctx, const h2_opts* opts,
@@ -889,6 +968,7 @@ h2_status h2_build(const h2_tree* tree, h2_sampler_fn sampler, void* ctx, const 
     p.tol = opts->tol;
     p.adaptive = opts->adaptive != 0;
     p.max_rounds = opts->max_rounds;
+    p.mlp = opts->learned;
     p.seed = opts->seed;
     p.iteration = opts->iteration;
     p.norm = opts->norm;

@@ -110,3 +110,22 @@ def config_advdiff2d(n=128, nobs=400, obs_seed=55, vel_seed=5):
                 kappa=1e-3, steps=400, obs_steps=list(range(40, 401, 40)), obs_points=obs,
                 sigma=1e-2, mode_a=a, mode_b=b, mode_s=s, leaf=64, eta=0.7, cap=32, p=10,
                 adaptive=True, tol=1e-4, seed=6)
+
+
+def learned_training_problem(i, base_seed=10000):
+    """Problem i of the rank-predictor training set: even i from the 1D
+    kernel family (N log-uniform in [512, 4096] cell centres, ell ~ U[0.02,
+    0.3], shift 10^U[-3, -1], leaf 32, cap 16), odd i from the 2D grid family
+    (side 32..128, ell ~ U[0.02, 0.2], shift 10^U[-3, -2], leaf 64, cap 32);
+    eps drawn from {1e-3, 1e-4, 1e-5, 1e-6}."""
+    g = np.random.Generator(np.random.PCG64(base_seed + i))
+    eps = float(g.choice([1e-3, 1e-4, 1e-5, 1e-6]))
+    if i % 2 == 0:
+        n = int(round(math.exp(g.uniform(math.log(512), math.log(4096)))))
+        return dict(name="kernel1d", n=n, points=points_1d_cell_centres(n),
+                    ell=float(g.uniform(0.02, 0.3)), shift=float(10 ** g.uniform(-3, -1)),
+                    leaf=32, eta=0.7, cap=16, p=10, tol=eps, seed=base_seed + i)
+    side = int(g.integers(32, 129))
+    return dict(name="kernel2d", n=side * side, points=points_grid_cell_centres(side, side),
+                ell=float(g.uniform(0.02, 0.2)), shift=float(10 ** g.uniform(-3, -2)),
+                leaf=64, eta=0.7, cap=32, p=10, tol=eps, seed=base_seed + i)

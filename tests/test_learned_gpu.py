@@ -1,0 +1,172 @@
+"""GPU parity of the learned first-round counts against the oracle: the
+network's forward and gradient (BF16 weights, FP32 accumulation against the
+oracle's exact sums with the same BF16 weights), one Adam step, the build's
+recorded features and ranks, the build with a learned schedule, and the gain
+of a network trained on the GPU over plain adaptive sampling."""
+import numpy as np
+import pytest
+
+import seeded_inputs as si
+from oracle import learned as OL
+from oracle.hessians import AdvDiffGN, KernelHessian, tree_order
+from oracle.ns import build as obuild, power_norm
+from oracle.tree import Tree as OTree
+from tests.h2_helpers import rel_err
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+h2 = pytest.importorskip("paper_2003_10173_amd")
+
+
+def unpack(p):
+    o = 0
+    W = {}
+    for k, shape in (("W1", (64, 16)), ("b1", (64,)), ("W2", (64, 64)), ("b2", (64,)),
+                     ("W3", (1, 64)), ("b3", (1,))):
+        n = int(np.prod(shape))
+        W[k] = np.asarray(p[o:o + n], dtype=np.float32).reshape(shape)
+        o += n
+    return W
+
+
+def pack(W):
+    return np.concatenate([np.asarray(W[k], dtype=np.float64).ravel() for k in OL.PARAMS])
+
+
+def features(n, seed):
+    g = np.random.Generator(np.random.PCG64(seed))
+    return g.uniform(-1, 1, size=(n, 16)).astype(np.float32), g.uniform(0, 5, n).astype(np.float32)
+
+
+def test_mlp_forward_matches_oracle():
+    p = h2.MLP.he_init(11)
+    net = h2.MLP(p)
+    X, _ = features(700, 1)
+    y = net.forward(torch.tensor(X, device="cuda")).cpu().numpy()
+    yo, _ = OL.forward(unpack(p), X.astype(np.float64), round_weights=True)
+    # FP32 sums of <= 64 terms against exact sums: 1e-5 relative
+    assert np.abs(y - yo).max() <= 1e-5 * max(1.0, np.abs(yo).max())
+    # the products really use BF16 weights: unrounded weights differ
+    yu, _ = OL.forward(unpack(p), X.astype(np.float64), round_weights=False)
+    assert np.abs(yu - yo).max() > 1e-4 * np.abs(yo).max()
+
+
+@pytest.mark.parametrize("batch", [1, 128, 300])
+def test_mlp_gradient_matches_oracle(batch):
+    p = h2.MLP.he_init(12)
+    net = h2.MLP(p)
+    X, T = features(batch, 2)
+    g, loss = net.gradient(torch.tensor(X, device="cuda"), torch.tensor(T, device="cuda"))
+    W = unpack(p)
+    yo, cache = OL.forward(W, X.astype(np.float64), round_weights=True)
+    lo, go = OL.backward(cache, yo, T.astype(np.float64))
+    assert abs(float(loss.item()) - lo) <= 1e-5 * lo
+    gg = unpack(g.cpu().numpy())
+    for k in OL.PARAMS:
+        ref = go[k].reshape(gg[k].shape)
+        assert np.abs(gg[k] - ref).max() <= 1e-4 * max(np.abs(ref).max(), 1e-6), k
+
+
+def test_mlp_adam_step_matches_oracle():
+    p = h2.MLP.he_init(13)
+    net = h2.MLP(p)
+    X, T = features(256, 3)
+    Xd, Td = torch.tensor(X, device="cuda"), torch.tensor(T, device="cuda")
+    W = unpack(p)
+    m = {k: np.zeros_like(v) for k, v in W.items()}
+    v = {k: np.zeros_like(v_) for k, v_ in W.items()}
+    for t in (1, 2):
+        net.train_step(Xd, Td, 1e-3)
+        yo, cache = OL.forward(W, X.astype(np.float64), round_weights=True)
+        _, go = OL.backward(cache, yo, T.astype(np.float64))
+        W, m, v = OL.adam_step(W, go, m, v, t, 1e-3)
+    got = net.params()
+    # each Adam step moves a weight by at most lr: compare at 1e-6 absolute
+    assert np.abs(got - pack(W)).max() <= 2e-6
+
+
+def _kernel2d(side, ell):
+    pts = si.points_grid_cell_centres(side, side)
+    return pts, KernelHessian(pts, ell, 1e-3)
+
+
+def test_build_records_match_oracle_features_and_ranks():
+    pts, K = _kernel2d(40, 0.1)
+    T = OTree(pts, 64, 0.7)
+    A = tree_order(K.apply, T.perm)
+    nu, _ = power_norm(A, T.n, 9)     # the build's seed: same norm estimate
+    tol = 1e-5
+    _, pr = obuild(A, T, tol, nu, 24, 10, adaptive=True, seed=9)
+    gt = h2.Tree(pts, 64, 0.7)
+    h2.records_enable(True)
+    try:
+        h2.build(gt, h2.KernelSampler(pts, 0.1, 1e-3),
+                 h2.opts(rank_cap=24, oversample=10, tol=tol, adaptive=1, seed=9))
+        F, Tg = h2.records_read()
+    finally:
+        h2.records_enable(False)
+    Fo = np.vstack([OL.level_features(T, pr, l, tol) for l in range(1, T.L + 1)])
+    To = np.concatenate([np.log1p(pr.kw[l]) for l in range(1, T.L + 1)])
+    assert F.shape == Fo.shape
+    assert np.array_equal(np.round(np.expm1(Tg)).astype(int), np.round(np.expm1(To)).astype(int))
+    # singular-value ratios near rounding level differ between SVD routines:
+    # compare those entries only where the ratio is above 1e-12
+    mask = np.ones_like(Fo, dtype=bool)
+    mask[:, 8:15] = (Fo[:, 8:15] > -12 / 16) & (F[:, 8:15] > -12 / 16)
+    assert np.abs(F - Fo)[mask].max() <= 2e-6
+
+
+def test_learned_schedule_build_matches_oracle():
+    """Whatever widths the network picks, the build equals the oracle's build
+    with the same first-round widths."""
+    pts, K = _kernel2d(36, 0.08)
+    T = OTree(pts, 64, 0.7)
+    A = tree_order(K.apply, T.perm)
+    nu, _ = power_norm(A, T.n, 4)
+    p = h2.MLP.he_init(5)
+    p[-1] = 4.5                         # output bias: ~90 predicted, a wide first round
+    net = h2.MLP(p)
+    gt = h2.Tree(pts, 64, 0.7)
+    G, st = h2.build(gt, h2.KernelSampler(pts, 0.08, 1e-3),
+                     h2.opts(rank_cap=24, oversample=10, tol=1e-6, adaptive=1, seed=4,
+                             learned=net))
+    fc = {l + 1: w for l, w in enumerate(st["first_cols"])}
+    assert max(fc.values()) > 34
+    H, pr = obuild(A, T, 1e-6, nu, 24, 10, adaptive=True, seed=4, first_cols=fc)
+    assert [pr.rounds[l] for l in range(1, T.L + 1)] == st["rounds"]
+    x = si.gaussian_vectors(T.n, 6, 8)
+    y = G.gemv(torch.tensor(np.ascontiguousarray(x.T), device="cuda")).cpu().numpy().T
+    assert rel_err(y, H.matvec(x)) <= 1e-10
+
+
+def test_trained_network_saves_rounds_on_advection_diffusion():
+    """Train on records of the library's own builds of the kernel families,
+    then build an advection-diffusion Gauss-Newton Hessian (not in the
+    training set) with and without the network: the learned build reaches
+    the same tolerance in fewer sampling rounds (sequential passes of PDE
+    solves)."""
+    from paper_2003_10173_amd import learned as LN
+    probs = [si.learned_training_problem(i) for i in range(40)]
+    probs = [p for p in probs if p["n"] <= 6000]
+    F, T = LN.generate_records(probs)
+    net, hist = LN.train(F, T, epochs=60, batch=128, lr=3e-3)
+    assert hist[-1] < 0.5 * hist[0]
+    cfg = si.config_advdiff2d(32)
+    S = h2.AdvDiffSampler(cfg)
+    gt = h2.Tree(cfg["points"], 64, 0.7)
+    tol = 1e-4
+    o_plain = h2.opts(rank_cap=32, oversample=10, tol=tol, adaptive=1, max_rounds=16, seed=6)
+    o_learn = h2.opts(rank_cap=32, oversample=10, tol=tol, adaptive=1, max_rounds=16, seed=6,
+                      learned=net)
+    Gp, sp = h2.build(gt, S, o_plain)
+    Gl, sl = h2.build(gt, S, o_learn)
+    G = AdvDiffGN(cfg)
+    x = si.gaussian_vectors(gt.n, 8, 3)
+    H = G.apply(x)
+    # the 2-norm target ||H - A|| <= tol ||H||, checked on probes
+    for Gm, st in ((Gp, sp), (Gl, sl)):
+        y = Gm.gemv(torch.tensor(np.ascontiguousarray(x.T), device="cuda")).cpu().numpy().T
+        assert np.linalg.norm(y - H) <= tol * st["norm"] * np.linalg.norm(x)
+    assert sum(sl["rounds"]) < sum(sp["rounds"]), (sl["rounds"], sp["rounds"])
+    print("plain rounds", sp["rounds"], "applies", sp["applies"],
+          "| learned rounds", sl["rounds"], "applies", sl["applies"], "first", sl["first_cols"])
