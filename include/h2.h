@@ -269,7 +269,8 @@ void h2_sampler_destroy(void* ctx);
  * Rank predictor for the adaptive range finder of Sec. 3.3 (not from the
  * paper; the estimator stays the stopping rule).  For sibling pair p of
  * level l (t2 = cluster 2p+1) the network maps 16 features to a predicted
- * log(1 + k), k the rank the pair is truncated to; the first sampling round
+ * log(1 + c), c the sample columns the pair held when the estimator accepted
+ * it in a plain adaptive build; the first sampling round
  * of the level takes max_p (expm1(y_p), rounded up) + oversample columns
  * (at least rank_cap + oversample, at most 1024 - (rank_cap + oversample)).
  * Features, in order:
@@ -306,7 +307,8 @@ h2_status h2_mlp_last_loss(const h2_mlp* m, float* loss_host);
 void h2_mlp_destroy(h2_mlp* m);
 /* Training records: while enabled (h2_records_enable(1) also clears), every
  * adaptive h2_build appends, for each sibling pair of each level, the 16
- * features above and log(1 + k).  h2_records_read returns the count and, if
+ * features above and log(1 + c), c the columns the pair held when the
+ * estimator accepted it (all its columns if it never did).  h2_records_read returns the count and, if
  * the pointers are not NULL, copies count x 16 features and count targets. */
 h2_status h2_records_enable(int on);
 h2_status h2_records_read(int64_t* count, float* features, float* targets);

@@ -2,11 +2,12 @@
 
 Not a method of the paper: a predictor that plugs into the adaptive range
 finder of Sec. 3.3.  For every sibling pair (t1, t2) = (2p, 2p+1) of level l
-it predicts log(1 + k), k the rank the pair is truncated to at tau; the
-level's first sampling round then takes max_p (predicted k_p) + oversample
-columns at once, and the Halko-Martinsson-Tropp estimator of the plain
-method still decides when sampling stops (extra rounds of rank_cap +
-oversample columns when the prediction fell short).
+it predicts log(1 + c), c the number of sample columns the pair held when
+the Halko-Martinsson-Tropp estimator accepted its basis in a plain adaptive
+build (all its columns if it never did); the level's first sampling round
+then takes max_p (predicted c_p) + oversample columns at once, and the
+estimator of the plain method still decides when sampling stops (extra
+rounds of rank_cap + oversample columns when the prediction fell short).
 
 Features of pair p at level l (16 values):
   0   l / L
@@ -155,10 +156,10 @@ def adam_step(W, g, m, v, t, lr, beta1=0.9, beta2=0.999, eps=1e-8):
     return Wn, mn, vn
 
 
-def first_round_width(pred_log1p_rank, oversample, base, limit=1024):
+def first_round_width(pred_log1p_cols, oversample, base, limit=1024):
     """Level width from the per-pair predictions: max_p (exp(y_p) - 1), rounded
     up, plus oversample; never below the plain width `base`, at most limit - base."""
-    if len(pred_log1p_rank) == 0:
+    if len(pred_log1p_cols) == 0:
         return base
-    k = max(0.0, math.expm1(float(np.max(pred_log1p_rank))))
+    k = max(0.0, math.expm1(float(np.max(pred_log1p_cols))))
     return int(min(max(base, math.ceil(k) + oversample), limit - base))

@@ -77,6 +77,7 @@ class PeelResult:
         self.k0 = {}         # level -> range-basis sizes
         self.sig = {}        # level -> per pair singular values of B0 (descending)
         self.first_cols = {} # level -> width of the first sampling round
+        self.needed = {}     # level -> per pair sample columns held when the estimator accepted
         self.converged = True
 
 
@@ -120,6 +121,7 @@ def peel(apply_tree, tree, tol, nu, rank_cap, oversample, adaptive=True,
         npairs = 1 << (l - 1)
         Z = [np.zeros((tree.size(l, 2 * p + 1), 0)) for p in range(npairs)]
         frozen = [False] * npairs
+        needed = [-1] * npairs
         b0 = max(b, int(first_cols.get(l, b))) if first_cols else b
         res.first_cols[l] = b0
         rounds_max = max(2, min(max_rounds, 1 + (1024 - b0) // b))
@@ -141,9 +143,10 @@ def peel(apply_tree, tree, tol, nu, rank_cap, oversample, adaptive=True,
                     Q = range_basis(Z[p])
                     resid = Yp - Q @ (Q.T @ Yp)
                     e = 10.0 * math.sqrt(2.0 / math.pi) * float(np.max(np.linalg.norm(resid, axis=0)))
-                    Z[p] = np.hstack([Z[p], Yp])
                     if e <= tau:
                         frozen[p] = True
+                        needed[p] = Z[p].shape[1]
+                    Z[p] = np.hstack([Z[p], Yp])
                 else:
                     Z[p] = np.hstack([Z[p], Yp])
             r += 1
@@ -155,6 +158,8 @@ def peel(apply_tree, tree, tol, nu, rank_cap, oversample, adaptive=True,
                 res.converged = False
                 break
         res.rounds[l] = r
+        res.needed[l] = np.array([needed[p] if needed[p] >= 0 else Z[p].shape[1]
+                                  for p in range(npairs)], dtype=np.int64)
         Q0 = [range_basis(Z[p]) for p in range(npairs)]
         k0 = np.array([q.shape[1] for q in Q0], dtype=np.int64)
         res.k0[l] = k0

@@ -337,7 +337,7 @@ std::unique_ptr<h2_matrix> build_h2(const h2_tree* t, Sampler& S, const BuildPar
     DevBuf qbuf(std::max<int64_t>(qoff[np], 1) * sizeof(double));
     double* Z = zbuf.as<double>();
     double* Qe = qbuf.as<double>();
-    std::vector<int> cols(np, 0), qc(np, 0);
+    std::vector<int> cols(np, 0), qc(np, 0), needed(np, -1);
     std::vector<char> frozen(np, 0);
     om_buf.reserve((size_t)n * b0 * sizeof(double));
     y_buf.reserve((size_t)n * b0 * sizeof(double));
@@ -392,7 +392,10 @@ std::unique_ptr<h2_matrix> build_h2(const h2_tree* t, Sampler& S, const BuildPar
         auto e = to_host(ebuf.as<double>(), res_blocks.size(), c.s);
         for (size_t q = 0; q < act.size(); ++q) {
           H2_CHECK(std::isfinite(e[q]), H2_ENUMERIC, "non-finite samples");
-          if (kHMT * e[q] <= tau) newly[act[q]] = 1;
+          if (kHMT * e[q] <= tau) {
+            newly[act[q]] = 1;
+            needed[act[q]] = cols[act[q]];   // columns that sufficed, before this probe round
+          }
         }
       }
       // append this round's samples
@@ -616,7 +619,7 @@ std::unique_ptr<h2_matrix> build_h2(const h2_tree* t, Sampler& S, const BuildPar
     stats.weak_rank[l] = LV.K;
     if (!feats.empty() && records_on()) {
       std::vector<float> tg(np);
-      for (int p = 0; p < np; ++p) tg[p] = (float)std::log1p((double)LV.k[p]);
+      for (int p = 0; p < np; ++p) tg[p] = (float)std::log1p((double)(needed[p] >= 0 ? needed[p] : cols[p]));
       records_add(feats, tg);
     }
     prev_sig = std::move(cur_sig);

@@ -1,6 +1,6 @@
 // Learned first-round sample counts: a 16 -> 64 -> 64 -> 1 ReLU network that
-// predicts log(1 + rank) of a sibling block from its geometry and the
-// singular-value decay of its parent block (features listed in h2.h).  The
+// predicts log(1 + sample columns a sibling block needs) from its geometry
+// and the singular-value decay of its parent block (features listed in h2.h).  The
 // products use BF16 copies of the weights (round to nearest even from the
 // FP32 masters) with FP32 inputs, activations and accumulation; training is
 // mean-squared error with Adam on the FP32 masters.

@@ -1,7 +1,8 @@
 """Training and use of the first-round rank predictor (h2_mlp).
 
 Records come from the library's own adaptive builds (h2_records_*): for every
-sibling pair of every level, the 16 features and log(1 + rank).  Training
+sibling pair of every level, the 16 features and log(1 + columns the estimator
+accepted).  Training
 runs on the GPU through h2_mlp_train_step (BF16-weight products, FP32 Adam).
 """
 import os

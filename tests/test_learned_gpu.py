@@ -90,7 +90,7 @@ def _kernel2d(side, ell):
     return pts, KernelHessian(pts, ell, 1e-3)
 
 
-def test_build_records_match_oracle_features_and_ranks():
+def test_build_records_match_oracle_features_and_counts():
     pts, K = _kernel2d(40, 0.1)
     T = OTree(pts, 64, 0.7)
     A = tree_order(K.apply, T.perm)
@@ -106,7 +106,7 @@ def test_build_records_match_oracle_features_and_ranks():
     finally:
         h2.records_enable(False)
     Fo = np.vstack([OL.level_features(T, pr, l, tol) for l in range(1, T.L + 1)])
-    To = np.concatenate([np.log1p(pr.kw[l]) for l in range(1, T.L + 1)])
+    To = np.concatenate([np.log1p(pr.needed[l]) for l in range(1, T.L + 1)])
     assert F.shape == Fo.shape
     assert np.array_equal(np.round(np.expm1(Tg)).astype(int), np.round(np.expm1(To)).astype(int))
     # singular-value ratios near rounding level differ between SVD routines:
