@@ -114,6 +114,33 @@ def precision_ladder(h2, torch, si, stream, reps=20):
     return out
 
 
+def learned_form(h2, torch, si):
+    """Build of the advection-diffusion Gauss-Newton Hessian on a 128 x 128 grid
+    (N = 16384, cap 32, eps 1e-4) with plain adaptive sampling and with the
+    trained first-round predictor: wall time, Hessian applies, sampling rounds."""
+    from paper_2003_10173_amd import learned as LN
+    net = LN.load()
+    if net is None:
+        return None
+    cfg = si.config_advdiff2d(128)
+    S = h2.AdvDiffSampler(cfg)
+    tree = h2.Tree(cfg["points"], cfg["leaf"], cfg["eta"])
+    out = {"workload": "advdiff2d 128x128 (N=16384), leaf 64, cap 32, eps 1e-4, build only"}
+    for name, extra in (("plain", {}), ("learned", {"learned": net})):
+        o = h2.opts(rank_cap=cfg["cap"], oversample=cfg["p"], tol=1e-4, adaptive=1,
+                    max_rounds=16, seed=6, **extra)
+        h2.build(tree, S, o)                      # warm-up (allocations)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, st = h2.build(tree, S, o)
+        torch.cuda.synchronize()
+        out[name] = {"s": round(time.perf_counter() - t0, 4), "applies": st["applies"],
+                     "rounds": sum(st["rounds"]), "first_cols": st["first_cols"]}
+        print("learned form %s: %.3f s, %d applies, %d rounds" % (
+            name, out[name]["s"], st["applies"], out[name]["rounds"]), file=sys.stderr, flush=True)
+    return out
+
+
 def cpu_baseline(cfg, gpu_iters):
     """Oracle timed on a bounded sample: the full FP64 build of the Hessian plus
     one Newton-Schulz iteration, extrapolated to the GPU's iteration count."""
@@ -253,7 +280,8 @@ def main():
                  "mixed_fp32_s": round(t_mixed, 4),
                  "mixed_iterations": nm["iterations"], "mixed_fp32_iterations": nm["low_iterations"],
                  "mixed_residual": nm["resid"][-1],
-                 "precision_ladder": precision_ladder(h2, torch, si, stream)}
+                 "precision_ladder": precision_ladder(h2, torch, si, stream),
+                 "learned": learned_form(h2, torch, si)}
 
     cpu = None
     if not args.no_cpu_baseline:
