@@ -125,6 +125,20 @@ typedef struct {
   int first_cols[H2_MAX_LEVELS];   /* width of the first sampling round at level l */
 } h2_build_stats;
 
+/*
+ * Batched construction: nprob independent problems (trees, samplers,
+ * contexts and options per problem) built level-synchronously on one stream.
+ * Every launch of a phase (projections, QR, SVD, subtraction of peeled
+ * levels, recompression) covers the blocks of every problem that has that
+ * level; the samplers are called problem by problem.  out[i] receives each
+ * result; stats (nullable) is an array of nprob.  Each result equals the
+ * h2_build of the same problem.  H2_ENOTCONVERGED if any problem ran out of
+ * rounds; on an error every out[i] is NULL.
+ */
+h2_status h2_build_batched(int nprob, const h2_tree* const* trees, const h2_sampler_fn* samplers,
+                           void* const* ctxs, const h2_opts* opts, hipStream_t stream,
+                           h2_matrix** out, h2_build_stats* stats);
+
 /* default options: cap 32, p 10, tol 1e-4, adaptive, 16 rounds, seed 1 */
 void h2_opts_default(h2_opts* opts);
 
@@ -225,6 +239,17 @@ void h2_ns_opts_default(h2_ns_opts* opts);
  */
 h2_status h2_newton_schulz(const h2_matrix* A, const h2_ns_opts* opts, hipStream_t stream,
                            h2_matrix** X_out, h2_ns_stats* stats);
+
+/*
+ * Newton-Schulz for nprob independent FP64 matrices in lock step: each
+ * iteration evaluates every unfinished problem's residual, then rebuilds all
+ * unfinished iterates in one batched construction (h2_build_batched).
+ * opts, X_out, stats (nullable) and status (nullable) are arrays of nprob;
+ * status[i] is what h2_newton_schulz would return for problem i.
+ */
+h2_status h2_newton_schulz_batched(int nprob, const h2_matrix* const* A, const h2_ns_opts* opts,
+                                   hipStream_t stream, h2_matrix** X_out, h2_ns_stats* stats,
+                                   h2_status* status);
 
 /* E = ||I - A X||_2 by the power method on R^T R (four HGEMVs per step) */
 h2_status h2_residual_norm(const h2_matrix* A, const h2_matrix* X, double rel, int max_iter,

@@ -351,6 +351,46 @@ def build(tree, sampler, o=None, stream=None, allow_not_converged=True):
     return H2Matrix(h, tree), stats_dict(st, tree.L)
 
 
+def build_batched(trees, samplers, opts_list, stream=None):
+    """Level-synchronous construction of several problems (h2_build_batched);
+    returns ([H2Matrix], [stats dict], status)."""
+    n = len(trees)
+    assert len(samplers) == n and len(opts_list) == n
+    th = (C.c_void_p * n)(*[t.handle.value for t in trees])
+    fns = (C.c_void_p * n)(*[C.cast(s.fn, C.c_void_p).value for s in samplers])
+    ctxs = (C.c_void_p * n)(*[s.ctx.value if isinstance(s.ctx, C.c_void_p) else s.ctx
+                              for s in samplers])
+    oa = (H2Opts * n)(*opts_list)
+    out = (C.c_void_p * n)()
+    st = (H2BuildStats * n)()
+    rc = lib().h2_build_batched(n, th, fns, ctxs, oa, _stream(stream), out, st)
+    check(rc, "h2_build_batched", (0, 1))
+    mats = [H2Matrix(C.c_void_p(out[i]), trees[i]) for i in range(n)]
+    return mats, [stats_dict(st[i], trees[i].L) for i in range(n)], rc
+
+
+def newton_schulz_batched(As, opts_list, stream=None):
+    """Newton-Schulz of several matrices in lock step (h2_newton_schulz_batched);
+    returns ([X], [info dict])."""
+    n = len(As)
+    ah = (C.c_void_p * n)(*[A.handle.value for A in As])
+    oa = (H2NSOpts * n)(*opts_list)
+    out = (C.c_void_p * n)()
+    st = (H2NSStats * n)()
+    status = (C.c_int * n)()
+    check(lib().h2_newton_schulz_batched(n, ah, oa, _stream(stream), out, st, status),
+          "h2_newton_schulz_batched")
+    Xs, infos = [], []
+    for i in range(n):
+        k = st[i].iterations
+        infos.append(dict(iterations=k, norm=st[i].norm, resid=list(st[i].resid[:k + 1]),
+                          applies=list(st[i].applies[:k]), max_rank=list(st[i].max_rank[:k]),
+                          time_ms=list(st[i].time_ms), status=status[i],
+                          low_iterations=st[i].low_iterations))
+        Xs.append(H2Matrix(C.c_void_p(out[i]), As[i].tree))
+    return Xs, infos
+
+
 def newton_schulz(A, o=None, stream=None):
     """Hierarchical Newton-Schulz (h2_newton_schulz); returns (X, stats dict, status)."""
     if o is None:

@@ -77,6 +77,8 @@ SIGNATURES = {
     "h2_matrix_words": (C.c_int, [vp, P(i64), P(i64)]),
     "h2_ns_opts_default": (None, [P(H2NSOpts)]),
     "h2_timing_enable": (C.c_int, [C.c_int]),
+    "h2_build_batched": (C.c_int, [C.c_int, vp, vp, vp, vp, vp, vp, vp]),
+    "h2_newton_schulz_batched": (C.c_int, [C.c_int, vp, vp, vp, vp, vp, vp]),
     "h2_mlp_create": (C.c_int, [vp, P(vp)]),
     "h2_mlp_params": (C.c_int, [vp, vp]),
     "h2_mlp_forward": (C.c_int, [vp, C.c_int, vp, vp, vp]),

@@ -43,4 +43,18 @@ struct BuildParams {
 std::unique_ptr<h2_matrix> build_h2(const h2_tree* t, Sampler& S, const BuildParams& p, Ctx& c,
                                     h2_build_stats* st, bool* converged);
 
+// Several independent problems built level-synchronously: every launch of a
+// phase covers the blocks of all problems that have that level (the samplers
+// are applied problem by problem).  Each problem's result equals its own
+// build_h2 (the batched kernels treat every matrix independently).
+struct BuildJob {
+  const h2_tree* t = nullptr;
+  Sampler* S = nullptr;
+  BuildParams prm;
+  h2_build_stats stats{};
+  bool converged = true;
+  std::unique_ptr<h2_matrix> out;
+};
+void build_h2_multi(std::vector<BuildJob>& jobs, Ctx& c);
+
 }  // namespace h2

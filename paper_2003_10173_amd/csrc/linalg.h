@@ -10,17 +10,20 @@
 namespace h2 {
 
 // Pinned host + device ring used to ship descriptor arrays to kernels without
-// synchronising the stream (a wrap of the ring synchronises once).
+// synchronising the stream; a full ring is replaced by a fresh one and freed
+// at the next reset().
 struct Staging {
   char* host = nullptr;
   DevBuf dev;
   size_t cap = 0, head = 0;
+  std::vector<char*> retired_host;   // full rings kept until reset()
+  std::vector<DevBuf> retired_dev;
   explicit Staging(size_t cap_bytes = (size_t)32 << 20);
   ~Staging();
   Staging(const Staging&) = delete;
   Staging& operator=(const Staging&) = delete;
   void* put(const void* src, size_t bytes, hipStream_t s);
-  void reset() { head = 0; }  // only when the stream is known to be idle
+  void reset();  // only when the stream is known to be idle
 };
 
 // Grow-only scratch arena reused across launches of one driver call.

@@ -25,13 +25,21 @@ Staging::Staging(size_t cap_bytes) : cap(cap_bytes) {
   dev.alloc(cap);
 }
 Staging::~Staging() {
+  reset();
   if (host) (void)hipHostFree(host);
 }
 void* Staging::put(const void* src, size_t bytes, hipStream_t s) {
   const size_t n = (bytes + 255) & ~(size_t)255;
-  H2_CHECK(n <= cap, H2_EINVAL, "descriptor batch exceeds the staging ring");
   if (head + n > cap) {
-    H2_HIP(hipStreamSynchronize(s));
+    // Continue in a fresh ring: regions handed out since the last reset() may
+    // still be read by queued copies and kernels (a launch often takes several
+    // arrays), so the old ring stays allocated until reset().
+    retired_host.push_back(host);
+    retired_dev.push_back(std::move(dev));
+    host = nullptr;
+    cap = std::max(cap, 2 * n);
+    H2_HIP(hipHostMalloc((void**)&host, cap, hipHostMallocDefault));
+    dev.alloc(cap);
     head = 0;
   }
   std::memcpy(host + head, src, bytes);
@@ -39,6 +47,14 @@ void* Staging::put(const void* src, size_t bytes, hipStream_t s) {
   H2_HIP(hipMemcpyAsync(d, host + head, bytes, hipMemcpyHostToDevice, s));
   head += n;
   return d;
+}
+
+void Staging::reset() {
+  head = 0;
+  for (char* h : retired_host)
+    if (h) (void)hipHostFree(h);
+  retired_host.clear();
+  retired_dev.clear();
 }
 
 double* Scratch::get(size_t elems) {
@@ -203,10 +219,13 @@ void gemm_batched(Ctx& c, const std::vector<GemmDesc>& ds) {
   if (!reds.empty()) {
     int64_t mx = 0;
     for (auto& r : reds) mx = std::max(mx, (int64_t)r.M * r.N);
-    auto* dr = (ReduceTask*)c.stage.put(reds.data(), reds.size() * sizeof(ReduceTask), c.s);
-    dim3 grid((unsigned)((mx + 255) / 256), (unsigned)reds.size());
-    k_reduce_parts<<<grid, 256, 0, c.s>>>(dr, (int)reds.size());
-    H2_LAUNCH_CHECK();
+    for (size_t i0 = 0; i0 < reds.size(); i0 += 65535) {
+      const size_t cnt = std::min<size_t>(65535, reds.size() - i0);
+      auto* dr = (ReduceTask*)c.stage.put(reds.data() + i0, cnt * sizeof(ReduceTask), c.s);
+      dim3 grid((unsigned)((mx + 255) / 256), (unsigned)cnt);
+      k_reduce_parts<<<grid, 256, 0, c.s>>>(dr, (int)cnt);
+      H2_LAUNCH_CHECK();
+    }
   }
 }
 
@@ -1185,11 +1204,14 @@ void copy_batched(Ctx& c, const std::vector<CopyDesc>& ds) {
       mx = std::max(mx, (int64_t)d.rows * d.cols);
     }
   if (v.empty()) return;
-  H2_CHECK(v.size() < 65535, H2_EINVAL, "copy batch too large");
-  auto* dd = (CopyDesc*)c.stage.put(v.data(), v.size() * sizeof(CopyDesc), c.s);
-  dim3 grid((unsigned)std::min<int64_t>((mx + 255) / 256, 1024), (unsigned)v.size());
-  k_copy<<<grid, 256, 0, c.s>>>(dd);
-  H2_LAUNCH_CHECK();
+  // one grid row per descriptor: launches of at most 65535 descriptors
+  for (size_t i0 = 0; i0 < v.size(); i0 += 65535) {
+    const size_t cnt = std::min<size_t>(65535, v.size() - i0);
+    auto* dd = (CopyDesc*)c.stage.put(v.data() + i0, cnt * sizeof(CopyDesc), c.s);
+    dim3 grid((unsigned)std::min<int64_t>((mx + 255) / 256, 1024), (unsigned)cnt);
+    k_copy<<<grid, 256, 0, c.s>>>(dd);
+    H2_LAUNCH_CHECK();
+  }
 }
 
 __global__ __launch_bounds__(256) void k_colnorm_max(const CopyDesc* __restrict__ ds,
@@ -1229,13 +1251,15 @@ __global__ void k_scale_cols(const ScaleDesc* __restrict__ ds) {
 
 void scale_columns(Ctx& c, const std::vector<ScaleDesc>& ds) {
   if (ds.empty()) return;
-  H2_CHECK(ds.size() < 65535, H2_EINVAL, "scale batch too large");
   int64_t mx = 0;
   for (auto& d : ds) mx = std::max(mx, (int64_t)d.rows * d.cols);
-  auto* dd = (ScaleDesc*)c.stage.put(ds.data(), ds.size() * sizeof(ScaleDesc), c.s);
-  dim3 grid((unsigned)std::min<int64_t>((mx + 255) / 256, 1024), (unsigned)ds.size());
-  k_scale_cols<<<grid, 256, 0, c.s>>>(dd);
-  H2_LAUNCH_CHECK();
+  for (size_t i0 = 0; i0 < ds.size(); i0 += 65535) {
+    const size_t cnt = std::min<size_t>(65535, ds.size() - i0);
+    auto* dd = (ScaleDesc*)c.stage.put(ds.data() + i0, cnt * sizeof(ScaleDesc), c.s);
+    dim3 grid((unsigned)std::min<int64_t>((mx + 255) / 256, 1024), (unsigned)cnt);
+    k_scale_cols<<<grid, 256, 0, c.s>>>(dd);
+    H2_LAUNCH_CHECK();
+  }
 }
 
 // one block per matrix, one wave per column: arg-max of |x| (first index on

@@ -123,99 +123,143 @@ double residual_norm_device(const h2_matrix* A, const h2_matrix* X, double rel, 
   return power_norm_device(n, op, seed, iteration, rel, 3, max_it, s, nullptr, PHASE_RESID, true);
 }
 
-std::unique_ptr<h2_matrix> ns_iterate(const h2_matrix* A, const h2_ns_opts& o, hipStream_t s,
-                                      h2_ns_stats* st, h2_status* status) {
-  const h2_tree* t = A->tree;
-  const double t_begin = now_ms2();
-  h2_ns_stats local{};
-  h2_ns_stats& stats = st ? *st : local;
-  stats = h2_ns_stats{};
-  const int n = t->n;
-  const double norm_rel = o.norm_rel > 0 ? o.norm_rel : 1e-2;
-  const double resid_rel = o.resid_rel > 0 ? o.resid_rel : 1e-2;
-  const double eps_build = o.eps_build > 0 ? o.eps_build : o.eps / 10.0;
-  H2_CHECK(eps_build > 0, H2_EINVAL, "need eps > 0 or eps_build > 0");
-  auto gop = [&](const double* v, double* w) { gemv_tree_f64(A, 1, 1.0, v, n, 0.0, w, n, s); };
-  const double nuA = power_norm_device(n, gop, o.seed, 0, norm_rel, 3, norm_rel >= 1e-2 ? 30 : 500,
-                                       s, nullptr);
-  H2_CHECK(std::isfinite(nuA) && nuA > 0, H2_ENUMERIC, "norm of A is zero or not finite");
-  stats.norm = nuA;
-  auto X = std::make_unique<h2_matrix>();
-  if (o.x0 == 0) {
-    matrix_identity(X.get(), t, 1.0 / nuA, s);
-  } else {
-    matrix_layout(X.get(), t, A->rank);
-    matrix_alloc(X.get(), H2_FP64);
-    matrix_copy_convert(A, X.get(), 1.0 / (nuA * nuA), s);
-  }
+// Newton-Schulz for several independent matrices in lock step: every
+// iteration evaluates each residual, then rebuilds all unfinished iterates in
+// one batched construction (build_h2_multi).
+struct NSJob {
+  const h2_matrix* A = nullptr;
+  h2_ns_opts o{};
+  h2_ns_stats stats{};
+  h2_status status = H2_ENOTCONVERGED;
+  std::unique_ptr<h2_matrix> X;
+  // state
+  double nuA = 0, prevE = -1, eps_build = 0, norm_rel = 0, resid_rel = 0, switch_E = 0;
+  bool low = false, active = true;
   BuildParams bp;
-  bp.rank_cap = o.rank_cap > 0 ? o.rank_cap : t->leaf;
-  bp.oversample = o.oversample;
-  bp.adaptive = o.adaptive != 0;
-  bp.max_rounds = o.max_rounds;
-  bp.seed = o.seed;
-  bp.norm = 1.0 / nuA;
+  std::unique_ptr<h2_matrix> A32, X32;
+  std::unique_ptr<Sampler> S;
+};
+
+static std::unique_ptr<h2_matrix> to_f32(const h2_matrix* M, hipStream_t s) {
+  auto B = std::make_unique<h2_matrix>();
+  matrix_layout(B.get(), M->tree, M->rank);
+  matrix_alloc(B.get(), H2_FP32);
+  matrix_copy_convert(M, B.get(), 1.0, s);
+  return B;
+}
+
+void ns_iterate_multi(std::vector<NSJob>& jobs, hipStream_t s) {
+  const double t_begin = now_ms2();
+  for (auto& J : jobs) {
+    const h2_ns_opts& o = J.o;
+    const h2_tree* t = J.A->tree;
+    const int n = t->n;
+    J.stats = h2_ns_stats{};
+    J.status = H2_ENOTCONVERGED;
+    J.active = true;
+    J.prevE = -1;
+    J.norm_rel = o.norm_rel > 0 ? o.norm_rel : 1e-2;
+    J.resid_rel = o.resid_rel > 0 ? o.resid_rel : 1e-2;
+    J.eps_build = o.eps_build > 0 ? o.eps_build : o.eps / 10.0;
+    H2_CHECK(J.eps_build > 0, H2_EINVAL, "need eps > 0 or eps_build > 0");
+    const h2_matrix* A = J.A;
+    auto gop = [&](const double* v, double* w) { gemv_tree_f64(A, 1, 1.0, v, n, 0.0, w, n, s); };
+    J.nuA = power_norm_device(n, gop, o.seed, 0, J.norm_rel, 3, J.norm_rel >= 1e-2 ? 30 : 500, s,
+                              nullptr);
+    H2_CHECK(std::isfinite(J.nuA) && J.nuA > 0, H2_ENUMERIC, "norm of A is zero or not finite");
+    J.stats.norm = J.nuA;
+    J.X = std::make_unique<h2_matrix>();
+    if (o.x0 == 0) {
+      matrix_identity(J.X.get(), t, 1.0 / J.nuA, s);
+    } else {
+      matrix_layout(J.X.get(), t, A->rank);
+      matrix_alloc(J.X.get(), H2_FP64);
+      matrix_copy_convert(A, J.X.get(), 1.0 / (J.nuA * J.nuA), s);
+    }
+    J.bp = BuildParams{};
+    J.bp.rank_cap = o.rank_cap > 0 ? o.rank_cap : t->leaf;
+    J.bp.oversample = o.oversample;
+    J.bp.adaptive = o.adaptive != 0;
+    J.bp.max_rounds = o.max_rounds;
+    J.bp.seed = o.seed;
+    J.bp.norm = 1.0 / J.nuA;
+    // mixed precision: FP32 copies of A and of each iterate feed the sampler
+    // until E <= sqrt(eps) (or the iteration stops contracting), then FP64
+    J.low = o.prec == H2_FP32;
+    if (J.low) J.A32 = to_f32(A, s);
+    J.switch_E = std::sqrt(std::max(o.eps, 0.0));
+  }
   Ctx c;
   c.s = s;
-  // mixed precision: FP32 copies of A and of each iterate feed the sampler
-  // until E <= sqrt(eps) (or the iteration stops contracting), then FP64
-  bool low = o.prec == H2_FP32;
-  std::unique_ptr<h2_matrix> A32, X32;
-  auto to_f32 = [&](const h2_matrix* M) {
-    auto B = std::make_unique<h2_matrix>();
-    matrix_layout(B.get(), t, M->rank);
-    matrix_alloc(B.get(), H2_FP32);
-    matrix_copy_convert(M, B.get(), 1.0, s);
-    return B;
-  };
-  if (low) A32 = to_f32(A);
-  const double switch_E = std::sqrt(std::max(o.eps, 0.0));
-  *status = H2_ENOTCONVERGED;
-  int k = 0;
-  double prevE = -1;
-  while (true) {
-    double t0 = now_ms2();
-    const int max_it = resid_rel >= 1e-2 ? 30 : 3000;
-    const double E = residual_norm_device(A, X.get(), resid_rel, max_it, o.seed, (uint32_t)k, s);
-    stats.time_ms[0] += now_ms2() - t0;
-    H2_CHECK(std::isfinite(E), H2_ENUMERIC, "residual is not finite");
-    if (k <= H2_MAX_NS_ITERS) stats.resid[k] = E;
-    if (o.eps > 0 && E <= o.eps) { *status = H2_OK; break; }
-    if (k >= 1 && E > prevE && E > 1.0) { *status = H2_EDIVERGED; break; }
-    if (k >= o.max_iter || k >= H2_MAX_NS_ITERS) break;
-    if (low && (E <= switch_E || (k >= 2 && E < 0.5 && E > 0.5 * prevE))) low = false;
-    prevE = E;
-    const double eps_k = o.dynamic ? std::min(std::max(0.1 * E * E, eps_build), 1e-2) : eps_build;
-    bp.tol = eps_k;
-    bp.iteration = (uint32_t)(k + 1);
-    h2_build_stats bst{};
-    bool conv = true;
-    t0 = now_ms2();
-    std::unique_ptr<h2_matrix> Xn;
-    if (low) {
-      X32 = to_f32(X.get());
-      NSSamplerF32 S(X32.get(), A32.get());
-      Xn = build_h2(t, S, bp, c, &bst, &conv);
-      stats.low_iterations += 1;
-    } else {
-      NSSampler S(X.get(), A);
-      Xn = build_h2(t, S, bp, c, &bst, &conv);
-      if (o.prec == H2_FP32) stats.time_ms[2] += now_ms2() - t0;
+  for (int k = 0;; ++k) {
+    std::vector<BuildJob> bj;
+    std::vector<NSJob*> who;
+    for (auto& J : jobs) {
+      if (!J.active) continue;
+      const h2_ns_opts& o = J.o;
+      double t0 = now_ms2();
+      const int max_it = J.resid_rel >= 1e-2 ? 30 : 3000;
+      const double E = residual_norm_device(J.A, J.X.get(), J.resid_rel, max_it, o.seed,
+                                            (uint32_t)k, s);
+      J.stats.time_ms[0] += now_ms2() - t0;
+      H2_CHECK(std::isfinite(E), H2_ENUMERIC, "residual is not finite");
+      if (k <= H2_MAX_NS_ITERS) J.stats.resid[k] = E;
+      J.stats.iterations = k;
+      if (o.eps > 0 && E <= o.eps) { J.status = H2_OK; J.active = false; continue; }
+      if (k >= 1 && E > J.prevE && E > 1.0) { J.status = H2_EDIVERGED; J.active = false; continue; }
+      if (k >= o.max_iter || k >= H2_MAX_NS_ITERS) { J.active = false; continue; }
+      if (J.low && (E <= J.switch_E || (k >= 2 && E < 0.5 && E > 0.5 * J.prevE))) J.low = false;
+      J.prevE = E;
+      const double eps_k =
+          o.dynamic ? std::min(std::max(0.1 * E * E, J.eps_build), 1e-2) : J.eps_build;
+      J.bp.tol = eps_k;
+      J.bp.iteration = (uint32_t)(k + 1);
+      if (J.low) {
+        J.X32 = to_f32(J.X.get(), s);
+        J.S = std::make_unique<NSSamplerF32>(J.X32.get(), J.A32.get());
+        J.stats.low_iterations += 1;
+      } else {
+        J.S = std::make_unique<NSSampler>(J.X.get(), J.A);
+      }
+      BuildJob b;
+      b.t = J.A->tree;
+      b.S = J.S.get();
+      b.prm = J.bp;
+      bj.push_back(std::move(b));
+      who.push_back(&J);
     }
-    stats.time_ms[1] += now_ms2() - t0;
-    stats.applies[k] = bst.applies;
-    int mr = 0;
-    for (int l = 0; l <= t->L; ++l) mr = std::max(mr, bst.strong_rank[l]);
-    stats.max_rank[k] = mr;
-    X = std::move(Xn);
-    if (verbose())
-      std::fprintf(stderr, "[h2_ns] iteration %d (%s): E %.3e eps_k %.1e applies %lld max rank %d build %.1f ms\n",
-                   k, low ? "fp32" : "fp64", E, eps_k, (long long)bst.applies, mr, now_ms2() - t0);
-    ++k;
+    if (bj.empty()) break;
+    const double t0 = now_ms2();
+    build_h2_multi(bj, c);
+    const double dt = now_ms2() - t0;
+    for (size_t i = 0; i < bj.size(); ++i) {
+      NSJob& J = *who[i];
+      J.stats.time_ms[1] += dt;
+      if (!J.low && J.o.prec == H2_FP32) J.stats.time_ms[2] += dt;
+      J.stats.applies[k] = bj[i].stats.applies;
+      int mr = 0;
+      for (int l = 0; l <= J.A->tree->L; ++l) mr = std::max(mr, bj[i].stats.strong_rank[l]);
+      J.stats.max_rank[k] = mr;
+      J.X = std::move(bj[i].out);
+      J.S.reset();
+      if (verbose())
+        std::fprintf(stderr, "[h2_ns] iteration %d (%s): E %.3e eps_k %.1e applies %lld max rank %d build %.1f ms (%zu problems)\n",
+                     k, J.low ? "fp32" : "fp64", J.prevE, J.bp.tol, (long long)bj[i].stats.applies, mr, dt,
+                     bj.size());
+    }
   }
-  stats.iterations = k;
-  stats.time_ms[3] = now_ms2() - t_begin;
-  return X;
+  for (auto& J : jobs) J.stats.time_ms[3] = now_ms2() - t_begin;
+}
+
+std::unique_ptr<h2_matrix> ns_iterate(const h2_matrix* A, const h2_ns_opts& o, hipStream_t s,
+                                      h2_ns_stats* st, h2_status* status) {
+  std::vector<NSJob> jobs(1);
+  jobs[0].A = A;
+  jobs[0].o = o;
+  ns_iterate_multi(jobs, s);
+  if (st) *st = jobs[0].stats;
+  *status = jobs[0].status;
+  return std::move(jobs[0].X);
 }
 
 }  // namespace h2
@@ -255,6 +299,30 @@ h2_status h2_newton_schulz(const h2_matrix* A, const h2_ns_opts* opts, hipStream
     *X_out = X.release();
   });
   return st != H2_OK ? st : result;
+}
+
+h2_status h2_newton_schulz_batched(int nprob, const h2_matrix* const* A, const h2_ns_opts* opts,
+                                   hipStream_t stream, h2_matrix** X_out, h2_ns_stats* stats,
+                                   h2_status* status) {
+  return guarded_status([&] {
+    H2_CHECK(nprob >= 0 && (nprob == 0 || (A && opts && X_out)), H2_EINVAL, "null argument");
+    std::vector<NSJob> jobs(nprob);
+    for (int i = 0; i < nprob; ++i) {
+      X_out[i] = nullptr;
+      H2_CHECK(A[i] && A[i]->st.prec == H2_FP64, H2_EINVAL, "Newton-Schulz needs FP64 matrices");
+      H2_CHECK(opts[i].max_iter >= 0, H2_EINVAL, "max_iter must be >= 0");
+      H2_CHECK(opts[i].prec == H2_FP64 || opts[i].prec == H2_FP32, H2_EINVAL,
+               "Newton-Schulz precision must be FP64 or FP32");
+      jobs[i].A = A[i];
+      jobs[i].o = opts[i];
+    }
+    ns_iterate_multi(jobs, stream);
+    for (int i = 0; i < nprob; ++i) {
+      if (stats) stats[i] = jobs[i].stats;
+      if (status) status[i] = jobs[i].status;
+      X_out[i] = jobs[i].X.release();
+    }
+  });
 }
 
 h2_status h2_residual_norm(const h2_matrix* A, const h2_matrix* X, double rel, int max_iter,
