@@ -254,6 +254,18 @@ h2_status h2_newton_schulz_batched(int nprob, const h2_matrix* const* A, const h
 /* E = ||I - A X||_2 by the power method on R^T R (four HGEMVs per step) */
 h2_status h2_residual_norm(const h2_matrix* A, const h2_matrix* X, double rel, int max_iter,
                            uint64_t seed, uint32_t iteration, hipStream_t stream, double* out);
+/* The same for nprob (A[i], X[i]) pairs in lock step: one device-to-host
+ * copy per power step for all pairs.  graph != 0: after an eager first step
+ * the step's launch sequence (HGEMVs, copies, norms, normalisations of every
+ * unfinished pair) is captured once per set of unfinished pairs into a HIP
+ * graph and replayed.  out, iters (nullable) have nprob entries; history
+ * (nullable, nprob x max_iter) receives the estimate after every step (0
+ * after a pair stopped).  Newton-Schulz (batched or not) evaluates its
+ * residuals this way with graphs. */
+h2_status h2_residual_norm_batched(int nprob, const h2_matrix* const* A, const h2_matrix* const* X,
+                                   double rel, int max_iter, uint64_t seed, uint32_t iteration,
+                                   int graph, hipStream_t stream, double* out, int* iters,
+                                   double* history);
 
 /* ------------------------------------------------------------------ samplers */
 /*

@@ -391,6 +391,23 @@ def newton_schulz_batched(As, opts_list, stream=None):
     return Xs, infos
 
 
+def residual_norm_batched(As, Xs, rel=1e-2, max_iter=30, seed=1, iteration=0, graph=True,
+                          stream=None):
+    """||I - A_i X_i||_2 for several pairs in lock step; returns (E, iters,
+    history (n x max_iter))."""
+    n = len(As)
+    ah = (C.c_void_p * n)(*[a.handle.value for a in As])
+    xh = (C.c_void_p * n)(*[x.handle.value for x in Xs])
+    out = np.zeros(n)
+    its = np.zeros(n, dtype=np.int32)
+    hist = np.zeros((n, max_iter))
+    check(lib().h2_residual_norm_batched(n, ah, xh, rel, max_iter, seed, iteration,
+                                         1 if graph else 0, _stream(stream), out.ctypes.data,
+                                         its.ctypes.data, hist.ctypes.data),
+          "h2_residual_norm_batched")
+    return out, its, hist
+
+
 def newton_schulz(A, o=None, stream=None):
     """Hierarchical Newton-Schulz (h2_newton_schulz); returns (X, stats dict, status)."""
     if o is None:

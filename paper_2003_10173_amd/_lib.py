@@ -78,6 +78,8 @@ SIGNATURES = {
     "h2_ns_opts_default": (None, [P(H2NSOpts)]),
     "h2_timing_enable": (C.c_int, [C.c_int]),
     "h2_build_batched": (C.c_int, [C.c_int, vp, vp, vp, vp, vp, vp, vp]),
+    "h2_residual_norm_batched": (C.c_int, [C.c_int, vp, vp, dbl, C.c_int, u64, u32, C.c_int, vp,
+                                           vp, vp, vp]),
     "h2_newton_schulz_batched": (C.c_int, [C.c_int, vp, vp, vp, vp, vp, vp]),
     "h2_mlp_create": (C.c_int, [vp, P(vp)]),
     "h2_mlp_params": (C.c_int, [vp, vp]),

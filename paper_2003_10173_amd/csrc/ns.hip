@@ -105,22 +105,62 @@ struct GemvSampler : Sampler {
   }
 };
 
+// E = ||I - A X||_2 by the power method on R^T R (R v = v - A (X v),
+// R^T w = w - X (A w)) for several (A, X) pairs in lock step
+struct ResidJob {
+  const h2_matrix* A;
+  const h2_matrix* X;
+  double rel;
+  int max_it;
+  uint64_t seed;
+  uint32_t iteration;
+  double E = 0;
+  int iters = 0;
+  std::vector<double> history;
+};
+
+void residual_norm_multi(std::vector<ResidJob>& rj, hipStream_t s, bool graph) {
+  std::vector<DevBuf> tmp(rj.size());
+  std::vector<PowerJob> pj(rj.size());
+  for (size_t i = 0; i < rj.size(); ++i) {
+    const h2_matrix* A = rj[i].A;
+    const h2_matrix* X = rj[i].X;
+    const int n = A->tree->n;
+    tmp[i].alloc((size_t)2 * n * sizeof(double));
+    double* t1 = tmp[i].as<double>();
+    double* r = t1 + n;
+    PowerJob& J = pj[i];
+    J.n = n;
+    J.op = [A, X, n, t1, r](const double* v, double* w, hipStream_t st) {
+      // r = v - A (X v);  w = r - X (A r)
+      gemv_tree_f64(X, 1, 1.0, v, n, 0.0, t1, n, st);
+      H2_HIP(hipMemcpyAsync(r, v, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, st));
+      gemv_tree_f64(A, 1, -1.0, t1, n, 1.0, r, n, st);
+      gemv_tree_f64(A, 1, 1.0, r, n, 0.0, t1, n, st);
+      H2_HIP(hipMemcpyAsync(w, r, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, st));
+      gemv_tree_f64(X, 1, -1.0, t1, n, 1.0, w, n, st);
+    };
+    J.seed = rj[i].seed;
+    J.iteration = rj[i].iteration;
+    J.phase = PHASE_RESID;
+    J.rel = rj[i].rel;
+    J.min_it = 3;
+    J.max_it = rj[i].max_it;
+    J.sqrt_out = true;
+  }
+  power_norm_multi(pj, s, graph);
+  for (size_t i = 0; i < rj.size(); ++i) {
+    rj[i].E = pj[i].result;
+    rj[i].iters = pj[i].iters;
+    rj[i].history = std::move(pj[i].history);
+  }
+}
+
 double residual_norm_device(const h2_matrix* A, const h2_matrix* X, double rel, int max_it,
                             uint64_t seed, uint32_t iteration, hipStream_t s) {
-  const int n = A->tree->n;
-  DevBuf tmp((size_t)2 * n * sizeof(double));
-  double* t1 = tmp.as<double>();
-  double* r = t1 + n;
-  auto op = [&](const double* v, double* w) {
-    // r = v - A (X v);  w = r - X (A r)
-    gemv_tree_f64(X, 1, 1.0, v, n, 0.0, t1, n, s);
-    H2_HIP(hipMemcpyAsync(r, v, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, s));
-    gemv_tree_f64(A, 1, -1.0, t1, n, 1.0, r, n, s);
-    gemv_tree_f64(A, 1, 1.0, r, n, 0.0, t1, n, s);
-    H2_HIP(hipMemcpyAsync(w, r, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, s));
-    gemv_tree_f64(X, 1, -1.0, t1, n, 1.0, w, n, s);
-  };
-  return power_norm_device(n, op, seed, iteration, rel, 3, max_it, s, nullptr, PHASE_RESID, true);
+  std::vector<ResidJob> rj{{A, X, rel, max_it, seed, iteration}};
+  residual_norm_multi(rj, s, false);
+  return rj[0].E;
 }
 
 // Newton-Schulz for several independent matrices in lock step: every
@@ -194,14 +234,26 @@ void ns_iterate_multi(std::vector<NSJob>& jobs, hipStream_t s) {
   for (int k = 0;; ++k) {
     std::vector<BuildJob> bj;
     std::vector<NSJob*> who;
-    for (auto& J : jobs) {
-      if (!J.active) continue;
+    // residuals of every unfinished problem in lock step, the power steps
+    // replayed from a captured graph
+    std::vector<ResidJob> rj;
+    std::vector<NSJob*> rw;
+    for (auto& J : jobs)
+      if (J.active) {
+        rj.push_back({J.A, J.X.get(), J.resid_rel, J.resid_rel >= 1e-2 ? 30 : 3000, J.o.seed,
+                      (uint32_t)k});
+        rw.push_back(&J);
+      }
+    {
+      const double t0 = now_ms2();
+      residual_norm_multi(rj, s, true);
+      const double dt = now_ms2() - t0;
+      for (NSJob* J : rw) J->stats.time_ms[0] += dt;
+    }
+    for (size_t q = 0; q < rw.size(); ++q) {
+      NSJob& J = *rw[q];
       const h2_ns_opts& o = J.o;
-      double t0 = now_ms2();
-      const int max_it = J.resid_rel >= 1e-2 ? 30 : 3000;
-      const double E = residual_norm_device(J.A, J.X.get(), J.resid_rel, max_it, o.seed,
-                                            (uint32_t)k, s);
-      J.stats.time_ms[0] += now_ms2() - t0;
+      const double E = rj[q].E;
       H2_CHECK(std::isfinite(E), H2_ENUMERIC, "residual is not finite");
       if (k <= H2_MAX_NS_ITERS) J.stats.resid[k] = E;
       J.stats.iterations = k;
@@ -321,6 +373,31 @@ h2_status h2_newton_schulz_batched(int nprob, const h2_matrix* const* A, const h
       if (stats) stats[i] = jobs[i].stats;
       if (status) status[i] = jobs[i].status;
       X_out[i] = jobs[i].X.release();
+    }
+  });
+}
+
+h2_status h2_residual_norm_batched(int nprob, const h2_matrix* const* A, const h2_matrix* const* X,
+                                   double rel, int max_iter, uint64_t seed, uint32_t iteration,
+                                   int graph, hipStream_t stream, double* out, int* iters,
+                                   double* history) {
+  return guarded_status([&] {
+    H2_CHECK(nprob >= 0 && (nprob == 0 || (A && X && out)), H2_EINVAL, "null argument");
+    std::vector<ResidJob> rj;
+    const int mi = max_iter > 0 ? max_iter : 30;
+    for (int i = 0; i < nprob; ++i) {
+      H2_CHECK(A[i] && X[i] && A[i]->tree == X[i]->tree, H2_EINVAL, "A and X must share a tree");
+      H2_CHECK(A[i]->st.prec == H2_FP64 && X[i]->st.prec == H2_FP64, H2_EINVAL,
+               "FP64 matrices needed");
+      rj.push_back({A[i], X[i], rel > 0 ? rel : 1e-2, mi, seed, iteration});
+    }
+    residual_norm_multi(rj, stream, graph != 0);
+    for (int i = 0; i < nprob; ++i) {
+      out[i] = rj[i].E;
+      if (iters) iters[i] = rj[i].iters;
+      if (history)
+        for (int q = 0; q < mi; ++q)
+          history[(size_t)i * mi + q] = q < (int)rj[i].history.size() ? rj[i].history[q] : 0.0;
     }
   });
 }

@@ -25,4 +25,25 @@ double power_norm_device(int n, const std::function<void(const double*, double*)
                          uint64_t seed, uint32_t iteration, double rel, int min_it, int max_it,
                          hipStream_t s, int* iters, int phase = PHASE_NORM, bool sqrt_out = false);
 
+// Power iterations of several symmetric operators in lock step: each step
+// enqueues every unfinished job's w = op(v), |w| and v = w / |w| on the
+// device, then one copy of all norms to the host decides which jobs stop.
+// op must enqueue on the stream it is given.  graph: after an eager first
+// step (which sizes the operators' workspaces) the step's launch sequence is
+// captured once per set of unfinished jobs and replayed.
+struct PowerJob {
+  int n = 0;
+  std::function<void(const double*, double*, hipStream_t)> op;
+  uint64_t seed = 1;
+  uint32_t iteration = 0;
+  int phase = PHASE_NORM;
+  double rel = 1e-2;
+  int min_it = 3, max_it = 30;
+  bool sqrt_out = false;
+  double result = 0;            // norm (or its square root with sqrt_out)
+  int iters = 0;
+  std::vector<double> history;  // the value after every step
+};
+void power_norm_multi(std::vector<PowerJob>& jobs, hipStream_t s, bool graph);
+
 }  // namespace h2

@@ -84,31 +84,146 @@ void axpby(int n, int ncols, double a, const double* x, int ldx, double b, doubl
   H2_LAUNCH_CHECK();
 }
 
+// v = w / sqrt(ss[0]) (v = 0 when ss[0] is zero)
+__global__ void k_normalize(int n, const double* __restrict__ w, const double* __restrict__ ss,
+                            double* __restrict__ v) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double nrm = sqrt(ss[0]);
+  v[i] = nrm > 0.0 ? w[i] / nrm : 0.0;
+}
+
+namespace {
+// device buffers of one job: v, w and the sum of squares of w
+struct PowerBufs {
+  DevBuf vw;
+  double* v = nullptr;
+  double* w = nullptr;
+};
+
+void enqueue_step(PowerJob& J, PowerBufs& B, double* ss, hipStream_t s) {
+  J.op(B.v, B.w, s);
+  k_sumsq<<<1, 1024, 0, s>>>(J.n, B.w, ss);
+  k_normalize<<<(J.n + 255) / 256, 256, 0, s>>>(J.n, B.w, ss, B.v);
+}
+}  // namespace
+
+void power_norm_multi(std::vector<PowerJob>& jobs, hipStream_t s, bool graph) {
+  const int nj = (int)jobs.size();
+  if (nj == 0) return;
+  std::vector<PowerBufs> B(nj);
+  DevBuf ssb((size_t)nj * sizeof(double));
+  double* ss = ssb.as<double>();
+  std::vector<double> hs(nj);
+  // start vectors: Gaussian, normalised
+  for (int j = 0; j < nj; ++j) {
+    PowerJob& J = jobs[j];
+    B[j].vw.alloc((size_t)2 * J.n * sizeof(double));
+    B[j].v = B[j].vw.as<double>();
+    B[j].w = B[j].v + J.n;
+    gauss_fill(stream_key(J.seed, J.phase, 0, 0, J.iteration), J.n, 1, 0, B[j].v, J.n, s);
+    k_sumsq<<<1, 1024, 0, s>>>(J.n, B[j].v, ss + j);
+    k_normalize<<<(J.n + 255) / 256, 256, 0, s>>>(J.n, B[j].v, ss + j, B[j].v);
+    H2_LAUNCH_CHECK();
+    J.result = 0;
+    J.iters = 0;
+    J.history.clear();
+  }
+  H2_HIP(hipMemcpyAsync(hs.data(), ss, nj * sizeof(double), hipMemcpyDeviceToHost, s));
+  H2_HIP(hipStreamSynchronize(s));
+  for (int j = 0; j < nj; ++j)
+    H2_CHECK(std::isfinite(hs[j]) && hs[j] > 0, H2_ENUMERIC, "power method start vector is degenerate");
+  std::vector<char> active(nj, 1);
+  std::vector<double> prev(nj, -1.0);
+  // the captured step of the current active set (re-captured when it changes)
+  hipStream_t cap = nullptr;
+  hipGraphExec_t exec = nullptr;
+  std::vector<char> exec_set;
+  auto drop_graph = [&]() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    exec = nullptr;
+  };
+  try {
+    for (int it = 1;; ++it) {
+      bool any = false;
+      for (int j = 0; j < nj; ++j) any = any || active[j];
+      if (!any) break;
+      // the first step runs eagerly (it sizes the operators' workspaces)
+      const bool use_graph = graph && it >= 2;
+      if (use_graph) {
+        if (!exec || exec_set != active) {
+          drop_graph();
+          if (!cap) H2_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+          hipGraph_t g = nullptr;
+          H2_HIP(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
+          try {
+            for (int j = 0; j < nj; ++j)
+              if (active[j]) enqueue_step(jobs[j], B[j], ss + j, cap);
+          } catch (...) {
+            (void)hipStreamEndCapture(cap, &g);
+            if (g) (void)hipGraphDestroy(g);
+            throw;
+          }
+          H2_HIP(hipStreamEndCapture(cap, &g));
+          const hipError_t e = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
+          (void)hipGraphDestroy(g);
+          H2_HIP(e);
+          exec_set = active;
+        }
+        H2_HIP(hipGraphLaunch(exec, s));
+      } else {
+        for (int j = 0; j < nj; ++j)
+          if (active[j]) enqueue_step(jobs[j], B[j], ss + j, s);
+        H2_LAUNCH_CHECK();
+      }
+      H2_HIP(hipMemcpyAsync(hs.data(), ss, nj * sizeof(double), hipMemcpyDeviceToHost, s));
+      H2_HIP(hipStreamSynchronize(s));
+      for (int j = 0; j < nj; ++j) {
+        if (!active[j]) continue;
+        PowerJob& J = jobs[j];
+        const double nu = std::sqrt(hs[j]);
+        H2_CHECK(std::isfinite(nu), H2_ENUMERIC, "power method met a non-finite value");
+        J.iters = it;
+        if (nu == 0.0) {
+          J.result = 0.0;
+          active[j] = 0;
+          continue;
+        }
+        const double val = J.sqrt_out ? std::sqrt(nu) : nu;
+        J.result = val;
+        J.history.push_back(val);
+        if ((prev[j] >= 0 && it >= J.min_it && std::fabs(val - prev[j]) <= J.rel * val) ||
+            it >= J.max_it)
+          active[j] = 0;
+        prev[j] = val;
+      }
+    }
+  } catch (...) {
+    drop_graph();
+    if (cap) (void)hipStreamDestroy(cap);
+    throw;
+  }
+  drop_graph();
+  if (cap) H2_HIP(hipStreamDestroy(cap));
+}
+
 double power_norm_device(int n, const std::function<void(const double*, double*)>& op,
                          uint64_t seed, uint32_t iteration, double rel, int min_it, int max_it,
                          hipStream_t s, int* iters, int phase, bool sqrt_out) {
-  DevBuf vb((size_t)2 * n * sizeof(double));
-  double* v = vb.as<double>();
-  double* w = v + n;
-  gauss_fill(stream_key(seed, phase, 0, 0, iteration), n, 1, 0, v, n, s);
-  double nv = nrm2(n, v, s);
-  H2_CHECK(std::isfinite(nv) && nv > 0, H2_ENUMERIC, "power method start vector is degenerate");
-  scal(n, 1.0 / nv, v, s);
-  double prev = -1.0, val = 0.0;
-  int it = 0;
-  for (it = 1; it <= max_it; ++it) {
-    op(v, w);
-    double nu = nrm2(n, w, s);
-    H2_CHECK(std::isfinite(nu), H2_ENUMERIC, "power method met a non-finite value");
-    if (nu == 0.0) { val = 0.0; break; }
-    H2_HIP(hipMemcpyAsync(v, w, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, s));
-    scal(n, 1.0 / nu, v, s);
-    val = sqrt_out ? std::sqrt(nu) : nu;
-    if (prev >= 0 && it >= min_it && std::fabs(val - prev) <= rel * val) break;
-    prev = val;
-  }
-  if (iters) *iters = std::min(it, max_it);
-  return val;
+  std::vector<PowerJob> jobs(1);
+  PowerJob& J = jobs[0];
+  J.n = n;
+  J.op = [&](const double* v, double* w, hipStream_t) { op(v, w); };
+  J.seed = seed;
+  J.iteration = iteration;
+  J.phase = phase;
+  J.rel = rel;
+  J.min_it = min_it;
+  J.max_it = max_it;
+  J.sqrt_out = sqrt_out;
+  power_norm_multi(jobs, s, false);
+  if (iters) *iters = J.iters;
+  return J.result;
 }
 
 }  // namespace h2

@@ -84,3 +84,19 @@ def test_build_batched_rejects_bad_problem():
     opts[1].tol = 2.0
     with pytest.raises(h2.H2Error):
         h2.build_batched(trees, samp, opts)
+
+
+def test_residual_graph_replays_match_eager():
+    """The lock-step power method replays each step from a captured HIP graph
+    (re-captured when a pair finishes); every step's estimate must equal the
+    eager launches' value, and each pair must equal its own single run."""
+    ps = problems(4, nmax=3000)
+    trees, samp, opts = setup(ps)
+    mats, _, _ = h2.build_batched(trees, samp, opts)
+    Xs = [h2.H2Matrix.identity(trees[i], 1.0 / (2.0 + i)) for i in range(len(ps))]
+    Eg, ig, hg = h2.residual_norm_batched(mats, Xs, rel=1e-6, max_iter=40, seed=3, graph=True)
+    Ee, ie, he = h2.residual_norm_batched(mats, Xs, rel=1e-6, max_iter=40, seed=3, graph=False)
+    assert np.array_equal(ig, ie) and np.array_equal(hg, he) and np.array_equal(Eg, Ee)
+    assert len(set(ig.tolist())) > 1      # pairs stopped at different steps: re-captures ran
+    for i in range(len(ps)):
+        assert h2.residual_norm(mats[i], Xs[i], rel=1e-6, max_iter=40, seed=3) == Eg[i]
