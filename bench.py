@@ -141,6 +141,34 @@ def learned_form(h2, torch, si):
     return out
 
 
+def batched_form(h2, torch, si, count=32):
+    """Construction of `count` uneven 2D kernel Hessians (N log-uniform in
+    [1024, 16384] on random-aspect grids, ell ~ U[0.02, 0.2], cap 32, eps 1e-4)
+    in one level-synchronous batch against one build after the other."""
+    ps = si.config_batch(count)
+    trees = [h2.Tree(p["points"], p["leaf"], p["eta"]) for p in ps]
+    samp = [h2.KernelSampler(p["points"], p["ell"], p["shift"]) for p in ps]
+    opts = [h2.opts(rank_cap=p["cap"], oversample=p["p"], tol=p["tol"], adaptive=1, max_rounds=16,
+                    seed=p["seed"]) for p in ps]
+    h2.build(trees[0], samp[0], opts[0])       # warm-up (allocations, tile tuning)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    h2.build_batched(trees, samp, opts)
+    torch.cuda.synchronize()
+    tb = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    for i in range(count):
+        h2.build(trees[i], samp[i], opts[i])
+    torch.cuda.synchronize()
+    ts = time.perf_counter() - t0
+    print("batched form: %d problems, batched %.2f s, sequential %.2f s" % (count, tb, ts),
+          file=sys.stderr, flush=True)
+    return {"workload": "%d uneven kernel2d Hessians (N %d..%d, total %d), cap 32, eps 1e-4, build"
+                        % (count, min(p["n"] for p in ps), max(p["n"] for p in ps),
+                           sum(p["n"] for p in ps)),
+            "batched_s": round(tb, 3), "sequential_s": round(ts, 3), "speedup": round(ts / tb, 3)}
+
+
 def cpu_baseline(cfg, gpu_iters):
     """Oracle timed on a bounded sample: the full FP64 build of the Hessian plus
     one Newton-Schulz iteration, extrapolated to the GPU's iteration count."""
@@ -281,7 +309,8 @@ def main():
                  "mixed_iterations": nm["iterations"], "mixed_fp32_iterations": nm["low_iterations"],
                  "mixed_residual": nm["resid"][-1],
                  "precision_ladder": precision_ladder(h2, torch, si, stream),
-                 "learned": learned_form(h2, torch, si)}
+                 "learned": learned_form(h2, torch, si),
+                 "batched": batched_form(h2, torch, si)}
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -35,6 +35,12 @@ h2_status h2_test_svd(int m, int n, const double* A, double* sigma, double* U, d
    1: f32 16x16x4, 2: bf16 16x16x16) of known operands; out[lane*4 + reg]
    (256 values) -- pins the operand and result lane layouts the kernels use */
 h2_status h2_test_mfma_layout(int kind, double* out);
+/* y = A x (FP64, user order, ld n, device pointers) with the matrix-core tile
+   width fixed to nt (1, 2, 4 sixteen-vector tiles per workgroup; 0: tuned) */
+h2_status h2_test_gemv_tile(const h2_matrix* A, int nv, const double* x, double* y, int nt);
+/* the tile width the autotuner chose for FP64 products with nv vectors on
+   A's tree (0: not tuned yet) */
+int h2_test_tuned_tile(const h2_matrix* A, int nv);
 h2_status h2_test_svd_batch(int count, const int* m, const int* n, const double* A, double* sigma,
                             double* U, double* V);
 /* keep the weak factors of subsequent h2_build calls on this thread (1) or not (0) */

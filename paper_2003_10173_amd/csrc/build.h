@@ -37,6 +37,9 @@ struct BuildParams {
   double norm = 0;        // > 0: use as ||A||_2; else estimate
   double norm_rel = 1e-2;
   const h2_mlp* mlp = nullptr;  // rank predictor for the first round (adaptive mode)
+  // numerical-rank cut of the range basis, relative to the largest singular
+  // value of the samples: above the sampler's rounding level
+  double rank_cut = 1e-13;
 };
 
 // Peeling on the weak partition + recompression into the strong H2 of `t`.

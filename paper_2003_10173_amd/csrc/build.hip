@@ -602,7 +602,7 @@ void build_h2_multi(std::vector<BuildJob>& jobs, Ctx& c) {
     t_sample += now_ms() - t0;
 
     // ---- range basis: Z = Qe (Qe^T Z); SVD of Qe^T Z, singular values above
-    // 1e-13 sigma_1 (the left singular vectors of the samples)
+    // rank_cut sigma_1 (the left singular vectors of the samples)
     t0 = now_ms();
     {
       std::vector<GemmDesc> g;
@@ -644,7 +644,7 @@ void build_h2_multi(std::vector<BuildJob>& jobs, Ctx& c) {
           int k = 0;
           if (s->kq[p] > 0 && sv[0] > 0) {
             H2_CHECK(std::isfinite(sv[0]), H2_ENUMERIC, "non-finite singular values");
-            while (k < s->kq[p] && sv[k] > 1e-13 * sv[0]) ++k;
+            while (k < s->kq[p] && sv[k] > s->prm->rank_cut * sv[0]) ++k;
           }
           s->k0[p] = k;
           s->K0 = std::max(s->K0, k);

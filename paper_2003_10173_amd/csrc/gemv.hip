@@ -11,6 +11,7 @@
 //   concatenated in global order (offset kpre[c] * nv)
 //   multivectors: tree order, column-major (ld >= n)
 #include <algorithm>
+#include <cstdio>
 #include <cstring>
 #include <type_traits>
 
@@ -511,9 +512,38 @@ static constexpr bool has_mfma() {
          (std::is_same<M, bf16_t>::value && std::is_same<V, float>::value);
 }
 
+// launches of the matrix-core stages with NT 16-column tiles per workgroup
+template <class M, class V, int NT>
+static void up_leaf_nt(const h2_matrix* A, int nv, const V* xt, int ldx, V* xh, hipStream_t s) {
+  const h2_tree* t = A->tree;
+  const unsigned gy = (unsigned)((nv + 16 * NT - 1) / (16 * NT));
+  k_up_leaf_mfma<M, V, NT><<<dim3(1 << t->L, gy), 256, 0, s>>>(
+      t->L, t->d_cstart.as<int32_t>(), t->d_csize.as<int32_t>(), A->d_rank.as<int32_t>(),
+      A->d_kpre.as<int64_t>(), A->d_U_off.as<int64_t>(), A->st.U.as<M>(), xt, ldx, nv, xh);
+}
+template <class M, class V, int NT>
+static void coupling_nt(const h2_matrix* A, int nv, const V* xh, V* yh, hipStream_t s) {
+  const h2_tree* t = A->tree;
+  const unsigned gy = (unsigned)((nv + 16 * NT - 1) / (16 * NT));
+  k_coupling_mfma<M, V, NT><<<dim3(t->nclusters() - 1, gy), 256, 0, s>>>(
+      A->d_rank.as<int32_t>(), A->d_kpre.as<int64_t>(), t->d_far_ptr.as<int32_t>(),
+      t->d_far_col.as<int32_t>(), A->d_S_off.as<int64_t>(), A->st.S.as<M>(), nv, xh, yh);
+}
+template <class M, class V, int NT>
+static void leaf_nt(const h2_matrix* A, int nv, V alpha, const V* xt, int ldx, V beta, V* yt,
+                    int ldy, const V* yh, hipStream_t s) {
+  const h2_tree* t = A->tree;
+  const unsigned gy = (unsigned)((nv + 16 * NT - 1) / (16 * NT));
+  k_leaf_mfma<M, V, NT><<<dim3(1 << t->L, gy), 256, 0, s>>>(
+      t->L, t->d_cstart.as<int32_t>(), t->d_csize.as<int32_t>(), A->d_rank.as<int32_t>(),
+      A->d_kpre.as<int64_t>(), A->d_U_off.as<int64_t>(), A->st.U.as<M>(),
+      t->d_near_ptr.as<int32_t>(), t->d_near_col.as<int32_t>(), A->d_D_off.as<int64_t>(),
+      A->st.D.as<M>(), nv, yh, xt, ldx, alpha, beta, yt, ldy);
+}
+
 template <class M, class V>
-static void gemv_tree_impl(const h2_matrix* A, int nv, V alpha, const V* xt, int ldx, V beta,
-                           V* yt, int ldy, hipStream_t s) {
+static void gemv_tree_run(const h2_matrix* A, int nv, V alpha, const V* xt, int ldx, V beta,
+                          V* yt, int ldy, hipStream_t s, int nt) {
   const h2_tree* t = A->tree;
   const int L = t->L;
   const int64_t ktot = A->kpre.back();
@@ -531,19 +561,12 @@ static void gemv_tree_impl(const h2_matrix* A, int nv, V alpha, const V* xt, int
   const int32_t* csize = t->d_csize.as<int32_t>();
   // matrix cores for the dense contractions when every block fits the 64 x 64 tiles
   // (leaves are at most 64 points; ranks above 64 take the scalar kernels)
-  const bool mf = has_mfma<M, V>() && A->kmax <= LEAF_MAX;
-  const bool wide = nv > 32;
-  const unsigned gy = wide ? (unsigned)((nv + 63) / 64) : (unsigned)((nv + 31) / 32);
+  const bool mf = nt > 0;
   if (ktot > 0 && L >= 1) {
     if constexpr (has_mfma<M, V>()) {
-      if (mf) {
-        if (wide)
-          k_up_leaf_mfma<M, V, 4><<<dim3(1 << L, gy), 256, 0, s>>>(
-              L, cstart, csize, rank, kpre, A->d_U_off.as<int64_t>(), U, xt, ldx, nv, xh);
-        else
-          k_up_leaf_mfma<M, V, 2><<<dim3(1 << L, gy), 256, 0, s>>>(
-              L, cstart, csize, rank, kpre, A->d_U_off.as<int64_t>(), U, xt, ldx, nv, xh);
-      }
+      if (nt == 1) up_leaf_nt<M, V, 1>(A, nv, xt, ldx, xh, s);
+      else if (nt == 2) up_leaf_nt<M, V, 2>(A, nv, xt, ldx, xh, s);
+      else if (nt == 4) up_leaf_nt<M, V, 4>(A, nv, xt, ldx, xh, s);
     }
     if (!mf)
       k_up_leaf<M, V><<<1 << L, 256, 0, s>>>(L, cstart, csize, rank, kpre,
@@ -551,63 +574,103 @@ static void gemv_tree_impl(const h2_matrix* A, int nv, V alpha, const V* xt, int
     for (int l = L - 1; l >= 1; --l)
       k_up_transfer<M, V><<<1 << l, 256, 0, s>>>(l, rank, kpre, A->d_E_off.as<int64_t>(), E, nv,
                                                   xh);
-    const int32_t* fp = t->d_far_ptr.as<int32_t>();
-    const int32_t* fc = t->d_far_col.as<int32_t>();
-    const int64_t* so = A->d_S_off.as<int64_t>();
     if constexpr (has_mfma<M, V>()) {
-      if (mf) {
-        if (wide)
-          k_coupling_mfma<M, V, 4><<<dim3(t->nclusters() - 1, gy), 256, 0, s>>>(
-              rank, kpre, fp, fc, so, S, nv, xh, yh);
-        else
-          k_coupling_mfma<M, V, 2><<<dim3(t->nclusters() - 1, gy), 256, 0, s>>>(
-              rank, kpre, fp, fc, so, S, nv, xh, yh);
-      }
+      if (nt == 1) coupling_nt<M, V, 1>(A, nv, xh, yh, s);
+      else if (nt == 2) coupling_nt<M, V, 2>(A, nv, xh, yh, s);
+      else if (nt == 4) coupling_nt<M, V, 4>(A, nv, xh, yh, s);
     }
     if (!mf)
-      k_coupling<M, V><<<t->nclusters() - 1, 256, 0, s>>>(rank, kpre, fp, fc, so, S, nv, xh, yh);
+      k_coupling<M, V><<<t->nclusters() - 1, 256, 0, s>>>(
+          rank, kpre, t->d_far_ptr.as<int32_t>(), t->d_far_col.as<int32_t>(),
+          A->d_S_off.as<int64_t>(), S, nv, xh, yh);
     for (int l = 2; l <= L; ++l)
       k_down_transfer<M, V><<<1 << l, 256, 0, s>>>(l, rank, kpre, A->d_E_off.as<int64_t>(), E, nv,
                                                     yh);
   }
-  const int32_t* np_ = t->d_near_ptr.as<int32_t>();
-  const int32_t* nc_ = t->d_near_col.as<int32_t>();
-  const int64_t* doff = A->d_D_off.as<int64_t>();
-  const int64_t* uoff = A->d_U_off.as<int64_t>();
   if constexpr (has_mfma<M, V>()) {
-    if (mf) {
-      if (wide)
-        k_leaf_mfma<M, V, 4><<<dim3(1 << L, gy), 256, 0, s>>>(
-            L, cstart, csize, rank, kpre, uoff, U, np_, nc_, doff, D, nv, yh, xt, ldx, alpha, beta,
-            yt, ldy);
-      else
-        k_leaf_mfma<M, V, 2><<<dim3(1 << L, gy), 256, 0, s>>>(
-            L, cstart, csize, rank, kpre, uoff, U, np_, nc_, doff, D, nv, yh, xt, ldx, alpha, beta,
-            yt, ldy);
-    }
+    if (nt == 1) leaf_nt<M, V, 1>(A, nv, alpha, xt, ldx, beta, yt, ldy, yh, s);
+    else if (nt == 2) leaf_nt<M, V, 2>(A, nv, alpha, xt, ldx, beta, yt, ldy, yh, s);
+    else if (nt == 4) leaf_nt<M, V, 4>(A, nv, alpha, xt, ldx, beta, yt, ldy, yh, s);
   }
   if (!mf) {
     dim3 grid(1 << L, (nv + NVC - 1) / NVC);
-    k_leaf_out<M, V><<<grid, 256, 0, s>>>(L, cstart, csize, rank, kpre, uoff, U, np_, nc_, doff, D,
-                                          nv, yh, xt, ldx, alpha, beta, yt, ldy);
+    k_leaf_out<M, V><<<grid, 256, 0, s>>>(L, cstart, csize, rank, kpre, A->d_U_off.as<int64_t>(), U,
+                                          t->d_near_ptr.as<int32_t>(), t->d_near_col.as<int32_t>(),
+                                          A->d_D_off.as<int64_t>(), D, nv, yh, xt, ldx, alpha,
+                                          beta, yt, ldy);
   }
   H2_LAUNCH_CHECK();
 }
 
+// Tile-width autotuner: on the first product on a tree with a given class of
+// vector counts (ceil(nv / 16), capped at 4) and precisions, every width of
+// 16, 32 or 64 vectors per workgroup that the count can use is timed with HIP
+// events (two runs each into a scratch output, after one untimed run) and the
+// fastest is kept with the tree for the matrices built on it.
+// Under stream capture nothing is timed and a width from the vector count
+// is used instead.  Every width gives the same result (the same products
+// summed in the same order).
+template <class M, class V>
+static int tile_width(const h2_matrix* A, int nv, const V* xt, int ldx, hipStream_t s) {
+  if (!(has_mfma<M, V>() && A->kmax <= LEAF_MAX)) return 0;
+  const std::tuple<int, int, int> key{std::min((nv + 15) / 16, 4), (int)sizeof(M), (int)sizeof(V)};
+  auto it = A->tree->tuned_nt.find(key);
+  if (it != A->tree->tuned_nt.end()) return it->second;
+  const int heur = nv <= 16 ? 1 : (nv <= 32 ? 2 : 4);
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  H2_HIP(hipStreamIsCapturing(s, &cs));
+  if (cs != hipStreamCaptureStatusNone) return heur;
+  const int n = A->tree->n;
+  DevBuf ytmp((size_t)n * nv * sizeof(V));
+  hipEvent_t e0, e1;
+  H2_HIP(hipEventCreate(&e0));
+  H2_HIP(hipEventCreate(&e1));
+  int best = heur;
+  float best_ms = 1e30f;
+  for (int nt : {1, 2, 4}) {
+    if (nt > 1 && 16 * (nt / 2) >= nv) break;   // wider tiles would only add padding
+    gemv_tree_run<M, V>(A, nv, V(1), xt, ldx, V(0), ytmp.as<V>(), n, s, nt);
+    H2_HIP(hipEventRecord(e0, s));
+    for (int r = 0; r < 2; ++r) gemv_tree_run<M, V>(A, nv, V(1), xt, ldx, V(0), ytmp.as<V>(), n, s, nt);
+    H2_HIP(hipEventRecord(e1, s));
+    H2_HIP(hipEventSynchronize(e1));
+    float ms = 0;
+    H2_HIP(hipEventElapsedTime(&ms, e0, e1));
+    if (ms < best_ms) { best_ms = ms; best = nt; }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  A->tree->tuned_nt[key] = best;
+  if (verbose()) std::fprintf(stderr, "  [hgemv] n %d nv %d: tile width %d vectors\n", n, nv, 16 * best);
+  return best;
+}
+
+template <class M, class V>
+static void gemv_tree_impl(const h2_matrix* A, int nv, V alpha, const V* xt, int ldx, V beta,
+                           V* yt, int ldy, hipStream_t s, int nt_force) {
+  int nt = 0;
+  if (has_mfma<M, V>() && A->kmax <= LEAF_MAX) {
+    H2_CHECK(nt_force == 0 || nt_force == 1 || nt_force == 2 || nt_force == 4, H2_EINVAL,
+             "tile width must be 1, 2 or 4 tiles");
+    nt = nt_force ? nt_force : tile_width<M, V>(A, nv, xt, ldx, s);
+  }
+  gemv_tree_run<M, V>(A, nv, alpha, xt, ldx, beta, yt, ldy, s, nt);
+}
+
 void gemv_tree_f64(const h2_matrix* A, int nv, double alpha, const double* xt, int ldx,
-                   double beta, double* yt, int ldy, hipStream_t s) {
+                   double beta, double* yt, int ldy, hipStream_t s, int nt_force) {
   if (nv <= 0) return;
   H2_CHECK(A->st.prec == H2_FP64, H2_EINVAL, "FP64 HGEMV needs an FP64 matrix");
-  gemv_tree_impl<double, double>(A, nv, alpha, xt, ldx, beta, yt, ldy, s);
+  gemv_tree_impl<double, double>(A, nv, alpha, xt, ldx, beta, yt, ldy, s, nt_force);
 }
 
 void gemv_tree_f32(const h2_matrix* A, int nv, float alpha, const float* xt, int ldx, float beta,
-                   float* yt, int ldy, hipStream_t s) {
+                   float* yt, int ldy, hipStream_t s, int nt_force) {
   if (nv <= 0) return;
   switch (A->st.prec) {
-    case H2_FP64: gemv_tree_impl<double, float>(A, nv, alpha, xt, ldx, beta, yt, ldy, s); break;
-    case H2_FP32: gemv_tree_impl<float, float>(A, nv, alpha, xt, ldx, beta, yt, ldy, s); break;
-    case H2_BF16: gemv_tree_impl<bf16_t, float>(A, nv, alpha, xt, ldx, beta, yt, ldy, s); break;
+    case H2_FP64: gemv_tree_impl<double, float>(A, nv, alpha, xt, ldx, beta, yt, ldy, s, nt_force); break;
+    case H2_FP32: gemv_tree_impl<float, float>(A, nv, alpha, xt, ldx, beta, yt, ldy, s, nt_force); break;
+    case H2_BF16: gemv_tree_impl<bf16_t, float>(A, nv, alpha, xt, ldx, beta, yt, ldy, s, nt_force); break;
   }
 }
 

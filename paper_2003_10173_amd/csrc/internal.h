@@ -5,9 +5,11 @@
 
 #include <cstdint>
 #include <cstdio>
+#include <map>
 #include <memory>
 #include <stdexcept>
 #include <string>
+#include <tuple>
 #include <utility>
 #include <vector>
 
@@ -101,6 +103,10 @@ struct h2_tree {
   std::vector<int32_t> near_ptr, near_col;
   int max_leaf = 0;
   bool device_ready = false;
+  // autotuned matrix-core tile width (16-column tiles per workgroup) of the
+  // HGEMV stages of matrices on this tree, per (min(ceil(nv / 16), 4),
+  // matrix element size, vector element size)
+  mutable std::map<std::tuple<int, int, int>, int> tuned_nt;
   // device copies (made on first device use)
   h2::DevBuf d_perm, d_cstart, d_csize, d_far_ptr, d_far_col, d_near_ptr, d_near_col;
   int64_t num_far() const { return far_base.empty() ? 0 : far_base.back(); }
@@ -147,10 +153,11 @@ void matrix_alloc(h2_matrix* A, h2_precision prec);
 std::unique_ptr<h2_matrix> matrix_clone_layout(const h2_matrix* A);
 
 // HGEMV on tree-order column-major vectors (no permutation)
+// nt_force (1, 2 or 4) fixes the matrix-core tile width (tests); 0: autotuned
 void gemv_tree_f64(const h2_matrix* A, int nv, double alpha, const double* xt, int ldx,
-                   double beta, double* yt, int ldy, hipStream_t s);
+                   double beta, double* yt, int ldy, hipStream_t s, int nt_force = 0);
 void gemv_tree_f32(const h2_matrix* A, int nv, float alpha, const float* xt, int ldx,
-                   float beta, float* yt, int ldy, hipStream_t s);
+                   float beta, float* yt, int ldy, hipStream_t s, int nt_force = 0);
 
 // permutations between user and tree order (column-major, nv columns)
 void gather_rows(const h2_tree* t, int nv, const double* x, int ldx, double* xt, int ldt,

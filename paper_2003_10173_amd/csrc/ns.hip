@@ -277,6 +277,9 @@ void ns_iterate_multi(std::vector<NSJob>& jobs, hipStream_t s) {
       b.t = J.A->tree;
       b.S = J.S.get();
       b.prm = J.bp;
+      // FP32 samples carry rounding of about 1e-7 relative: the range basis
+      // keeps only directions above it
+      b.prm.rank_cut = J.low ? 1e-7 : 1e-13;
       bj.push_back(std::move(b));
       who.push_back(&J);
     }

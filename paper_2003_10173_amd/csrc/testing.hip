@@ -189,6 +189,26 @@ h2_status h2_test_mfma_layout(int kind, double* out) {
   });
 }
 
+h2_status h2_test_gemv_tile(const h2_matrix* A, int nv, const double* x, double* y, int nt) {
+  return guarded_status([&] {
+    H2_CHECK(A && x && y && nv > 0 && A->st.prec == H2_FP64, H2_EINVAL, "bad arguments");
+    const int n = A->tree->n;
+    DevBuf w((size_t)2 * n * nv * sizeof(double));
+    double* xt = w.as<double>();
+    double* yt = xt + (size_t)n * nv;
+    gather_rows(A->tree, nv, x, n, xt, n, 0);
+    gemv_tree_f64(A, nv, 1.0, xt, n, 0.0, yt, n, 0, nt);
+    scatter_rows(A->tree, nv, 1.0, yt, n, 0.0, y, n, 0);
+    H2_HIP(hipDeviceSynchronize());
+  });
+}
+
+int h2_test_tuned_tile(const h2_matrix* A, int nv) {
+  if (!A) return -1;
+  auto it = A->tree->tuned_nt.find(std::tuple<int, int, int>{std::min((nv + 15) / 16, 4), 8, 8});
+  return it == A->tree->tuned_nt.end() ? 0 : it->second;
+}
+
 void h2_test_keep_factors(int on) { g_keep_factors = on != 0; }
 
 h2_status h2_test_factors(int level, int32_t* ranks_out, int* K_out, double* F_out) {

@@ -133,3 +133,26 @@ def test_hgemv_reduced_precision_ragged_random(nv):
         assert err <= tol, (prec, err)
         if prec == h2.H2_BF16:
             assert err >= 1e-5   # the BF16 path really rounds its operands
+
+
+@pytest.mark.parametrize("nv", [7, 20, 64, 70])
+def test_hgemv_tile_widths_agree_and_tuner_picks_one(nv):
+    """Every matrix-core tile width gives the same product (the same sums in
+    the same order); the autotuner records one of them for the tree."""
+    from paper_2003_10173_amd._lib import lib
+    pts = np.random.Generator(np.random.PCG64(31)).uniform(size=(1800, 2))
+    T = OTree(pts, 64, 0.7)
+    H = _random_h2(T, 12, 6)
+    gt = h2.Tree(pts, 64, 0.7)
+    G = h2.H2Matrix.from_host(gt, *oracle_to_packed(H))
+    x = torch.tensor(si.gaussian_vectors(T.n, nv, 4).T.copy(), device="cuda")
+    outs = []
+    for nt in (1, 2, 4):
+        y = torch.empty_like(x)
+        h2.check(lib().h2_test_gemv_tile(G.handle, nv, x.data_ptr(), y.data_ptr(), nt), "tile")
+        outs.append(y.cpu().numpy())
+    assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[0], outs[2])
+    y = G.gemv(x)
+    torch.cuda.synchronize()
+    assert np.array_equal(y.cpu().numpy(), outs[0])
+    assert lib().h2_test_tuned_tile(G.handle, nv) in (1, 2, 4)
