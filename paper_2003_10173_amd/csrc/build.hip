@@ -131,7 +131,8 @@ std::vector<T> to_host(const T* d, size_t n, hipStream_t s) {
 }
 
 // Left singular vectors and singular values of X (M x K, column-major, ld):
-// K >= M: Jacobi on X^T; K < M: QR then Jacobi on R^T.  Writes U (M x r,
+// K >= 2M: QR of X^T, Jacobi on R^T (normalised columns); M <= K < 2M:
+// Jacobi on X^T; K < M: QR then Jacobi on R^T.  Writes U (M x r,
 // ld M) with r = min(M, K) and sigma (r).  X is destroyed.
 struct LsvTask {
   double* X;
@@ -145,9 +146,22 @@ void left_svd_batched(Ctx& c, const std::vector<LsvTask>& tasks) {
   std::vector<QRDesc> qrs;
   std::vector<SVDDesc> svs;
   std::vector<GemmDesc> back;
+  std::vector<QRDesc> rq;       // R-only QR of X^T (K >= 2M)
+  std::vector<CopyDesc> rtr;    // R -> R^T
   for (const auto& tk : tasks) {
     if (tk.M == 0 || tk.K == 0) continue;
-    if (tk.K >= tk.M) {
+    if (tk.K >= 2 * tk.M) {
+      // X^T = Q R: the left singular vectors of X are those of R^T, taken as
+      // the normalised columns of one-sided Jacobi on R^T (M x M rows instead
+      // of K; only the leading vectors, above the truncation, are used)
+      double* Xt = c.scratch.get((size_t)tk.K * tk.M);
+      double* R = c.scratch.get((size_t)tk.M * tk.M);
+      double* Rt = c.scratch.get((size_t)tk.M * tk.M);
+      tr.push_back({tk.X, tk.ld, Xt, tk.K, tk.K, tk.M, 1.0, 0.0, 1});
+      rq.push_back({Xt, tk.K, tk.K, tk.M, nullptr, 0, R, tk.M});
+      rtr.push_back({R, tk.M, Rt, tk.M, tk.M, tk.M, 1.0, 0.0, 1});
+      svs.push_back({Rt, tk.M, tk.M, tk.M, tk.sigma, tk.U, tk.M, nullptr, 0});
+    } else if (tk.K >= tk.M) {
       double* Xt = c.scratch.get((size_t)tk.K * tk.M);
       tr.push_back({tk.X, tk.ld, Xt, tk.K, tk.K, tk.M, 1.0, 0.0, 1});
       svs.push_back({Xt, tk.K, tk.K, tk.M, tk.sigma, nullptr, 0, tk.U, tk.M});
@@ -164,6 +178,8 @@ void left_svd_batched(Ctx& c, const std::vector<LsvTask>& tasks) {
   }
   qr_auto(c, qrs);
   copy_batched(c, tr);
+  qr_auto(c, rq);
+  copy_batched(c, rtr);
   svd_batched(c, svs);
   gemm_batched(c, back);
 }

@@ -622,14 +622,13 @@ __global__ __launch_bounds__(256) void k_svd_final(const SVDDesc* __restrict__ d
     if (lane == 0) sig[col] = sqrt(s);
   }
   __syncthreads();
-  if (tid == 0) {
-    for (int i = 0; i < n; ++i) order[i] = i;
-    for (int i = 1; i < n; ++i) {
-      const int key = order[i];
-      int j = i - 1;
-      while (j >= 0 && sig[order[j]] < sig[key]) { order[j + 1] = order[j]; --j; }
-      order[j + 1] = key;
-    }
+  // descending order, equal values by index: position of i = number of
+  // values ranked before it
+  for (int i = tid; i < n; i += 256) {
+    const double si = sig[i];
+    int r = 0;
+    for (int j = 0; j < n; ++j) r += (sig[j] > si) || (sig[j] == si && j < i);
+    order[r] = i;
   }
   __syncthreads();
   for (int e = tid; e < n; e += 256) d.sigma[e] = sig[order[e]];
