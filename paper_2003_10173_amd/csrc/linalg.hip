@@ -506,9 +506,26 @@ __global__ __launch_bounds__(512) void k_svd_block(const SVDDesc* __restrict__ d
         __syncthreads();
         int nc = 0;
         for (int q = 0; q < SVD_PC; ++q) nc += cols[q] >= 0;
-        for (int e = tid; e < SVD_PC * m; e += 512) {
-          const int q = e / m, i = e % m;
-          L[q * m + i] = q < nc ? d.A[(size_t)cols[q] * d.lda + i] : 0.0;
+        {
+          // all loads of the pair's columns issued before any is stored
+          constexpr int RS = SVD_MMAX / 512;
+          double xv[SVD_PC][RS];
+#pragma unroll
+          for (int q = 0; q < SVD_PC; ++q) {
+            const double* col = q < nc ? d.A + (size_t)cols[q] * d.lda : nullptr;
+#pragma unroll
+            for (int sr = 0; sr < RS; ++sr) {
+              const int row = tid + 512 * sr;
+              xv[q][sr] = (col && row < m) ? col[row] : 0.0;
+            }
+          }
+#pragma unroll
+          for (int q = 0; q < SVD_PC; ++q)
+#pragma unroll
+            for (int sr = 0; sr < RS; ++sr) {
+              const int row = tid + 512 * sr;
+              if (row < m) L[q * m + row] = xv[q][sr];
+            }
         }
         for (int e = tid; e < SVD_PC * SVD_PC; e += 512) Vl[e] = (e / SVD_PC == e % SVD_PC) ? 1.0 : 0.0;
         __syncthreads();
@@ -522,12 +539,18 @@ __global__ __launch_bounds__(512) void k_svd_block(const SVDDesc* __restrict__ d
             if (b >= nc) continue;
             double* ca = L + a * m;
             double* cb = L + b * m;
+            // the pair's two columns held in registers: one LDS read, one write
+            constexpr int RL = SVD_MMAX / 64;
+            double xa[RL], xb[RL];
             double al = 0, be = 0, ga = 0;
-            for (int i = lane; i < m; i += 64) {
-              const double x = ca[i], y = cb[i];
-              al += x * x;
-              be += y * y;
-              ga += x * y;
+#pragma unroll
+            for (int q = 0; q < RL; ++q) {
+              const int i = lane + 64 * q;
+              xa[q] = i < m ? ca[i] : 0.0;
+              xb[q] = i < m ? cb[i] : 0.0;
+              al += xa[q] * xa[q];
+              be += xb[q] * xb[q];
+              ga += xa[q] * xb[q];
             }
             al = wave_sum(al);
             be = wave_sum(be);
@@ -538,10 +561,13 @@ __global__ __launch_bounds__(512) void k_svd_block(const SVDDesc* __restrict__ d
             if (fabs(zeta) > 1e150) t = 0.5 / zeta;
             else t = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
             const double cs = 1.0 / sqrt(1.0 + t * t), sn = cs * t;
-            for (int i = lane; i < m; i += 64) {
-              const double x = ca[i], y = cb[i];
-              ca[i] = cs * x - sn * y;
-              cb[i] = sn * x + cs * y;
+#pragma unroll
+            for (int q = 0; q < RL; ++q) {
+              const int i = lane + 64 * q;
+              if (i < m) {
+                ca[i] = cs * xa[q] - sn * xb[q];
+                cb[i] = sn * xa[q] + cs * xb[q];
+              }
             }
             if (lane < SVD_PC) {
               const double x = Vl[a * SVD_PC + lane], y = Vl[b * SVD_PC + lane];
@@ -573,10 +599,8 @@ __global__ __launch_bounds__(512) void k_svd_block(const SVDDesc* __restrict__ d
           __syncthreads();
         }
         // write back the columns and update V(:, cols) <- V(:, cols) Vl
-        for (int e = tid; e < nc * m; e += 512) {
-          const int q = e / m, i = e % m;
-          d.A[(size_t)cols[q] * d.lda + i] = L[q * m + i];
-        }
+        for (int q = 0; q < nc; ++q)
+          for (int i = tid; i < m; i += 512) d.A[(size_t)cols[q] * d.lda + i] = L[q * m + i];
         if (d.V) {
           for (int i = tid; i < n; i += 512) {
             double row[SVD_PC];
