@@ -106,12 +106,16 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmTask* __restrict__ tasks
   const GemmDesc& d = t.d;
   const int tile = (int)(b - tile_start[lo]);
   const int bm = (tile % t.tiles_m) * TM, bn = (tile / t.tiles_m) * TN;
-  const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
-  double acc[4][4];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  // wave w: rows 32 (w % 2) .. +32, columns 32 (w / 2) .. +32 of the tile, as
+  // 2 x 2 sub-tiles of 16 x 16 on the FP64 matrix cores (16x16x4 products)
+  typedef double d4 __attribute__((ext_vector_type(4)));
+  const int wr = 32 * (wave & 1), wc = 32 * (wave >> 1);
+  d4 acc[2][2];
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = 0;
+    for (int j = 0; j < 2; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
   for (int k0 = t.k0; k0 < t.k1; k0 += TK) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
@@ -133,30 +137,36 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmTask* __restrict__ tasks
     }
     __syncthreads();
 #pragma unroll
-    for (int k = 0; k < TK; ++k) {
-      double a[4], bb[4];
+    for (int ks = 0; ks < TK; ks += 4) {
+      const int kk = ks + (lane >> 4);
+      double a[2], bb[2];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) a[i] = As[k][tx + 16 * i];
+      for (int i = 0; i < 2; ++i) a[i] = As[kk][wr + 16 * i + (lane & 15)];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) bb[j] = Bs[k][ty + 16 * j];
+      for (int j = 0; j < 2; ++j) bb[j] = Bs[kk][wc + 16 * j + (lane & 15)];
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+      for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = fma(a[i], bb[j], acc[i][j]);
+        for (int j = 0; j < 2; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], bb[j], acc[i][j], 0, 0, 0);
     }
     __syncthreads();
   }
+  // result register r of a 16 x 16 f64 product: row 4 r + lane / 16, column lane % 16
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int gi = bm + tx + 16 * i, gj = bn + ty + 16 * j;
-      if (gi < d.M && gj < d.N) {
-        double* o = t.out + (size_t)gj * t.ldo + gi;
-        const double v = d.alpha * acc[i][j];
-        *o = t.beta == 0.0 ? v : v + t.beta * *o;
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int gi = bm + wr + 16 * i + 4 * r + (lane >> 4);
+        const int gj = bn + wc + 16 * j + (lane & 15);
+        if (gi < d.M && gj < d.N) {
+          double* o = t.out + (size_t)gj * t.ldo + gi;
+          const double v = d.alpha * acc[i][j][r];
+          *o = t.beta == 0.0 ? v : v + t.beta * *o;
+        }
       }
-    }
 }
 
 struct ReduceTask {
@@ -1111,7 +1121,7 @@ void qr_blocked(Ctx& c, const std::vector<CholQRDesc>& ds) {
   // (BCGS2):  S1 = Q^T P, P -= Q S1, P = Q1 R1;  S2 = Q^T Q1, Q1 -= Q S2,
   // Q1 = Q2 R2;  R_jj = R2 R1,  R[0:j0, j] = S1 + S2 R1.  Stable when the
   // panel is numerically dependent on the previous ones.
-  constexpr int W = 64;
+  constexpr int W = 96;   // panel width: the widest TSQR node
   int maxp = 0;
   std::vector<CholQRDesc> v;
   for (auto& d : ds)
