@@ -112,7 +112,7 @@ void svd_batched(Ctx& c, const std::vector<SVDDesc>& d);
 void copy_batched(Ctx& c, const std::vector<CopyDesc>& d);
 // tall-skinny Householder QR by a TSQR tree (n <= 96, m >= n): explicit Q and R
 void qr_tall_batched(Ctx& c, const std::vector<QRDesc>& d);
-// blocked QR of tall matrices (m >= n): 96-column panels, two block
+// blocked QR of tall matrices (m >= n): 64-column panels, two block
 // Gram-Schmidt projections per panel by GEMM, TSQR per panel; P is
 // replaced by Q (m x n) and R (n x n, upper) is written to R
 void qr_blocked(Ctx& c, const std::vector<CholQRDesc>& d);

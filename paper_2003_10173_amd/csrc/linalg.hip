@@ -1121,7 +1121,7 @@ void qr_blocked(Ctx& c, const std::vector<CholQRDesc>& ds) {
   // (BCGS2):  S1 = Q^T P, P -= Q S1, P = Q1 R1;  S2 = Q^T Q1, Q1 -= Q S2,
   // Q1 = Q2 R2;  R_jj = R2 R1,  R[0:j0, j] = S1 + S2 R1.  Stable when the
   // panel is numerically dependent on the previous ones.
-  constexpr int W = 96;   // panel width: the widest TSQR node
+  constexpr int W = 64;
   int maxp = 0;
   std::vector<CholQRDesc> v;
   for (auto& d : ds)
