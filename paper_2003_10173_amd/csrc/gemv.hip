@@ -414,6 +414,105 @@ __global__ __launch_bounds__(256) void k_leaf_mfma(
     }
 }
 
+// Leaf stage with the matrix-core operands read straight from memory into
+// registers (no LDS, no barriers: every wave streams its own 16 rows of each
+// block, so many waves stay resident and hide the latency of each other's
+// loads).  Same products, accumulated in the same order, as the tile kernel.
+template <class M, class V, int NT>
+__global__ __launch_bounds__(256) void k_leaf_direct(
+    int L, const int32_t* __restrict__ cstart, const int32_t* __restrict__ csize,
+    const int32_t* __restrict__ rank, const int64_t* __restrict__ kpre,
+    const int64_t* __restrict__ Uoff, const M* __restrict__ U,
+    const int32_t* __restrict__ near_ptr, const int32_t* __restrict__ near_col,
+    const int64_t* __restrict__ Doff, const M* __restrict__ D, int nv, const V* __restrict__ yh,
+    const V* __restrict__ x, int ldx, V alpha, V beta, V* __restrict__ y, int ldy) {
+  using T = MfmaTraits<M>;
+  using Acc = typename T::Acc;
+  constexpr bool BF = T::KS == 16;
+  constexpr int NC = 16 * NT;
+  const int i = blockIdx.x;
+  const int leaf_base = (1 << L) - 1;
+  const int c = leaf_base + i;
+  const int r0 = cstart[c], m = csize[c];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (16 * wave >= m) return;
+  const int v0 = blockIdx.y * NC;
+  const int nvc = min(NC, nv - v0);
+  const int k = rank[c];
+  const int g0 = near_ptr[i], nnear = near_ptr[i + 1] - g0;
+  const int arow = 16 * wave + (lane & 15);        // A row of this lane
+  const bool arow_ok = arow < m;
+  const int kq = BF ? 4 * (lane >> 4) : (lane >> 4);  // k offset of this lane within a step
+  Acc acc[NT];
+#pragma unroll
+  for (int ct = 0; ct < NT; ++ct)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) acc[ct][r] = 0;
+  const int nsrc = nnear + (k > 0 ? 1 : 0);
+  for (int src = 0; src < nsrc; ++src) {
+    const M* Ap;
+    const V* Bp;
+    int K, ldb;
+    if (src < nnear) {
+      const int g = g0 + src;
+      const int sc = leaf_base + near_col[g];
+      Ap = D + Doff[g];
+      K = csize[sc];
+      Bp = x + (size_t)v0 * ldx + cstart[sc];
+      ldb = ldx;
+    } else {
+      Ap = U + Uoff[i];
+      K = k;
+      Bp = yh + kpre[c] * nv + (size_t)v0 * k;
+      ldb = k;
+    }
+    const M* arow_p = Ap + (size_t)arow * K;
+#pragma unroll 4
+    for (int k0 = 0; k0 < K; k0 += T::KS) {
+      const int kk = k0 + kq;
+      if constexpr (BF) {
+        mf_s4 a;
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+          a[e] = (short)((arow_ok && kk + e < K) ? mf_a(arow_p[kk + e]) : (uint16_t)0);
+#pragma unroll
+        for (int ct = 0; ct < NT; ++ct) {
+          const int col = ct * 16 + (lane & 15);
+          const V* bp = Bp + (size_t)col * ldb + kk;
+          mf_s4 b;
+#pragma unroll
+          for (int e = 0; e < 4; ++e)
+            b[e] = (short)((col < nvc && kk + e < K) ? mf_b<uint16_t, V>(bp[e]) : (uint16_t)0);
+          acc[ct] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[ct], 0, 0, 0);
+        }
+      } else {
+        const typename T::SA a = (arow_ok && kk < K) ? mf_a(arow_p[kk]) : typename T::SA(0);
+#pragma unroll
+        for (int ct = 0; ct < NT; ++ct) {
+          const int col = ct * 16 + (lane & 15);
+          const typename T::SB b = (col < nvc && kk < K) ? mf_b<typename T::SB, V>(Bp[(size_t)col * ldb + kk])
+                                                           : typename T::SB(0);
+          if constexpr (sizeof(typename T::SA) == 8)
+            acc[ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[ct], 0, 0, 0);
+          else
+            acc[ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[ct], 0, 0, 0);
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int ct = 0; ct < NT; ++ct)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = 16 * wave + mf_row<M>(r, lane), col = ct * 16 + (lane & 15);
+      if (row < m && col < nvc) {
+        V* yp = y + (size_t)(v0 + col) * ldy + r0 + row;
+        const V val = alpha * (V)acc[ct][r];
+        *yp = beta == V(0) ? val : val + beta * *yp;
+      }
+    }
+}
+
 // upsweep at the leaves: x^_t = U_t^T x_t (k_t x nv)
 template <class M, class V, int NT>
 __global__ __launch_bounds__(256) void k_up_leaf_mfma(
@@ -534,11 +633,20 @@ static void leaf_nt(const h2_matrix* A, int nv, V alpha, const V* xt, int ldx, V
                     int ldy, const V* yh, hipStream_t s) {
   const h2_tree* t = A->tree;
   const unsigned gy = (unsigned)((nv + 16 * NT - 1) / (16 * NT));
-  k_leaf_mfma<M, V, NT><<<dim3(1 << t->L, gy), 256, 0, s>>>(
-      t->L, t->d_cstart.as<int32_t>(), t->d_csize.as<int32_t>(), A->d_rank.as<int32_t>(),
-      A->d_kpre.as<int64_t>(), A->d_U_off.as<int64_t>(), A->st.U.as<M>(),
-      t->d_near_ptr.as<int32_t>(), t->d_near_col.as<int32_t>(), A->d_D_off.as<int64_t>(),
-      A->st.D.as<M>(), nv, yh, xt, ldx, alpha, beta, yt, ldy);
+  // FP64: operands straight from memory (8-byte loads); FP32 / BF16: LDS tiles
+  // (their 4- and 2-byte element loads would waste memory transactions)
+  if constexpr (std::is_same<M, double>::value)
+    k_leaf_direct<M, V, NT><<<dim3(1 << t->L, gy), 256, 0, s>>>(
+        t->L, t->d_cstart.as<int32_t>(), t->d_csize.as<int32_t>(), A->d_rank.as<int32_t>(),
+        A->d_kpre.as<int64_t>(), A->d_U_off.as<int64_t>(), A->st.U.as<M>(),
+        t->d_near_ptr.as<int32_t>(), t->d_near_col.as<int32_t>(), A->d_D_off.as<int64_t>(),
+        A->st.D.as<M>(), nv, yh, xt, ldx, alpha, beta, yt, ldy);
+  else
+    k_leaf_mfma<M, V, NT><<<dim3(1 << t->L, gy), 256, 0, s>>>(
+        t->L, t->d_cstart.as<int32_t>(), t->d_csize.as<int32_t>(), A->d_rank.as<int32_t>(),
+        A->d_kpre.as<int64_t>(), A->d_U_off.as<int64_t>(), A->st.U.as<M>(),
+        t->d_near_ptr.as<int32_t>(), t->d_near_col.as<int32_t>(), A->d_D_off.as<int64_t>(),
+        A->st.D.as<M>(), nv, yh, xt, ldx, alpha, beta, yt, ldy);
 }
 
 template <class M, class V>

@@ -437,8 +437,8 @@ __global__ void k_svd_init_v(const SVDDesc* __restrict__ descs) {
     d.V[(size_t)(e / d.n) * d.ldv + e % d.n] = (e / d.n == e % d.n) ? 1.0 : 0.0;
 }
 
-// single workgroup per matrix (small n)
-__global__ __launch_bounds__(256) void k_svd_sweeps(const SVDDesc* __restrict__ descs) {
+// single workgroup per matrix (small n): 8 waves rotate 8 disjoint pairs at a time
+__global__ __launch_bounds__(512) void k_svd_sweeps(const SVDDesc* __restrict__ descs) {
   const SVDDesc d = descs[blockIdx.x];
   const int n = d.n, m = d.m;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -448,7 +448,7 @@ __global__ __launch_bounds__(256) void k_svd_sweeps(const SVDDesc* __restrict__ 
     if (threadIdx.x == 0) rotated = 0;
     __syncthreads();
     for (int r = 0; r < np - 1; ++r) {
-      for (int k = wave; k < np / 2; k += 4) {
+      for (int k = wave; k < np / 2; k += 8) {
         int a, b;
         tournament_pair(np, r, k, a, b);
         if (b >= n) continue;
@@ -706,7 +706,7 @@ void svd_batched(Ctx& c, const std::vector<SVDDesc>& ds) {
   H2_LAUNCH_CHECK();
   if (!small.empty()) {
     auto* dd = (SVDDesc*)c.stage.put(small.data(), small.size() * sizeof(SVDDesc), c.s);
-    k_svd_sweeps<<<(unsigned)small.size(), 256, 0, c.s>>>(dd);
+    k_svd_sweeps<<<(unsigned)small.size(), 512, 0, c.s>>>(dd);
     H2_LAUNCH_CHECK();
   }
   if (!big.empty()) {
