@@ -463,21 +463,64 @@ __global__ __launch_bounds__(512) void k_svd_sweeps(const SVDDesc* __restrict__ 
 
 // Block one-sided Jacobi over many workgroups: columns are grouped in blocks
 // of SVD_BS; each round of the block tournament gives every workgroup one
-// pair of blocks, whose 2*SVD_BS columns are rotated pairwise in LDS (one
-// cyclic inner sweep), with the accumulated rotation applied to the matching
-// columns of V.  A grid-wide barrier
-// separates rounds; every workgroup executes the same number of barriers
-// (rounds of the widest matrix, identical termination decision from flags read
-// after a barrier).
-constexpr int SVD_BS = 8, SVD_PC = 2 * SVD_BS, SVD_MMAX = 1024;
+// pair of blocks.  Its 2*SVD_BS columns are staged in LDS, their Gram matrix
+// G = L^T L is formed on the FP64 matrix cores, and the small symmetric
+// problem G = W diag W^T is solved by cyclic two-sided Jacobi on G (parallel
+// tournament order, one wave, up to SVD_INNER sweeps); the columns of A and
+// of V are then multiplied by the accumulated rotation W once.  Whether a
+// pair still needs rotating is decided on the Gram matrix of the current
+// columns (|a.b| > tol |a| |b|), so a sweep without rotations certifies the
+// columns themselves.  A grid-wide barrier separates rounds; every workgroup
+// executes the same number of barriers (rounds of the widest matrix,
+// identical termination decision from flags read after a barrier).
+constexpr int SVD_BS = 8, SVD_PC = 2 * SVD_BS, SVD_MMAX = 1024, SVD_INNER = 1;
+typedef double svd_d4 __attribute__((ext_vector_type(4)));
+
+// the pairs of tournament_pair without integer division (r < np - 1, k < np / 2)
+__device__ inline void tournament_pair_fast(int np, int r, int k, int& a, int& b) {
+  if (k == 0) { a = np - 1; b = r; }
+  else {
+    a = r + k;
+    if (a >= np - 1) a -= np - 1;
+    b = r - k;
+    if (b < 0) b += np - 1;
+  }
+  if (a > b) { const int t = a; a = b; b = t; }
+}
+
+// columns a, b (Gram entries al = a.a, be = b.b, ga = a.b) need a rotation
+__device__ inline bool jacobi_needs(double al, double be, double ga, double tol) {
+  return ga != 0.0 && ga * ga > (tol * tol) * (al * be);
+}
+
+// rotation a <- c a - s b, b <- s a + c b that makes a.b vanish:
+// t = sign(d e) |e| / (|d| + sqrt(d^2 + e^2)) with d = be - al, e = 2 ga is the
+// smaller root of t^2 + 2 (d / e) t - 1 = 0; c = 1 / sqrt(1 + t^2), s = c t
+__device__ inline void jacobi_cs(double al, double be, double ga, double& c, double& s) {
+  const double d = be - al, e = 2.0 * ga;
+  const double h = sqrt(d * d + e * e);
+  double t = fabs(e) / (fabs(d) + h);
+  if ((d < 0) != (e < 0) && d != 0.0) t = -t;
+  c = rsqrt(1.0 + t * t);
+  s = c * t;
+}
+
+// LDS ordering between the lanes of one wave (the wave runs in lockstep):
+// every LDS access issued before has completed, and no access is moved
+// across by the compiler
+__device__ inline void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+}
 
 __global__ __launch_bounds__(512) void k_svd_block(const SVDDesc* __restrict__ descs,
                                                    const int* __restrict__ wg_start, int nmat,
                                                    int maxnpb, int* flags, int* sweeps_out) {
   cooperative_groups::grid_group grid = cooperative_groups::this_grid();
   __shared__ double L[SVD_PC * SVD_MMAX];
-  __shared__ double Vl[SVD_PC * SVD_PC];
-  __shared__ double Gl[SVD_PC * SVD_PC];
+  __shared__ double Gp[8 * SVD_PC * SVD_PC];      // per-wave Gram partials
+  __shared__ double Gs[SVD_PC * SVD_PC];          // Gram, G(i, j) at [i * 16 + j]
+  __shared__ double Ws[SVD_PC * SVD_PC];          // rotation, W(q, j) at [q * 16 + j]
   __shared__ int cols[SVD_PC];
   __shared__ int rot_any;
   int lo = 0, hi = nmat - 1;
@@ -493,6 +536,7 @@ __global__ __launch_bounds__(512) void k_svd_block(const SVDDesc* __restrict__ d
   const int n = d.n, m = d.m;
   const int nb = (n + SVD_BS - 1) / SVD_BS;
   const int npb = nb + (nb & 1);
+  const double tol = jacobi_tol(m);
   for (int sweep = 0; sweep < 60; ++sweep) {
     int* fl = flags + (sweep & 1) * nmat;
     for (int r = 0; r < maxnpb - 1; ++r) {
@@ -537,92 +581,155 @@ __global__ __launch_bounds__(512) void k_svd_block(const SVDDesc* __restrict__ d
               if (row < m) L[q * m + row] = xv[q][sr];
             }
         }
-        for (int e = tid; e < SVD_PC * SVD_PC; e += 512) Vl[e] = (e / SVD_PC == e % SVD_PC) ? 1.0 : 0.0;
         __syncthreads();
-        // one cyclic inner sweep over the nc columns: every pair of the two
-        // blocks is met once per visit, as often as in the scalar cyclic order
-        const int npc = nc + (nc & 1);
-        for (int rr = 0; rr < npc - 1; ++rr) {
-          for (int kk = wave; kk < npc / 2; kk += 8) {
-            int a, b;
-            tournament_pair(npc, rr, kk, a, b);
-            if (b >= nc) continue;
-            double* ca = L + a * m;
-            double* cb = L + b * m;
-            // the pair's two columns held in registers: one LDS read, one write
-            constexpr int RL = SVD_MMAX / 64;
-            double xa[RL], xb[RL];
-            double al = 0, be = 0, ga = 0;
-#pragma unroll
-            for (int q = 0; q < RL; ++q) {
-              const int i = lane + 64 * q;
-              xa[q] = i < m ? ca[i] : 0.0;
-              xb[q] = i < m ? cb[i] : 0.0;
-              al += xa[q] * xa[q];
-              be += xb[q] * xb[q];
-              ga += xa[q] * xb[q];
-            }
-            al = wave_sum(al);
-            be = wave_sum(be);
-            ga = wave_sum(ga);
-            if (ga == 0.0 || !(fabs(ga) > jacobi_tol(m) * sqrt(al) * sqrt(be))) continue;
-            const double zeta = (be - al) / (2.0 * ga);
-            double t;
-            if (fabs(zeta) > 1e150) t = 0.5 / zeta;
-            else t = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-            const double cs = 1.0 / sqrt(1.0 + t * t), sn = cs * t;
-#pragma unroll
-            for (int q = 0; q < RL; ++q) {
-              const int i = lane + 64 * q;
-              if (i < m) {
-                ca[i] = cs * xa[q] - sn * xb[q];
-                cb[i] = sn * xa[q] + cs * xb[q];
-              }
-            }
-            if (lane < SVD_PC) {
-              const double x = Vl[a * SVD_PC + lane], y = Vl[b * SVD_PC + lane];
-              Vl[a * SVD_PC + lane] = cs * x - sn * y;
-              Vl[b * SVD_PC + lane] = sn * x + cs * y;
-            }
-            if (lane == 0) rot_any = 1;
+        // Gram partials on the matrix cores: wave w takes rows 4 kb .. 4 kb + 3
+        // for kb = w, w + 8, ...; lane l supplies L(row 4 kb + l / 16, column
+        // l % 16) as both operands; result element (4 e + l / 16, l % 16) in acc[e]
+        {
+          svd_d4 acc = {0.0, 0.0, 0.0, 0.0};
+          const int col = lane & 15, kr = lane >> 4;
+          for (int kb = wave; 4 * kb < m; kb += 8) {
+            const int row = 4 * kb + kr;
+            const double x = (row < m && col < nc) ? L[col * m + row] : 0.0;
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(x, x, acc, 0, 0, 0);
           }
-          __syncthreads();
+#pragma unroll
+          for (int e = 0; e < 4; ++e) Gp[wave * 256 + (4 * e + kr) * SVD_PC + col] = acc[e];
         }
+        __syncthreads();
+        if (tid < SVD_PC * SVD_PC) {
+          double g = 0;
+#pragma unroll
+          for (int w = 0; w < 8; ++w) g += Gp[w * 256 + tid];
+          Gs[tid] = g;
+          Ws[tid] = (tid / SVD_PC == tid % SVD_PC) ? 1.0 : 0.0;
+        }
+        __syncthreads();
+        // convergence test on the Gram matrix of the current columns
+        if (tid < SVD_PC * SVD_PC) {
+          const int i = tid / SVD_PC, j = tid % SVD_PC;
+          if (i < j && j < nc) {
+            if (jacobi_needs(Gs[i * 17], Gs[j * 17], Gs[tid], tol)) rot_any = 1;
+          }
+        }
+        __syncthreads();
+        if (!rot_any) {
+          // already orthogonal: the columns stay as they are
+          __syncthreads();
+          continue;
+        }
+        if (wave == 0) {
+          // cyclic two-sided Jacobi on G, W accumulating the rotations.  In
+          // each step lane (P, Q) = (lane / 8, lane % 8) owns the 2 x 2 block of
+          // G and of W at rows of pair P and columns of pair Q, so the update
+          // G <- J^T G J, W <- W J stays within the lane; the diagonal lanes
+          // compute the rotations and the others read them by shuffles
+          double* G = Gs;
+          double* Wm = Ws;
+          const int npc = nc + (nc & 1);
+          const int P = lane >> 3, Q = lane & 7;
+          const bool act = P < npc / 2 && Q < npc / 2;
+          for (int isw = 0; isw < SVD_INNER; ++isw) {
+            int rotated = 0;
+            for (int rr = 0; rr < npc - 1; ++rr) {
+              int aP = 0, bP = 0, aQ = 0, bQ = 0;
+              double g00 = 0, g01 = 0, g10 = 0, g11 = 0, w00 = 0, w01 = 0, w10 = 0, w11 = 0;
+              if (act) {
+                tournament_pair_fast(npc, rr, P, aP, bP);
+                tournament_pair_fast(npc, rr, Q, aQ, bQ);
+                g00 = G[aP * SVD_PC + aQ];
+                g01 = G[aP * SVD_PC + bQ];
+                g10 = G[bP * SVD_PC + aQ];
+                g11 = G[bP * SVD_PC + bQ];
+                w00 = Wm[aP * SVD_PC + aQ];
+                w01 = Wm[aP * SVD_PC + bQ];
+                w10 = Wm[bP * SVD_PC + aQ];
+                w11 = Wm[bP * SVD_PC + bQ];
+              }
+              double c = 1.0, sn = 0.0;
+              if (act && P == Q && bP < nc && jacobi_needs(g00, g11, g01, tol)) jacobi_cs(g00, g11, g01, c, sn);
+              const double cP = __shfl(c, 9 * P, 64), sP = __shfl(sn, 9 * P, 64);
+              const double cQ = __shfl(c, 9 * Q, 64), sQ = __shfl(sn, 9 * Q, 64);
+              rotated |= __any(sn != 0.0);
+              if (act) {
+                // J = [[c, s], [-s, c]] on (a, b)
+                const double h00 = g00 * cQ - g01 * sQ, h01 = g00 * sQ + g01 * cQ;
+                const double h10 = g10 * cQ - g11 * sQ, h11 = g10 * sQ + g11 * cQ;
+                G[aP * SVD_PC + aQ] = cP * h00 - sP * h10;
+                G[aP * SVD_PC + bQ] = cP * h01 - sP * h11;
+                G[bP * SVD_PC + aQ] = sP * h00 + cP * h10;
+                G[bP * SVD_PC + bQ] = sP * h01 + cP * h11;
+                Wm[aP * SVD_PC + aQ] = w00 * cQ - w01 * sQ;
+                Wm[aP * SVD_PC + bQ] = w00 * sQ + w01 * cQ;
+                Wm[bP * SVD_PC + aQ] = w10 * cQ - w11 * sQ;
+                Wm[bP * SVD_PC + bQ] = w10 * sQ + w11 * cQ;
+              }
+              wave_lds_sync();
+            }
+            if (!rotated) break;
+          }
+        }
+        __syncthreads();
+        const double* W = Ws;
         // restore the orthogonality of the accumulated rotation lost to
         // rounding (one Newton-Schulz polar step Q <- Q (3I - Q^T Q) / 2) so
         // that the many block products applied to V do not drift
-        if (rot_any && d.V) {
+        {
+          double* Gl = Gp;
+          double* Wq = Gp + 256;
           if (tid < SVD_PC * SVD_PC) {
             const int i = tid / SVD_PC, j = tid % SVD_PC;
             double g = 0;
-            for (int p = 0; p < SVD_PC; ++p) g += Vl[i * SVD_PC + p] * Vl[j * SVD_PC + p];
-            Gl[j * SVD_PC + i] = ((i == j ? 3.0 : 0.0) - g) * 0.5;
+            for (int p = 0; p < SVD_PC; ++p) g += W[p * SVD_PC + i] * W[p * SVD_PC + j];
+            Gl[tid] = ((i == j ? 3.0 : 0.0) - g) * 0.5;
           }
           __syncthreads();
-          double qn = 0;
           if (tid < SVD_PC * SVD_PC) {
-            const int q = tid / SVD_PC, p = tid % SVD_PC;
-            for (int r2 = 0; r2 < SVD_PC; ++r2) qn += Vl[r2 * SVD_PC + p] * Gl[q * SVD_PC + r2];
+            const int q = tid / SVD_PC, j = tid % SVD_PC;
+            double acc = 0;
+            for (int p = 0; p < SVD_PC; ++p) acc += W[q * SVD_PC + p] * Gl[p * SVD_PC + j];
+            Wq[tid] = acc;
           }
-          __syncthreads();
-          if (tid < SVD_PC * SVD_PC) Vl[tid] = qn;
           __syncthreads();
         }
-        // write back the columns and update V(:, cols) <- V(:, cols) Vl
-        for (int q = 0; q < nc; ++q)
-          for (int i = tid; i < m; i += 512) d.A[(size_t)cols[q] * d.lda + i] = L[q * m + i];
-        if (d.V) {
-          for (int i = tid; i < n; i += 512) {
-            double row[SVD_PC];
-            for (int q = 0; q < nc; ++q) row[q] = d.V[(size_t)cols[q] * d.ldv + i];
-            for (int q = 0; q < nc; ++q) {
-              double acc = 0;
-              for (int p = 0; p < nc; ++p) acc += row[p] * Vl[q * SVD_PC + p];
-              d.V[(size_t)cols[q] * d.ldv + i] = acc;
+        const double* Wf = Gp + 256;
+        // columns of A (from LDS) and of V (from memory) times W on the matrix
+        // cores, 16 rows per product: lane l supplies X(row r0 + l % 16, column
+        // k0 + l / 16) and W(k0 + l / 16, l % 16); the result element
+        // (r0 + 4 e + l / 16, l % 16) is in acc[e]
+        {
+          const int kr = lane >> 4, cl = lane & 15;
+          double wb[4];
+#pragma unroll
+          for (int kk = 0; kk < 4; ++kk) wb[kk] = Wf[(4 * kk + kr) * SVD_PC + cl];
+          const int tiles_a = (m + 15) / 16;
+          const int tiles = tiles_a + (d.V ? (n + 15) / 16 : 0);
+          for (int tl = wave; tl < tiles; tl += 8) {
+            const bool isa = tl < tiles_a;
+            const int r0 = 16 * (isa ? tl : tl - tiles_a);
+            const int rows = isa ? m : n;
+            const int ar = r0 + cl;
+            svd_d4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int kk = 0; kk < 4; ++kk) {
+              const int q = 4 * kk + kr;
+              double x = 0.0;
+              if (q < nc && ar < rows) x = isa ? L[q * m + ar] : d.V[(size_t)cols[q] * d.ldv + ar];
+              acc = __builtin_amdgcn_mfma_f64_16x16x4f64(x, wb[kk], acc, 0, 0, 0);
+            }
+            if (cl < nc) {
+#pragma unroll
+              for (int e = 0; e < 4; ++e) {
+                const int row = r0 + 4 * e + kr;
+                if (row < rows) {
+                  if (isa) d.A[(size_t)cols[cl] * d.lda + row] = acc[e];
+                  else d.V[(size_t)cols[cl] * d.ldv + row] = acc[e];
+                }
+              }
             }
           }
         }
-        if (tid == 0 && rot_any) atomicOr(&fl[mi], 1);
+        if (tid == 0) atomicOr(&fl[mi], 1);
         __syncthreads();
       }
       grid.sync();
