@@ -35,6 +35,9 @@ h2_status h2_test_svd(int m, int n, const double* A, double* sigma, double* U, d
    1: f32 16x16x4, 2: bf16 16x16x16) of known operands; out[lane*4 + reg]
    (256 values) -- pins the operand and result lane layouts the kernels use */
 h2_status h2_test_mfma_layout(int kind, double* out);
+/* out[lane] = the wave-wide sum of in[0..63] as the kernels' reduction returns
+   it to each lane of one 64-lane wave (host arrays of 64 doubles) */
+h2_status h2_test_wave_sum(const double* in, double* out);
 /* y = A x (FP64, user order, ld n, device pointers) with the matrix-core tile
    width fixed to nt (1, 2, 4 sixteen-vector tiles per workgroup; 0: tuned) */
 h2_status h2_test_gemv_tile(const h2_matrix* A, int nv, const double* x, double* y, int nt);

@@ -75,6 +75,35 @@ __device__ inline T wave_sum(T v) {
   return v;
 }
 
+// DPP move of a double (both 32-bit halves); lanes whose row is outside
+// ROW_MASK, or whose source lane is invalid, read 0
+template <int CTRL, int ROW_MASK>
+__device__ inline double dpp_f64(double v) {
+  const uint64_t b = __builtin_bit_cast(uint64_t, v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)b, CTRL, ROW_MASK, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(b >> 32), CTRL, ROW_MASK, 0xf, false);
+  return __builtin_bit_cast(double, ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+
+// Sum over the 64 lanes of a wave, returned to every lane.  Data-parallel
+// moves (no LDS traffic): pairs and quads within each row of 16 lanes, the
+// half-row and row mirrors complete the row sums, two row broadcasts
+// accumulate the four rows into lane 63, which is read back as a uniform
+// value.  Every lane of the wave must be active.
+template <>
+__device__ inline double wave_sum<double>(double v) {
+  v += dpp_f64<0xB1, 0xf>(v);   // quad_perm [1, 0, 3, 2]
+  v += dpp_f64<0x4E, 0xf>(v);   // quad_perm [2, 3, 0, 1]
+  v += dpp_f64<0x141, 0xf>(v);  // row_half_mirror
+  v += dpp_f64<0x140, 0xf>(v);  // row_mirror
+  v += dpp_f64<0x142, 0xa>(v);  // row_bcast:15 into rows 1 and 3
+  v += dpp_f64<0x143, 0xc>(v);  // row_bcast:31 into rows 2 and 3
+  const uint64_t b = __builtin_bit_cast(uint64_t, v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, 63);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), 63);
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
 template <class T>
 __device__ inline T wave_max(T v) {
 #pragma unroll

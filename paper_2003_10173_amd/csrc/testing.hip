@@ -67,6 +67,11 @@ __global__ void k_mfma_probe(int kind, double* out) {
   }
 }
 
+// every lane's value of the double wave sum of in[0..63]
+__global__ void k_wave_sum_probe(const double* __restrict__ in, double* __restrict__ out) {
+  out[threadIdx.x] = wave_sum(in[threadIdx.x]);
+}
+
 }  // namespace h2
 
 using namespace h2;
@@ -186,6 +191,18 @@ h2_status h2_test_mfma_layout(int kind, double* out) {
     H2_LAUNCH_CHECK();
     H2_HIP(hipDeviceSynchronize());
     H2_HIP(hipMemcpy(out, o.p, 256 * 8, hipMemcpyDeviceToHost));
+  });
+}
+
+h2_status h2_test_wave_sum(const double* in, double* out) {
+  return guarded_status([&] {
+    H2_CHECK(in && out, H2_EINVAL, "in and out needed");
+    DevBuf b(128 * 8);
+    H2_HIP(hipMemcpy(b.p, in, 64 * 8, hipMemcpyHostToDevice));
+    k_wave_sum_probe<<<1, 64>>>(b.as<double>(), b.as<double>() + 64);
+    H2_LAUNCH_CHECK();
+    H2_HIP(hipDeviceSynchronize());
+    H2_HIP(hipMemcpy(out, b.as<double>() + 64, 64 * 8, hipMemcpyDeviceToHost));
   });
 }
 

@@ -22,3 +22,23 @@ def test_mfma_result_layout(kind):
             got = (v % 32 - 1, v // 32 - 1)
             row = 4 * reg + lane // 16 if kind == 0 else 4 * (lane // 16) + reg
             assert got == (row, lane % 16), (kind, lane, reg, got)
+
+
+def test_wave_sum_dpp():
+    """The data-parallel wave reduction returns the same total to every lane,
+    equal to the exact sum within the rounding of a 64-term sum."""
+    import math
+    g = np.random.default_rng(5)
+    for scale in (1.0, 1e-300, 1e300):
+        x = g.standard_normal(64) * np.exp(g.uniform(-5, 5, 64)) * scale
+        out = np.zeros(64)
+        h2.check(lib().h2_test_wave_sum(x.ctypes.data, out.ctypes.data), "wave sum")
+        assert np.all(out == out[0])
+        exact = math.fsum(x)
+        assert abs(out[0] - exact) <= 64 * 2.0 ** -53 * np.abs(x).sum()
+    x = np.zeros(64)
+    x[63] = 1.5
+    x[0] = -0.25
+    out = np.zeros(64)
+    h2.check(lib().h2_test_wave_sum(x.ctypes.data, out.ctypes.data), "wave sum")
+    assert np.all(out == 1.25)
