@@ -473,7 +473,7 @@ __global__ __launch_bounds__(512) void k_svd_sweeps(const SVDDesc* __restrict__ 
 // columns themselves.  A grid-wide barrier separates rounds; every workgroup
 // executes the same number of barriers (rounds of the widest matrix,
 // identical termination decision from flags read after a barrier).
-constexpr int SVD_BS = 8, SVD_PC = 2 * SVD_BS, SVD_MMAX = 1024, SVD_INNER = 1;
+constexpr int SVD_BS = 8, SVD_PC = 2 * SVD_BS, SVD_MMAX = 1024, SVD_INNER = 1, SVD_VPF = 4;
 typedef double svd_d4 __attribute__((ext_vector_type(4)));
 
 // the pairs of tournament_pair without integer division (r < np - 1, k < np / 2)
@@ -560,6 +560,19 @@ __global__ __launch_bounds__(512) void k_svd_block(const SVDDesc* __restrict__ d
         __syncthreads();
         int nc = 0;
         for (int q = 0; q < SVD_PC; ++q) nc += cols[q] >= 0;
+        // the first SVD_VPF row tiles of V this wave updates at the end of the
+        // round, loaded now so that their latency overlaps the work below
+        // (layout of the matrix-core operand used there)
+        double vpf[SVD_VPF][4];
+#pragma unroll
+        for (int t = 0; t < SVD_VPF; ++t) {
+          const int ar = 16 * (wave + 8 * t) + (lane & 15);
+#pragma unroll
+          for (int kk = 0; kk < 4; ++kk) {
+            const int q = 4 * kk + (lane >> 4);
+            vpf[t][kk] = (d.V && q < nc && ar < n) ? d.V[(size_t)cols[q] * d.ldv + ar] : 0.0;
+          }
+        }
         {
           // all loads of the pair's columns issued before any is stored
           constexpr int RS = SVD_MMAX / 512;
@@ -622,8 +635,7 @@ __global__ __launch_bounds__(512) void k_svd_block(const SVDDesc* __restrict__ d
           // cyclic two-sided Jacobi on G, W accumulating the rotations.  In
           // each step lane (P, Q) = (lane / 8, lane % 8) owns the 2 x 2 block of
           // G and of W at rows of pair P and columns of pair Q, so the update
-          // G <- J^T G J, W <- W J stays within the lane; the diagonal lanes
-          // compute the rotations and the others read them by shuffles
+          // G <- J^T G J, W <- W J stays within the lane
           double* G = Gs;
           double* Wm = Ws;
           const int npc = nc + (nc & 1);
@@ -634,6 +646,7 @@ __global__ __launch_bounds__(512) void k_svd_block(const SVDDesc* __restrict__ d
             for (int rr = 0; rr < npc - 1; ++rr) {
               int aP = 0, bP = 0, aQ = 0, bQ = 0;
               double g00 = 0, g01 = 0, g10 = 0, g11 = 0, w00 = 0, w01 = 0, w10 = 0, w11 = 0;
+              double pa = 0, pb = 0, pg = 0, qa = 0, qb = 0, qg = 0;
               if (act) {
                 tournament_pair_fast(npc, rr, P, aP, bP);
                 tournament_pair_fast(npc, rr, Q, aQ, bQ);
@@ -645,12 +658,18 @@ __global__ __launch_bounds__(512) void k_svd_block(const SVDDesc* __restrict__ d
                 w01 = Wm[aP * SVD_PC + bQ];
                 w10 = Wm[bP * SVD_PC + aQ];
                 w11 = Wm[bP * SVD_PC + bQ];
+                pa = G[aP * 17];
+                pb = G[bP * 17];
+                pg = G[aP * SVD_PC + bP];
+                qa = G[aQ * 17];
+                qb = G[bQ * 17];
+                qg = G[aQ * SVD_PC + bQ];
               }
-              double c = 1.0, sn = 0.0;
-              if (act && P == Q && bP < nc && jacobi_needs(g00, g11, g01, tol)) jacobi_cs(g00, g11, g01, c, sn);
-              const double cP = __shfl(c, 9 * P, 64), sP = __shfl(sn, 9 * P, 64);
-              const double cQ = __shfl(c, 9 * Q, 64), sQ = __shfl(sn, 9 * Q, 64);
-              rotated |= __any(sn != 0.0);
+              // every lane forms the rotations of its two pairs itself
+              double cP = 1.0, sP = 0.0, cQ = 1.0, sQ = 0.0;
+              if (act && bP < nc && jacobi_needs(pa, pb, pg, tol)) jacobi_cs(pa, pb, pg, cP, sP);
+              if (act && bQ < nc && jacobi_needs(qa, qb, qg, tol)) jacobi_cs(qa, qb, qg, cQ, sQ);
+              rotated |= __any(sP != 0.0);
               if (act) {
                 // J = [[c, s], [-s, c]] on (a, b)
                 const double h00 = g00 * cQ - g01 * sQ, h01 = g00 * sQ + g01 * cQ;
@@ -702,31 +721,41 @@ __global__ __launch_bounds__(512) void k_svd_block(const SVDDesc* __restrict__ d
           double wb[4];
 #pragma unroll
           for (int kk = 0; kk < 4; ++kk) wb[kk] = Wf[(4 * kk + kr) * SVD_PC + cl];
-          const int tiles_a = (m + 15) / 16;
-          const int tiles = tiles_a + (d.V ? (n + 15) / 16 : 0);
-          for (int tl = wave; tl < tiles; tl += 8) {
-            const bool isa = tl < tiles_a;
-            const int r0 = 16 * (isa ? tl : tl - tiles_a);
-            const int rows = isa ? m : n;
-            const int ar = r0 + cl;
+          // one 16-row tile: X (lane operand x[kk]) times W, stored to Y
+          auto tile = [&](const double (&x)[4], double* Y, int ldy, int r0, int rows) {
             svd_d4 acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-            for (int kk = 0; kk < 4; ++kk) {
-              const int q = 4 * kk + kr;
-              double x = 0.0;
-              if (q < nc && ar < rows) x = isa ? L[q * m + ar] : d.V[(size_t)cols[q] * d.ldv + ar];
-              acc = __builtin_amdgcn_mfma_f64_16x16x4f64(x, wb[kk], acc, 0, 0, 0);
-            }
+            for (int kk = 0; kk < 4; ++kk) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(x[kk], wb[kk], acc, 0, 0, 0);
             if (cl < nc) {
 #pragma unroll
               for (int e = 0; e < 4; ++e) {
                 const int row = r0 + 4 * e + kr;
-                if (row < rows) {
-                  if (isa) d.A[(size_t)cols[cl] * d.lda + row] = acc[e];
-                  else d.V[(size_t)cols[cl] * d.ldv + row] = acc[e];
-                }
+                if (row < rows) Y[(size_t)cols[cl] * ldy + row] = acc[e];
               }
             }
+          };
+          if (d.V) {
+#pragma unroll
+            for (int t = 0; t < SVD_VPF; ++t)
+              if (16 * (wave + 8 * t) < n) tile(vpf[t], d.V, d.ldv, 16 * (wave + 8 * t), n);
+            for (int r0 = 16 * (wave + 8 * SVD_VPF); r0 < n; r0 += 128) {
+              double x[4];
+#pragma unroll
+              for (int kk = 0; kk < 4; ++kk) {
+                const int q = 4 * kk + kr;
+                x[kk] = (q < nc && r0 + cl < n) ? d.V[(size_t)cols[q] * d.ldv + r0 + cl] : 0.0;
+              }
+              tile(x, d.V, d.ldv, r0, n);
+            }
+          }
+          for (int r0 = 16 * wave; r0 < m; r0 += 128) {
+            double x[4];
+#pragma unroll
+            for (int kk = 0; kk < 4; ++kk) {
+              const int q = 4 * kk + kr;
+              x[kk] = (q < nc && r0 + cl < m) ? L[q * m + r0 + cl] : 0.0;
+            }
+            tile(x, d.A, d.lda, r0, m);
           }
         }
         if (tid == 0) atomicOr(&fl[mi], 1);
