@@ -1108,8 +1108,19 @@ static void launch_nodes(Ctx& c, const std::vector<TsqrNode>& v) {
     H2_CHECK(nd.w <= TS_W && nd.ra + nd.rb <= TS_RS * 64 && nd.ra + nd.rb >= nd.w, H2_EINVAL,
              "TSQR node shape out of range");
   auto* dd = (TsqrNode*)c.stage.put(v.data(), v.size() * sizeof(TsqrNode), c.s);
+  VTimer vt(c.s);
   k_tsqr_node<<<(unsigned)v.size(), 1024, 0, c.s>>>(dd);
   H2_LAUNCH_CHECK();
+  if (vt.on()) {
+    int w = 0, rows = 0, q = 0;
+    for (auto& nd : v) {
+      w = std::max(w, nd.w);
+      rows = std::max(rows, nd.ra + nd.rb);
+      q += nd.Q != nullptr;
+    }
+    std::fprintf(stderr, "    [tsqr node] %zu nodes, w %d, rows %d, %d with Q: %.3f ms\n", v.size(), w, rows,
+                 q, vt.stop());
+  }
 }
 
 void qr_tall_batched(Ctx& c, const std::vector<QRDesc>& ds) {
