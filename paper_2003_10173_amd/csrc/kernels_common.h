@@ -76,19 +76,29 @@ __device__ inline T wave_sum(T v) {
 }
 
 // DPP move of a double (both 32-bit halves); lanes whose row is outside
-// ROW_MASK, or whose source lane is invalid, read 0
+// ROW_MASK keep their own value
 template <int CTRL, int ROW_MASK>
 __device__ inline double dpp_f64(double v) {
   const uint64_t b = __builtin_bit_cast(uint64_t, v);
-  const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)b, CTRL, ROW_MASK, 0xf, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(b >> 32), CTRL, ROW_MASK, 0xf, false);
+  const int lo = __builtin_amdgcn_update_dpp((int)(uint32_t)b, (int)(uint32_t)b, CTRL, ROW_MASK, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp((int)(uint32_t)(b >> 32), (int)(uint32_t)(b >> 32), CTRL, ROW_MASK,
+                                             0xf, false);
   return __builtin_bit_cast(double, ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+
+// value of lane `lane` (wave-uniform) as a uniform double
+__device__ inline double readlane_f64(double v, int lane) {
+  const uint64_t b = __builtin_bit_cast(uint64_t, v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, lane);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), lane);
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
 }
 
 // Sum over the 64 lanes of a wave, returned to every lane.  Data-parallel
 // moves (no LDS traffic): pairs and quads within each row of 16 lanes, the
 // half-row and row mirrors complete the row sums, two row broadcasts
-// accumulate the four rows into lane 63, which is read back as a uniform
+// accumulate the four rows into lane 63 (rows left out of a broadcast hold
+// partial values that lane 63 never reads), which is read back as a uniform
 // value.  Every lane of the wave must be active.
 template <>
 __device__ inline double wave_sum<double>(double v) {
@@ -98,10 +108,27 @@ __device__ inline double wave_sum<double>(double v) {
   v += dpp_f64<0x140, 0xf>(v);  // row_mirror
   v += dpp_f64<0x142, 0xa>(v);  // row_bcast:15 into rows 1 and 3
   v += dpp_f64<0x143, 0xc>(v);  // row_bcast:31 into rows 2 and 3
-  const uint64_t b = __builtin_bit_cast(uint64_t, v);
-  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, 63);
-  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), 63);
-  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+  return readlane_f64(v, 63);
+}
+
+// K independent wave sums at once, stage by stage, so that the data moves of
+// the K reductions overlap (same order of additions as wave_sum)
+template <int K>
+__device__ inline void wave_sum_n(double (&v)[K]) {
+#pragma unroll
+  for (int k = 0; k < K; ++k) v[k] += dpp_f64<0xB1, 0xf>(v[k]);
+#pragma unroll
+  for (int k = 0; k < K; ++k) v[k] += dpp_f64<0x4E, 0xf>(v[k]);
+#pragma unroll
+  for (int k = 0; k < K; ++k) v[k] += dpp_f64<0x141, 0xf>(v[k]);
+#pragma unroll
+  for (int k = 0; k < K; ++k) v[k] += dpp_f64<0x140, 0xf>(v[k]);
+#pragma unroll
+  for (int k = 0; k < K; ++k) v[k] += dpp_f64<0x142, 0xa>(v[k]);
+#pragma unroll
+  for (int k = 0; k < K; ++k) v[k] += dpp_f64<0x143, 0xc>(v[k]);
+#pragma unroll
+  for (int k = 0; k < K; ++k) v[k] = readlane_f64(v[k], 63);
 }
 
 template <class T>

@@ -191,7 +191,7 @@ __global__ void k_reduce_parts(const ReduceTask* __restrict__ tasks, int ntasks)
 void gemm_batched(Ctx& c, const std::vector<GemmDesc>& ds) {
   std::vector<GemmTask> tasks;
   std::vector<ReduceTask> reds;
-  constexpr int KCHUNK = 1024;
+  constexpr int KMIN = 256;
   for (const auto& d : ds) {
     if (d.M <= 0 || d.N <= 0) continue;
     const int tm = (d.M + TM - 1) / TM, tn = (d.N + TN - 1) / TN;
@@ -201,7 +201,12 @@ void gemm_batched(Ctx& c, const std::vector<GemmDesc>& ds) {
       tasks.push_back(t);
       continue;
     }
-    const int nsplit = (d.K > 2 * KCHUNK && tm * tn <= 64) ? std::min(64, (d.K + KCHUNK - 1) / KCHUNK) : 1;
+    // split K for products with few output tiles (the K loop is serial per
+    // tile): chunks of at least KMIN, about 64 tiles in all, decided per
+    // product alone so that a product's sums do not depend on its batch
+    int nsplit = 1;
+    if (d.K >= 2 * KMIN && tm * tn < 64)
+      nsplit = std::max(1, std::min({64, d.K / KMIN, (64 + tm * tn - 1) / (tm * tn)}));
     if (nsplit == 1) {
       tasks.push_back(GemmTask{d, tm, tn, 0, d.K, d.C, d.ldc, d.beta});
     } else {
@@ -404,9 +409,11 @@ __device__ inline bool jacobi_rotate(double* A, int lda, int m, double* V, int l
     be += y * y;
     ga += x * y;
   }
-  al = wave_sum(al);
-  be = wave_sum(be);
-  ga = wave_sum(ga);
+  double sums[3] = {al, be, ga};
+  wave_sum_n(sums);
+  al = sums[0];
+  be = sums[1];
+  ga = sums[2];
   if (ga == 0.0 || !(fabs(ga) > jacobi_tol(m) * sqrt(al) * sqrt(be))) return false;
   const double zeta = (be - al) / (2.0 * ga);
   double t;
@@ -982,7 +989,7 @@ __global__ __launch_bounds__(1024) void k_tsqr_node(const TsqrNode* __restrict__
           if (i == j) alpha = a[q][r];
         }
         s = wave_sum(s);
-        alpha = __shfl(alpha, j & 63, 64);
+        alpha = readlane_f64(alpha, j & 63);
         double tau = 0.0, scale = 0.0, beta = alpha;
         if (s != 0.0) {
           const double norm = sqrt(alpha * alpha + s);
