@@ -191,7 +191,7 @@ __global__ void k_reduce_parts(const ReduceTask* __restrict__ tasks, int ntasks)
 void gemm_batched(Ctx& c, const std::vector<GemmDesc>& ds) {
   std::vector<GemmTask> tasks;
   std::vector<ReduceTask> reds;
-  constexpr int KMIN = 256;
+  constexpr int KMIN = 128;
   for (const auto& d : ds) {
     if (d.M <= 0 || d.N <= 0) continue;
     const int tm = (d.M + TM - 1) / TM, tn = (d.N + TN - 1) / TN;
@@ -202,11 +202,11 @@ void gemm_batched(Ctx& c, const std::vector<GemmDesc>& ds) {
       continue;
     }
     // split K for products with few output tiles (the K loop is serial per
-    // tile): chunks of at least KMIN, about 64 tiles in all, decided per
+    // tile): chunks of at least KMIN, about 128 tiles in all, decided per
     // product alone so that a product's sums do not depend on its batch
     int nsplit = 1;
-    if (d.K >= 2 * KMIN && tm * tn < 64)
-      nsplit = std::max(1, std::min({64, d.K / KMIN, (64 + tm * tn - 1) / (tm * tn)}));
+    if (d.K >= 2 * KMIN && tm * tn < 128)
+      nsplit = std::max(1, std::min({64, d.K / KMIN, (128 + tm * tn - 1) / (tm * tn)}));
     if (nsplit == 1) {
       tasks.push_back(GemmTask{d, tm, tn, 0, d.K, d.C, d.ldc, d.beta});
     } else {
