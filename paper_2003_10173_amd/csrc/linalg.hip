@@ -925,39 +925,38 @@ void svd_batched(Ctx& c, const std::vector<SVDDesc>& ds) {
 }
 
 // ------------------------------------------------------------------ TSQR
-// Tall-skinny Householder QR (n <= 96 columns): row chunks of 96..191 rows are
-// factorised in LDS by one workgroup each, pairs of R factors are stacked and
-// factorised again up a binary tree, and the explicit Q is formed top-down by
-// batched GEMMs (Q = diag(Q_chunks) * ... * Q_root).  Backward stable for any
-// rank, like a single Householder QR.
-constexpr int TS_W = 96, TS_CH = 96, TS_LD = 193;
+// Tall-skinny Householder QR (n <= 96 columns): row chunks of at most 192
+// rows are factorised by one workgroup each, groups of up to 192 / n of the R
+// factors are stacked and factorised again up the tree, and the explicit Q is
+// formed top-down by batched GEMMs (Q = diag(Q_chunks) * ... * Q_root).
+// Backward stable for any rank, like a single Householder QR.
+constexpr int TS_W = 96, TS_ROWS = 192, TS_SRC = 8;
 
 struct TsqrNode {
-  const double* a;
-  int lda, ra;        // top rows
-  const double* b;
-  int ldb, rb;        // bottom rows (0: none)
+  const double* src[TS_SRC];  // stacked row blocks, rs rows each
+  int lds[TS_SRC];
+  int nsrc, rs;
   int w;
-  double* Q;          // (ra + rb) x w explicit Q
+  double* Q;          // (nsrc * rs) x w explicit Q (optional)
   int ldq;
   double* R;          // w x w, zero below the diagonal
   int ldr;
 };
 
-// One node = Householder QR of a stacked (ra + rb) x w block, rows <= 192,
+// One node = Householder QR of a stacked (nsrc * rs) x w block, rows <= 192,
 // w <= 96, held in registers: wave v owns columns v, v + 16, ... (at most 6),
 // lane l holds rows l, l + 64, l + 128.  Per column j the owner wave forms the
 // reflector and publishes it through LDS (double-buffered), after one barrier
 // every wave applies it to its own columns.  The explicit Q (when requested)
 // is accumulated backwards the same way: Q = H_0 ... H_{w-1} [I; 0].
 constexpr int TS_WAVES = 16, TS_CPW = (TS_W + TS_WAVES - 1) / TS_WAVES, TS_RS = 3;
-static_assert(TS_RS * 64 >= 2 * TS_W && TS_RS * 64 >= 2 * TS_CH - 1, "node rows must fit the lanes");
+static_assert(TS_RS * 64 >= TS_ROWS, "node rows must fit the lanes");
 
 __global__ __launch_bounds__(1024) void k_tsqr_node(const TsqrNode* __restrict__ nodes) {
   const TsqrNode d = nodes[blockIdx.x];
   __shared__ double vbuf[2][TS_RS * 64];
   __shared__ double tbuf[2];
-  const int m = d.ra + d.rb, w = d.w;
+  const int m = d.nsrc * d.rs, w = d.w;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   double a[TS_CPW][TS_RS];
 #pragma unroll
@@ -967,7 +966,10 @@ __global__ __launch_bounds__(1024) void k_tsqr_node(const TsqrNode* __restrict__
     for (int r = 0; r < TS_RS; ++r) {
       const int i = r * 64 + lane;
       double x = 0.0;
-      if (c < w && i < m) x = i < d.ra ? d.a[(size_t)c * d.lda + i] : d.b[(size_t)c * d.ldb + (i - d.ra)];
+      if (c < w && i < m) {
+        const int sb = i / d.rs, li = i - sb * d.rs;
+        x = d.src[sb][(size_t)c * d.lds[sb] + li];
+      }
       a[q][r] = x;
     }
   }
@@ -1112,7 +1114,8 @@ __global__ __launch_bounds__(1024) void k_tsqr_node(const TsqrNode* __restrict__
 static void launch_nodes(Ctx& c, const std::vector<TsqrNode>& v) {
   if (v.empty()) return;
   for (auto& nd : v)
-    H2_CHECK(nd.w <= TS_W && nd.ra + nd.rb <= TS_RS * 64 && nd.ra + nd.rb >= nd.w, H2_EINVAL,
+    H2_CHECK(nd.w <= TS_W && nd.nsrc >= 1 && nd.nsrc <= TS_SRC && nd.rs >= 1 &&
+                 nd.nsrc * nd.rs <= TS_ROWS && nd.nsrc * nd.rs >= nd.w, H2_EINVAL,
              "TSQR node shape out of range");
   auto* dd = (TsqrNode*)c.stage.put(v.data(), v.size() * sizeof(TsqrNode), c.s);
   VTimer vt(c.s);
@@ -1122,7 +1125,7 @@ static void launch_nodes(Ctx& c, const std::vector<TsqrNode>& v) {
     int w = 0, rows = 0, q = 0;
     for (auto& nd : v) {
       w = std::max(w, nd.w);
-      rows = std::max(rows, nd.ra + nd.rb);
+      rows = std::max(rows, nd.nsrc * nd.rs);
       q += nd.Q != nullptr;
     }
     std::fprintf(stderr, "    [tsqr node] %zu nodes, w %d, rows %d, %d with Q: %.3f ms\n", v.size(), w, rows,
@@ -1131,12 +1134,14 @@ static void launch_nodes(Ctx& c, const std::vector<TsqrNode>& v) {
 }
 
 void qr_tall_batched(Ctx& c, const std::vector<QRDesc>& ds) {
-  // per matrix: the tree of nodes (level 0 = chunks)
+  // per matrix: the tree of nodes (level 0 = chunks); a node of level l >= 1
+  // stacks the R factors of up to `fan` consecutive nodes of level l - 1
   struct Mat {
     QRDesc d;
-    std::vector<std::vector<int>> lvl_rows;   // rows of each node per level
+    int fan = 2;
+    std::vector<int> chunk_rows;               // level 0
     std::vector<std::vector<double*>> Qs, Rs;
-    std::vector<std::vector<int>> pass;       // 1: node passes its R through (no QR)
+    std::vector<std::vector<int>> nchild;      // children per node (1: R passed through)
   };
   std::vector<Mat> mats;
   for (auto& d : ds) {
@@ -1145,10 +1150,11 @@ void qr_tall_batched(Ctx& c, const std::vector<QRDesc>& ds) {
              "TSQR: needs n <= 96, m >= n, Q or R");
     Mat M;
     M.d = d;
-    const int nch = std::max(1, d.m / TS_CH);
-    std::vector<int> rows(nch, TS_CH);
-    rows.back() += d.m - nch * TS_CH;
-    M.lvl_rows.push_back(rows);
+    M.fan = std::min(TS_SRC, TS_ROWS / d.n);
+    // chunks of at most TS_ROWS rows and at least n rows, sizes balanced
+    int nch = (d.m + TS_ROWS - 1) / TS_ROWS;
+    while (nch > 1 && d.m / nch < d.n) --nch;
+    for (int i = 0; i < nch; ++i) M.chunk_rows.push_back(d.m / nch + (i < d.m % nch ? 1 : 0));
     mats.push_back(std::move(M));
   }
   if (mats.empty()) return;
@@ -1157,23 +1163,32 @@ void qr_tall_batched(Ctx& c, const std::vector<QRDesc>& ds) {
     std::vector<TsqrNode> nodes;
     for (auto& M : mats) {
       const int w = M.d.n;
-      auto& rows = M.lvl_rows[0];
       M.Qs.push_back({});
       M.Rs.push_back({});
-      M.pass.push_back(std::vector<int>(rows.size(), 0));
+      M.nchild.push_back(std::vector<int>(M.chunk_rows.size(), 0));
       int r0 = 0;
-      for (size_t i = 0; i < rows.size(); ++i) {
-        double* Q = M.d.Q ? c.scratch.get((size_t)rows[i] * w) : nullptr;
+      for (int rows : M.chunk_rows) {
+        double* Q = M.d.Q ? c.scratch.get((size_t)rows * w) : nullptr;
         double* R = c.scratch.get((size_t)w * w);
         M.Qs[0].push_back(Q);
         M.Rs[0].push_back(R);
-        nodes.push_back({M.d.A + r0, M.d.lda, rows[i], nullptr, 0, 0, w, Q, rows[i], R, w});
-        r0 += rows[i];
+        TsqrNode nd{};
+        nd.src[0] = M.d.A + r0;
+        nd.lds[0] = M.d.lda;
+        nd.nsrc = 1;
+        nd.rs = rows;
+        nd.w = w;
+        nd.Q = Q;
+        nd.ldq = rows;
+        nd.R = R;
+        nd.ldr = w;
+        nodes.push_back(nd);
+        r0 += rows;
       }
     }
     launch_nodes(c, nodes);
   }
-  // upward: pairs of R factors until one remains
+  // upward: groups of R factors until one remains
   for (int lev = 1;; ++lev) {
     std::vector<TsqrNode> nodes;
     bool any = false;
@@ -1183,22 +1198,36 @@ void qr_tall_batched(Ctx& c, const std::vector<QRDesc>& ds) {
       if ((int)M.Rs.size() < lev || M.Rs[lev - 1].size() == 1) continue;
       const std::vector<double*> prevR = M.Rs[lev - 1];   // copy: Rs grows below
       any = true;
-      const int cnt = ((int)prevR.size() + 1) / 2;
+      const int np = (int)prevR.size();
+      const int cnt = (np + M.fan - 1) / M.fan;
       M.Qs.push_back({});
       M.Rs.push_back({});
-      M.pass.push_back(std::vector<int>(cnt, 0));
+      M.nchild.push_back(std::vector<int>(cnt, 0));
       for (int i = 0; i < cnt; ++i) {
-        if (2 * i + 1 < (int)prevR.size()) {
-          double* Q = M.d.Q ? c.scratch.get((size_t)2 * w * w) : nullptr;
-          double* R = c.scratch.get((size_t)w * w);
-          M.Qs[lev].push_back(Q);
-          M.Rs[lev].push_back(R);
-          nodes.push_back({prevR[2 * i], w, w, prevR[2 * i + 1], w, w, w, Q, 2 * w, R, w});
-        } else {
+        const int k0 = i * M.fan, k = std::min(M.fan, np - k0);
+        M.nchild[lev][i] = k;
+        if (k == 1) {
           M.Qs[lev].push_back(nullptr);
-          M.Rs[lev].push_back(prevR[2 * i]);
-          M.pass[lev][i] = 1;
+          M.Rs[lev].push_back(prevR[k0]);
+          continue;
         }
+        double* Q = M.d.Q ? c.scratch.get((size_t)k * w * w) : nullptr;
+        double* R = c.scratch.get((size_t)w * w);
+        M.Qs[lev].push_back(Q);
+        M.Rs[lev].push_back(R);
+        TsqrNode nd{};
+        for (int j = 0; j < k; ++j) {
+          nd.src[j] = prevR[k0 + j];
+          nd.lds[j] = w;
+        }
+        nd.nsrc = k;
+        nd.rs = w;
+        nd.w = w;
+        nd.Q = Q;
+        nd.ldq = k * w;
+        nd.R = R;
+        nd.ldr = w;
+        nodes.push_back(nd);
       }
     }
     if (!any) break;
@@ -1240,17 +1269,18 @@ void qr_tall_batched(Ctx& c, const std::vector<QRDesc>& ds) {
       X[mi][lev - 1].assign(M.Rs[lev - 1].size(), nullptr);
       ldx[mi][lev - 1].assign(M.Rs[lev - 1].size(), w);
       for (size_t i = 0; i < cnt; ++i) {
-        if (M.pass[lev][i]) {  // R passed through: the child keeps this X
-          X[mi][lev - 1][2 * i] = X[mi][lev][i];
-          ldx[mi][lev - 1][2 * i] = ldx[mi][lev][i];
+        const int k = M.nchild[lev][i], k0 = (int)i * M.fan;
+        if (k == 1) {  // R passed through: the child keeps this X
+          X[mi][lev - 1][k0] = X[mi][lev][i];
+          ldx[mi][lev - 1][k0] = ldx[mi][lev][i];
           continue;
         }
-        double* Y = c.scratch.get((size_t)2 * w * w);
-        g.push_back({M.Qs[lev][i], X[mi][lev][i], Y, 2 * w, w, w, 2 * w, ldx[mi][lev][i], 2 * w, 0, 0, 1.0, 0.0});
-        X[mi][lev - 1][2 * i] = Y;
-        X[mi][lev - 1][2 * i + 1] = Y + w;
-        ldx[mi][lev - 1][2 * i] = 2 * w;
-        ldx[mi][lev - 1][2 * i + 1] = 2 * w;
+        double* Y = c.scratch.get((size_t)k * w * w);
+        g.push_back({M.Qs[lev][i], X[mi][lev][i], Y, k * w, w, w, k * w, ldx[mi][lev][i], k * w, 0, 0, 1.0, 0.0});
+        for (int j = 0; j < k; ++j) {
+          X[mi][lev - 1][k0 + j] = Y + (size_t)j * w;
+          ldx[mi][lev - 1][k0 + j] = k * w;
+        }
       }
     }
     gemm_batched(c, g);
@@ -1261,8 +1291,8 @@ void qr_tall_batched(Ctx& c, const std::vector<QRDesc>& ds) {
     auto& M = mats[mi];
     const int w = M.d.n;
     int r0 = 0;
-    for (size_t i = 0; i < M.lvl_rows[0].size(); ++i) {
-      const int rows = M.lvl_rows[0][i];
+    for (size_t i = 0; i < M.chunk_rows.size(); ++i) {
+      const int rows = M.chunk_rows[i];
       g.push_back({M.Qs[0][i], X[mi][0][i], M.d.Q + r0, rows, w, w, rows, ldx[mi][0][i], M.d.ldq, 0, 0, 1.0, 0.0});
       r0 += rows;
     }
@@ -1335,7 +1365,7 @@ void qr_auto(Ctx& c, const std::vector<QRDesc>& ds) {
   std::vector<CopyDesc> toq;
   for (auto d : ds) {
     if (d.m <= 0 || d.n <= 0) continue;
-    if (d.m < 2 * TS_CH || d.m < d.n) {
+    if (d.m < TS_ROWS || d.m < d.n) {
       small.push_back(d);
     } else if (d.n <= TS_W) {
       tall.push_back(d);
