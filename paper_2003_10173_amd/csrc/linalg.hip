@@ -783,7 +783,7 @@ __global__ __launch_bounds__(512) void k_svd_block(const SVDDesc* __restrict__ d
 
 // singular values = column norms, sorted descending; U = normalised columns;
 // V columns permuted accordingly (through A, which is no longer needed)
-__global__ __launch_bounds__(256) void k_svd_final(const SVDDesc* __restrict__ descs) {
+__global__ __launch_bounds__(1024) void k_svd_final(const SVDDesc* __restrict__ descs) {
   const SVDDesc d = descs[blockIdx.x];
   const int n = d.n, m = d.m;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -791,7 +791,7 @@ __global__ __launch_bounds__(256) void k_svd_final(const SVDDesc* __restrict__ d
   __shared__ int order[1024];
   double* A = d.A;
   const int lda = d.lda;
-  for (int col = wave; col < n; col += 4) {
+  for (int col = wave; col < n; col += 16) {
     const double* ca = A + (size_t)col * lda;
     double s = 0;
     for (int i = lane; i < m; i += 64) s += ca[i] * ca[i];
@@ -801,16 +801,16 @@ __global__ __launch_bounds__(256) void k_svd_final(const SVDDesc* __restrict__ d
   __syncthreads();
   // descending order, equal values by index: position of i = number of
   // values ranked before it
-  for (int i = tid; i < n; i += 256) {
+  for (int i = tid; i < n; i += 1024) {
     const double si = sig[i];
     int r = 0;
     for (int j = 0; j < n; ++j) r += (sig[j] > si) || (sig[j] == si && j < i);
     order[r] = i;
   }
   __syncthreads();
-  for (int e = tid; e < n; e += 256) d.sigma[e] = sig[order[e]];
+  for (int e = tid; e < n; e += 1024) d.sigma[e] = sig[order[e]];
   if (d.U) {
-    for (int e = tid; e < m * n; e += 256) {
+    for (int e = tid; e < m * n; e += 1024) {
       const int i = e % m, r = e / m;
       const int src = order[r];
       const double s = sig[src];
@@ -819,12 +819,12 @@ __global__ __launch_bounds__(256) void k_svd_final(const SVDDesc* __restrict__ d
   }
   __syncthreads();
   if (d.V) {
-    for (int e = tid; e < n * n; e += 256) {
+    for (int e = tid; e < n * n; e += 1024) {
       const int i = e % n, c = e / n;
       A[(size_t)c * lda + i] = d.V[(size_t)c * d.ldv + i];
     }
     __syncthreads();
-    for (int e = tid; e < n * n; e += 256) {
+    for (int e = tid; e < n * n; e += 1024) {
       const int i = e % n, r = e / n;
       d.V[(size_t)r * d.ldv + i] = A[(size_t)order[r] * lda + i];
     }
@@ -920,7 +920,7 @@ void svd_batched(Ctx& c, const std::vector<SVDDesc>& ds) {
       i0 = i1;
     }
   }
-  k_svd_final<<<(unsigned)all.size(), 256, 0, c.s>>>(dall);
+  k_svd_final<<<(unsigned)all.size(), 1024, 0, c.s>>>(dall);
   H2_LAUNCH_CHECK();
 }
 
@@ -1481,28 +1481,28 @@ void scale_columns(Ctx& c, const std::vector<ScaleDesc>& ds) {
 
 // one block per matrix, one wave per column: arg-max of |x| (first index on
 // ties), then the column is negated when that entry is negative
+// one wave per column: blockIdx.y selects the block, blockIdx.x a group of 4 columns
 __global__ __launch_bounds__(256) void k_canon_sign(const CopyDesc* __restrict__ ds) {
-  const CopyDesc d = ds[blockIdx.x];
+  const CopyDesc d = ds[blockIdx.y];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  double* X = const_cast<double*>(d.src);
-  for (int j = wave; j < d.cols; j += 4) {
-    double* col = X + (size_t)j * d.lds;
-    double best = -1.0;
-    int bi = 0x7fffffff;
-    for (int i = lane; i < d.rows; i += 64) {
-      const double a = fabs(col[i]);
-      if (a > best) { best = a; bi = i; }   // ascending i: keeps the first maximum
-    }
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-      const double ob = __shfl_xor(best, off, 64);
-      const int oi = __shfl_xor(bi, off, 64);
-      if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
-    }
-    const bool flip = bi < d.rows && col[bi] < 0.0;
-    if (flip)
-      for (int i = lane; i < d.rows; i += 64) col[i] = -col[i];
+  const int j = 4 * blockIdx.x + wave;
+  if (j >= d.cols) return;
+  double* col = const_cast<double*>(d.src) + (size_t)j * d.lds;
+  double best = -1.0;
+  int bi = 0x7fffffff;
+  for (int i = lane; i < d.rows; i += 64) {
+    const double a = fabs(col[i]);
+    if (a > best) { best = a; bi = i; }   // ascending i: keeps the first maximum
   }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    const double ob = __shfl_xor(best, off, 64);
+    const int oi = __shfl_xor(bi, off, 64);
+    if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+  }
+  const bool flip = bi < d.rows && col[bi] < 0.0;
+  if (flip)
+    for (int i = lane; i < d.rows; i += 64) col[i] = -col[i];
 }
 
 void canonical_signs(Ctx& c, const std::vector<CopyDesc>& blocks) {
@@ -1510,9 +1510,14 @@ void canonical_signs(Ctx& c, const std::vector<CopyDesc>& blocks) {
   for (auto& b : blocks)
     if (b.rows > 0 && b.cols > 0) v.push_back(b);
   if (v.empty()) return;
-  auto* dd = (CopyDesc*)c.stage.put(v.data(), v.size() * sizeof(CopyDesc), c.s);
-  k_canon_sign<<<(unsigned)v.size(), 256, 0, c.s>>>(dd);
-  H2_LAUNCH_CHECK();
+  int maxc = 0;
+  for (auto& b : v) maxc = std::max(maxc, b.cols);
+  for (size_t i0 = 0; i0 < v.size(); i0 += 65535) {
+    const size_t cnt = std::min<size_t>(65535, v.size() - i0);
+    auto* dd = (CopyDesc*)c.stage.put(v.data() + i0, cnt * sizeof(CopyDesc), c.s);
+    k_canon_sign<<<dim3((unsigned)((maxc + 3) / 4), (unsigned)cnt), 256, 0, c.s>>>(dd);
+    H2_LAUNCH_CHECK();
+  }
 }
 
 __global__ void k_zero(double* p, int rows, int cols, int ld) {
