@@ -831,7 +831,7 @@ __global__ __launch_bounds__(1024) void k_svd_final(const SVDDesc* __restrict__ 
   }
 }
 
-constexpr int SVD_COOP_MIN_N = 96;
+constexpr int SVD_COOP_MIN_N = 24;
 
 void svd_batched(Ctx& c, const std::vector<SVDDesc>& ds) {
   std::vector<SVDDesc> all, small, big;
