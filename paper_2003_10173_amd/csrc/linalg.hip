@@ -477,9 +477,13 @@ __global__ __launch_bounds__(512) void k_svd_sweeps(const SVDDesc* __restrict__ 
 // of V are then multiplied by the accumulated rotation W once.  Whether a
 // pair still needs rotating is decided on the Gram matrix of the current
 // columns (|a.b| > tol |a| |b|), so a sweep without rotations certifies the
-// columns themselves.  A grid-wide barrier separates rounds; every workgroup
-// executes the same number of barriers (rounds of the widest matrix,
-// identical termination decision from flags read after a barrier).
+// columns themselves.  Rounds are ordered by data flow: each block carries the
+// number of rounds it has been through, and a workgroup starts a round once
+// both of its blocks have finished the previous one (release/acquire at
+// device scope).  One grid-wide barrier per sweep precedes the termination
+// test, which every workgroup takes from the same flags.  A wait that does not
+// end within a few seconds marks status[1] (the singular values of the call
+// then come out as NaN) instead of hanging.
 constexpr int SVD_BS = 8, SVD_PC = 2 * SVD_BS, SVD_MMAX = 1024, SVD_INNER = 1, SVD_VPF = 4;
 typedef double svd_d4 __attribute__((ext_vector_type(4)));
 
@@ -512,6 +516,15 @@ __device__ inline void jacobi_cs(double al, double be, double ga, double& c, dou
   s = c * t;
 }
 
+// wait until *p >= v (device-scope load); false after a few seconds
+__device__ inline bool svd_wait(const int* p, int v) {
+  for (int it = 0; it < (1 << 22); ++it) {
+    if (__hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= v) return true;
+    __builtin_amdgcn_s_sleep(2);
+  }
+  return false;
+}
+
 // LDS ordering between the lanes of one wave (the wave runs in lockstep):
 // every LDS access issued before has completed, and no access is moved
 // across by the compiler
@@ -520,9 +533,12 @@ __device__ inline void wave_lds_sync() {
   __builtin_amdgcn_wave_barrier();
 }
 
+// flags: 3 x nmat rotation flags (one set per sweep, in turn); ver: nmat x
+// maxnb round counters of the blocks; status[0] = sweeps, status[1] = wait
+// timeout (all zero at launch)
 __global__ __launch_bounds__(512) void k_svd_block(const SVDDesc* __restrict__ descs,
                                                    const int* __restrict__ wg_start, int nmat,
-                                                   int maxnpb, int* flags, int* sweeps_out) {
+                                                   int maxnb, int* flags, int* ver, int* status) {
   cooperative_groups::grid_group grid = cooperative_groups::this_grid();
   __shared__ double L[SVD_PC * SVD_MMAX];
   __shared__ double Gp[8 * SVD_PC * SVD_PC];      // per-wave Gram partials
@@ -544,14 +560,24 @@ __global__ __launch_bounds__(512) void k_svd_block(const SVDDesc* __restrict__ d
   const int nb = (n + SVD_BS - 1) / SVD_BS;
   const int npb = nb + (nb & 1);
   const double tol = jacobi_tol(m);
+  int* vb = ver + (size_t)mi * maxnb;
   for (int sweep = 0; sweep < 60; ++sweep) {
-    int* fl = flags + (sweep & 1) * nmat;
-    for (int r = 0; r < maxnpb - 1; ++r) {
-      for (int k = wl; r < npb - 1 && k < npb / 2; k += nwg) {
+    int* fl = flags + (sweep % 3) * nmat;
+    // the set used two sweeps ago is free again: clear it for the next sweep
+    if (blockIdx.x == 0 && tid == 0)
+      for (int i = 0; i < nmat; ++i) atomicExch(&flags[((sweep + 1) % 3) * nmat + i], 0);
+    for (int r = 0; r < npb - 1; ++r) {
+      for (int k = wl; k < npb / 2; k += nwg) {
         int bi, bj;
         tournament_pair(npb, r, k, bi, bj);
+        const int rq = sweep * (npb - 1) + r;   // rounds both blocks went through before
         // gather the columns of both blocks (the dummy block has none)
         if (tid == 0) {
+          bool ok = true;
+          if (bi < nb) ok = svd_wait(vb + bi, rq) && ok;
+          if (bj < nb) ok = svd_wait(vb + bj, rq) && ok;
+          if (!ok) atomicOr(status + 1, 1);
+          __threadfence();
           int c = 0;
           for (int q = 0; q < SVD_BS; ++q) {
             const int ci = bi * SVD_BS + q;
@@ -633,12 +659,7 @@ __global__ __launch_bounds__(512) void k_svd_block(const SVDDesc* __restrict__ d
           }
         }
         __syncthreads();
-        if (!rot_any) {
-          // already orthogonal: the columns stay as they are
-          __syncthreads();
-          continue;
-        }
-        if (wave == 0) {
+        if (rot_any && wave == 0) {
           // cyclic two-sided Jacobi on G, W accumulating the rotations.  In
           // each step lane (P, Q) = (lane / 8, lane % 8) owns the 2 x 2 block of
           // G and of W at rows of pair P and columns of pair Q, so the update
@@ -700,7 +721,7 @@ __global__ __launch_bounds__(512) void k_svd_block(const SVDDesc* __restrict__ d
         // restore the orthogonality of the accumulated rotation lost to
         // rounding (one Newton-Schulz polar step Q <- Q (3I - Q^T Q) / 2) so
         // that the many block products applied to V do not drift
-        {
+        if (rot_any) {
           double* Gl = Gp;
           double* Wq = Gp + 256;
           if (tid < SVD_PC * SVD_PC) {
@@ -723,7 +744,7 @@ __global__ __launch_bounds__(512) void k_svd_block(const SVDDesc* __restrict__ d
         // cores, 16 rows per product: lane l supplies X(row r0 + l % 16, column
         // k0 + l / 16) and W(k0 + l / 16, l % 16); the result element
         // (r0 + 4 e + l / 16, l % 16) is in acc[e]
-        {
+        if (rot_any) {
           const int kr = lane >> 4, cl = lane & 15;
           double wb[4];
 #pragma unroll
@@ -764,18 +785,22 @@ __global__ __launch_bounds__(512) void k_svd_block(const SVDDesc* __restrict__ d
             }
             tile(x, d.A, d.lda, r0, m);
           }
+          if (tid == 0) atomicOr(&fl[mi], 1);
         }
-        if (tid == 0) atomicOr(&fl[mi], 1);
+        // both blocks have been through round rq: publish after all writes
         __syncthreads();
+        if (tid == 0) {
+          __threadfence();
+          if (bi < nb) atomicExch(vb + bi, rq + 1);
+          if (bj < nb) atomicExch(vb + bj, rq + 1);
+        }
       }
-      grid.sync();
-      if (r == 0 && blockIdx.x == 0 && threadIdx.x == 0)
-        for (int i = 0; i < nmat; ++i) atomicExch(&flags[((sweep + 1) & 1) * nmat + i], 0);
     }
+    grid.sync();
     int any = 0;
     for (int i = 0; i < nmat; ++i) any |= atomicAdd(&fl[i], 0);
     if (!any || sweep == 59) {
-      if (blockIdx.x == 0 && threadIdx.x == 0) atomicExch(sweeps_out, sweep + 1);
+      if (blockIdx.x == 0 && threadIdx.x == 0) atomicExch(status, sweep + 1);
       break;
     }
   }
@@ -783,7 +808,9 @@ __global__ __launch_bounds__(512) void k_svd_block(const SVDDesc* __restrict__ d
 
 // singular values = column norms, sorted descending; U = normalised columns;
 // V columns permuted accordingly (through A, which is no longer needed)
-__global__ __launch_bounds__(1024) void k_svd_final(const SVDDesc* __restrict__ descs) {
+// status[1] set (a block Jacobi wait timed out): singular values are NaN
+__global__ __launch_bounds__(1024) void k_svd_final(const SVDDesc* __restrict__ descs,
+                                                    const int* __restrict__ status) {
   const SVDDesc d = descs[blockIdx.x];
   const int n = d.n, m = d.m;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -808,7 +835,8 @@ __global__ __launch_bounds__(1024) void k_svd_final(const SVDDesc* __restrict__ 
     order[r] = i;
   }
   __syncthreads();
-  for (int e = tid; e < n; e += 1024) d.sigma[e] = sig[order[e]];
+  const bool failed = status[1] != 0;
+  for (int e = tid; e < n; e += 1024) d.sigma[e] = failed ? __builtin_nan("") : sig[order[e]];
   if (d.U) {
     for (int e = tid; e < m * n; e += 1024) {
       const int i = e % m, r = e / m;
@@ -852,6 +880,9 @@ void svd_batched(Ctx& c, const std::vector<SVDDesc>& ds) {
     k_svd_sweeps<<<(unsigned)small.size(), 512, 0, c.s>>>(dd);
     H2_LAUNCH_CHECK();
   }
+  // status[0]: sweeps of the last launch, status[1]: synchronisation timeout
+  int* status = (int*)c.scratch.get(1);
+  H2_HIP(hipMemsetAsync(status, 0, 2 * sizeof(int), c.s));
   if (!big.empty()) {
     static int capacity = 0;
     if (capacity == 0) {
@@ -877,19 +908,21 @@ void svd_batched(Ctx& c, const std::vector<SVDDesc>& ds) {
       }
       const int nm = (int)(i1 - i0);
       std::vector<int> start(nm + 1, 0);
-      int maxnpb = 0;
+      int maxnb = 0;
       for (int j = 0; j < nm; ++j) {
         start[j + 1] = start[j] + want[j];
-        const int nb = (big[i0 + j].n + SVD_BS - 1) / SVD_BS;
-        maxnpb = std::max(maxnpb, nb + (nb & 1));
+        maxnb = std::max(maxnb, (big[i0 + j].n + SVD_BS - 1) / SVD_BS);
       }
       auto* dd = (SVDDesc*)c.stage.put(big.data() + i0, nm * sizeof(SVDDesc), c.s);
       auto* dstart = (int*)c.stage.put(start.data(), start.size() * sizeof(int), c.s);
-      int* flags = (int*)c.scratch.get((size_t)nm + 1);  // 2 * nm + 1 ints
-      H2_HIP(hipMemsetAsync(flags, 0, (2 * nm + 1) * sizeof(int), c.s));
-      int* sweeps = flags + 2 * nm;
+      // 3 nm rotation flags, nm * maxnb round counters, sweeps
+      const size_t nint = (size_t)3 * nm + (size_t)nm * maxnb + 1;
+      int* flags = (int*)c.scratch.get((nint + 1) / 2);
+      H2_HIP(hipMemsetAsync(flags, 0, nint * sizeof(int), c.s));
+      int* ver = flags + 3 * nm;
+      int* sweeps = ver + (size_t)nm * maxnb;
       int nmi = nm;
-      void* args[] = {&dd, &dstart, &nmi, &maxnpb, &flags, &sweeps};
+      void* args[] = {&dd, &dstart, &nmi, &maxnb, &flags, &ver, &status};
       hipEvent_t e0 = nullptr, e1 = nullptr;
       if (verbose()) {
         H2_HIP(hipEventCreate(&e0));
@@ -904,14 +937,14 @@ void svd_batched(Ctx& c, const std::vector<SVDDesc>& ds) {
       const int tok = timing_begin(c.s);
       H2_HIP(hipLaunchCooperativeKernel((const void*)k_svd_block, dim3(start[nm]), dim3(512), args,
                                         0, c.s));
-      timing_end(tok, "k_svd_block", c.s, 0.0, sweeps, per_sweep);
+      timing_end(tok, "k_svd_block", c.s, 0.0, status, per_sweep);
       if (verbose()) {
         H2_HIP(hipEventRecord(e1, c.s));
         H2_HIP(hipEventSynchronize(e1));
         float ms = 0;
         H2_HIP(hipEventElapsedTime(&ms, e0, e1));
         int sw = 0;
-        H2_HIP(hipMemcpy(&sw, sweeps, sizeof(int), hipMemcpyDeviceToHost));
+        H2_HIP(hipMemcpy(&sw, status, sizeof(int), hipMemcpyDeviceToHost));
         std::fprintf(stderr, "    [svd] %d matrices, n %d..%d, m %d, %d workgroups: %d sweeps, %.2f ms\n",
                      nm, big[i0].n, big[i1 - 1].n, big[i0].m, start[nm], sw, ms);
         (void)hipEventDestroy(e0);
@@ -920,7 +953,7 @@ void svd_batched(Ctx& c, const std::vector<SVDDesc>& ds) {
       i0 = i1;
     }
   }
-  k_svd_final<<<(unsigned)all.size(), 1024, 0, c.s>>>(dall);
+  k_svd_final<<<(unsigned)all.size(), 1024, 0, c.s>>>(dall, status);
   H2_LAUNCH_CHECK();
 }
 
