@@ -1398,7 +1398,7 @@ void qr_auto(Ctx& c, const std::vector<QRDesc>& ds) {
   std::vector<CopyDesc> toq;
   for (auto d : ds) {
     if (d.m <= 0 || d.n <= 0) continue;
-    if (d.m < TS_ROWS || d.m < d.n) {
+    if (d.m < d.n) {
       small.push_back(d);
     } else if (d.n <= TS_W) {
       tall.push_back(d);
