@@ -979,99 +979,148 @@ struct TsqrNode {
 // One node = Householder QR of a stacked (nsrc * rs) x w block, rows <= 192,
 // w <= 96, held in registers: wave v owns columns v, v + 16, ... (at most 6),
 // lane l holds rows l, l + 64, l + 128.  Per column j the owner wave forms the
-// reflector and publishes it through LDS (double-buffered), after one barrier
-// every wave applies it to its own columns.  The explicit Q (when requested)
-// is accumulated backwards the same way: Q = H_0 ... H_{w-1} [I; 0].
+// reflector and publishes it through LDS (double-buffered); after one barrier
+// every wave applies it to its own columns, the owner of the next column
+// first (see the factorisation loop).  The explicit Q (when requested) is
+// accumulated backwards the same way: Q = H_0 ... H_{w-1} [I; 0].
 constexpr int TS_WAVES = 16, TS_CPW = (TS_W + TS_WAVES - 1) / TS_WAVES, TS_RS = 3;
 static_assert(TS_RS * 64 >= TS_ROWS, "node rows must fit the lanes");
 
+// reflector of column j (rows held as col[r] = row r * 64 + lane): v below the
+// diagonal (v_j = 1) stays in col, beta goes on the diagonal; v and tau are
+// published to vb (rows) and tb (one value); returns tau
+__device__ __forceinline__ double tsqr_reflect(double (&col)[TS_RS], int j, int lane, double* vb,
+                                               double* tb) {
+  double s = 0.0, alpha = 0.0;
+#pragma unroll
+  for (int r = 0; r < TS_RS; ++r) {
+    const int i = r * 64 + lane;
+    if (i > j) s += col[r] * col[r];
+    if (i == j) alpha = col[r];
+  }
+  s = wave_sum(s);
+  alpha = readlane_f64(alpha, j & 63);
+  double tau = 0.0, scale = 0.0, beta = alpha;
+  if (s != 0.0) {
+    const double norm = sqrt(alpha * alpha + s);
+    beta = alpha >= 0 ? -norm : norm;
+    tau = (beta - alpha) / beta;
+    scale = 1.0 / (alpha - beta);
+  }
+#pragma unroll
+  for (int r = 0; r < TS_RS; ++r) {
+    const int i = r * 64 + lane;
+    double v = 0.0;
+    if (i > j) {
+      if (s != 0.0) col[r] *= scale;
+      v = col[r];
+    } else if (i == j) {
+      col[r] = beta;
+      v = 1.0;
+    }
+    vb[i] = v;
+  }
+  if (lane == 0) *tb = tau;
+  return tau;
+}
+
+// explicit-Q set-up of column j: publish v_j and tau, column := e_j - tau v_j
+__device__ __forceinline__ void tsqr_publish(double (&col)[TS_RS], double tau, int j, int lane, double* vb,
+                                             double* tb) {
+#pragma unroll
+  for (int r = 0; r < TS_RS; ++r) {
+    const int i = r * 64 + lane;
+    double v = 0.0;
+    if (i > j) v = col[r];
+    else if (i == j) v = 1.0;
+    vb[i] = v;
+    col[r] = (i == j ? 1.0 : 0.0) - tau * v;
+  }
+  if (lane == 0) *tb = tau;
+}
+
 __global__ __launch_bounds__(1024) void k_tsqr_node(const TsqrNode* __restrict__ nodes) {
-  const TsqrNode d = nodes[blockIdx.x];
+  const TsqrNode& d = nodes[blockIdx.x];
   __shared__ double vbuf[2][TS_RS * 64];
   __shared__ double tbuf[2];
-  const int m = d.nsrc * d.rs, w = d.w;
+  __shared__ const double* rowp[TS_RS * 64];   // start of row i in its source
+  __shared__ int rowld[TS_RS * 64];
+  const int rs = d.rs, m = d.nsrc * rs, w = d.w;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (threadIdx.x < m) {
+    const int sb = threadIdx.x / rs;
+    rowp[threadIdx.x] = d.src[sb] + (threadIdx.x - sb * rs);
+    rowld[threadIdx.x] = d.lds[sb];
+  }
+  __syncthreads();
   double a[TS_CPW][TS_RS];
+  const double* rp[TS_RS];
+  int rl[TS_RS];
+#pragma unroll
+  for (int r = 0; r < TS_RS; ++r) {
+    const int i = r * 64 + lane;
+    rp[r] = i < m ? rowp[i] : nullptr;
+    rl[r] = i < m ? rowld[i] : 0;
+  }
 #pragma unroll
   for (int q = 0; q < TS_CPW; ++q) {
     const int c = wave + TS_WAVES * q;
 #pragma unroll
-    for (int r = 0; r < TS_RS; ++r) {
-      const int i = r * 64 + lane;
-      double x = 0.0;
-      if (c < w && i < m) {
-        const int sb = i / d.rs, li = i - sb * d.rs;
-        x = d.src[sb][(size_t)c * d.lds[sb] + li];
-      }
-      a[q][r] = x;
-    }
+    for (int r = 0; r < TS_RS; ++r) a[q][r] = (c < w && rp[r]) ? rp[r][(size_t)c * rl[r]] : 0.0;
   }
   double taus_own[TS_CPW];
 #pragma unroll
   for (int q = 0; q < TS_CPW; ++q) taus_own[q] = 0.0;
-  // ---- factorisation
+  // ---- factorisation.  Step j applies H_j to the columns right of j; the
+  // owner of column j + 1 updates that column first and forms reflector j + 1
+  // at raised priority, so the next step's reflector is ready at the barrier.
+  if (wave == 0 && w > 0) taus_own[0] = tsqr_reflect(a[0], 0, lane, vbuf[0], &tbuf[0]);
+  __syncthreads();
   for (int j = 0; j < w; ++j) {
-    const int owner = j % TS_WAVES, qj = j / TS_WAVES, buf = j & 1;
-    if (wave == owner) {
-#pragma unroll
-      for (int q = 0; q < TS_CPW; ++q) {
-        if (q != qj) continue;
-        double s = 0.0, alpha = 0.0;
-#pragma unroll
-        for (int r = 0; r < TS_RS; ++r) {
-          const int i = r * 64 + lane;
-          if (i > j) s += a[q][r] * a[q][r];
-          if (i == j) alpha = a[q][r];
-        }
-        s = wave_sum(s);
-        alpha = readlane_f64(alpha, j & 63);
-        double tau = 0.0, scale = 0.0, beta = alpha;
-        if (s != 0.0) {
-          const double norm = sqrt(alpha * alpha + s);
-          beta = alpha >= 0 ? -norm : norm;
-          tau = (beta - alpha) / beta;
-          scale = 1.0 / (alpha - beta);
-        }
-#pragma unroll
-        for (int r = 0; r < TS_RS; ++r) {
-          const int i = r * 64 + lane;
-          double v = 0.0;
-          if (i > j) {
-            if (s != 0.0) a[q][r] *= scale;
-            v = a[q][r];
-          } else if (i == j) {
-            a[q][r] = beta;
-            v = 1.0;
-          }
-          vbuf[buf][i] = v;
-        }
-        taus_own[q] = tau;
-        if (lane == 0) tbuf[buf] = tau;
-      }
-    }
-    __syncthreads();
+    const int buf = j & 1;
     const double tau = tbuf[buf];
-    if (tau == 0.0) continue;
     double v[TS_RS];
 #pragma unroll
     for (int r = 0; r < TS_RS; ++r) v[r] = vbuf[buf][r * 64 + lane];
-    double dot[TS_CPW];
+    const int nx = j + 1, qn = nx / TS_WAVES;
+    const bool lead = wave == nx % TS_WAVES && nx < w;
+    if (lead) {
+      __builtin_amdgcn_s_setprio(3);
 #pragma unroll
-    for (int q = 0; q < TS_CPW; ++q) {
-      double t = 0.0;
+      for (int q = 0; q < TS_CPW; ++q) {
+        if (q != qn) continue;
+        if (tau != 0.0) {
+          double t = 0.0;
 #pragma unroll
-      for (int r = 0; r < TS_RS; ++r) t += v[r] * a[q][r];
-      dot[q] = t;
+          for (int r = 0; r < TS_RS; ++r) t += v[r] * a[q][r];
+          t = wave_sum(t) * tau;
+#pragma unroll
+          for (int r = 0; r < TS_RS; ++r) a[q][r] -= v[r] * t;
+        }
+        taus_own[q] = tsqr_reflect(a[q], nx, lane, vbuf[nx & 1], &tbuf[nx & 1]);
+      }
+      __builtin_amdgcn_s_setprio(0);
     }
+    if (tau != 0.0) {
+      double dot[TS_CPW];
 #pragma unroll
-    for (int q = 0; q < TS_CPW; ++q) {
-      const int c = wave + TS_WAVES * q;
-      if (c > j && c < w) {
-        const double t = wave_sum(dot[q]) * tau;
+      for (int q = 0; q < TS_CPW; ++q) {
+        double t = 0.0;
 #pragma unroll
-        for (int r = 0; r < TS_RS; ++r) a[q][r] -= v[r] * t;
+        for (int r = 0; r < TS_RS; ++r) t += v[r] * a[q][r];
+        dot[q] = t;
+      }
+#pragma unroll
+      for (int q = 0; q < TS_CPW; ++q) {
+        const int c = wave + TS_WAVES * q;
+        if (c > j && c < w && !(lead && q == qn)) {
+          const double t = wave_sum(dot[q]) * tau;
+#pragma unroll
+          for (int r = 0; r < TS_RS; ++r) a[q][r] -= v[r] * t;
+        }
       }
     }
+    __syncthreads();
   }
   // R (w x w, upper triangular)
 #pragma unroll
@@ -1087,50 +1136,48 @@ __global__ __launch_bounds__(1024) void k_tsqr_node(const TsqrNode* __restrict__
     }
   }
   if (!d.Q) return;
-  __syncthreads();  // the last reflector's buffer is reused below
-  // ---- explicit Q, backwards: column j becomes H_j e_j, columns > j get H_j
+  // ---- explicit Q = H_0 ... H_{w-1} [I; 0], backwards.  Column j of Q is
+  // H_j e_j = e_j - tau_j v_j when step j begins; step j applies H_j to the
+  // columns right of j.  The owner of column j - 1 publishes its reflector and
+  // sets up that column during step j (it takes no part in step j).
+  if (w > 0 && wave == (w - 1) % TS_WAVES) {
+#pragma unroll
+    for (int q = 0; q < TS_CPW; ++q)
+      if (q == (w - 1) / TS_WAVES) tsqr_publish(a[q], taus_own[q], w - 1, lane, vbuf[(w - 1) & 1], &tbuf[(w - 1) & 1]);
+  }
+  __syncthreads();
   for (int j = w - 1; j >= 0; --j) {
-    const int owner = j % TS_WAVES, qj = j / TS_WAVES, buf = j & 1;
-    if (wave == owner) {
-#pragma unroll
-      for (int q = 0; q < TS_CPW; ++q) {
-        if (q != qj) continue;
-        const double tau = taus_own[q];
-#pragma unroll
-        for (int r = 0; r < TS_RS; ++r) {
-          const int i = r * 64 + lane;
-          double v = 0.0;
-          if (i > j) v = a[q][r];
-          else if (i == j) v = 1.0;
-          vbuf[buf][i] = v;
-          a[q][r] = (i == j ? 1.0 : 0.0) - tau * v;
-        }
-        if (lane == 0) tbuf[buf] = tau;
-      }
-    }
-    __syncthreads();
+    const int buf = j & 1;
     const double tau = tbuf[buf];
-    if (tau == 0.0) continue;
     double v[TS_RS];
 #pragma unroll
     for (int r = 0; r < TS_RS; ++r) v[r] = vbuf[buf][r * 64 + lane];
-    double dot[TS_CPW];
+    const int pv = j - 1;
+    if (pv >= 0 && wave == pv % TS_WAVES) {
 #pragma unroll
-    for (int q = 0; q < TS_CPW; ++q) {
-      double t = 0.0;
-#pragma unroll
-      for (int r = 0; r < TS_RS; ++r) t += v[r] * a[q][r];
-      dot[q] = t;
+      for (int q = 0; q < TS_CPW; ++q)
+        if (q == pv / TS_WAVES) tsqr_publish(a[q], taus_own[q], pv, lane, vbuf[pv & 1], &tbuf[pv & 1]);
     }
+    if (tau != 0.0) {
+      double dot[TS_CPW];
 #pragma unroll
-    for (int q = 0; q < TS_CPW; ++q) {
-      const int c = wave + TS_WAVES * q;
-      if (c > j && c < w) {
-        const double t = wave_sum(dot[q]) * tau;
+      for (int q = 0; q < TS_CPW; ++q) {
+        double t = 0.0;
 #pragma unroll
-        for (int r = 0; r < TS_RS; ++r) a[q][r] -= v[r] * t;
+        for (int r = 0; r < TS_RS; ++r) t += v[r] * a[q][r];
+        dot[q] = t;
+      }
+#pragma unroll
+      for (int q = 0; q < TS_CPW; ++q) {
+        const int c = wave + TS_WAVES * q;
+        if (c > j && c < w) {
+          const double t = wave_sum(dot[q]) * tau;
+#pragma unroll
+          for (int r = 0; r < TS_RS; ++r) a[q][r] -= v[r] * t;
+        }
       }
     }
+    __syncthreads();
   }
 #pragma unroll
   for (int q = 0; q < TS_CPW; ++q) {
