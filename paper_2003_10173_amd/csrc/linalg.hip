@@ -226,19 +226,26 @@ void gemm_batched(Ctx& c, const std::vector<GemmDesc>& ds) {
   std::vector<int64_t> start(tasks.size() + 1, 0);
   for (size_t i = 0; i < tasks.size(); ++i)
     start[i + 1] = start[i] + (int64_t)tasks[i].tiles_m * tasks[i].tiles_n;
-  auto* dt = (GemmTask*)c.stage.put(tasks.data(), tasks.size() * sizeof(GemmTask), c.s);
-  auto* dsf = (int64_t*)c.stage.put(start.data(), start.size() * sizeof(int64_t), c.s);
   H2_CHECK(start.back() < (int64_t)1 << 31, H2_EINVAL, "GEMM batch too large");
-  k_gemm<<<(unsigned)start.back(), 256, 0, c.s>>>(dt, dsf, (int)tasks.size());
+  // tasks, tile offsets and reductions in one upload
+  const size_t bt = tasks.size() * sizeof(GemmTask), bs = start.size() * sizeof(int64_t);
+  const size_t ot = 0, os = (bt + 15) & ~(size_t)15, orr = (os + bs + 15) & ~(size_t)15;
+  std::vector<char> blob(orr + reds.size() * sizeof(ReduceTask));
+  std::memcpy(blob.data() + ot, tasks.data(), bt);
+  std::memcpy(blob.data() + os, start.data(), bs);
+  if (!reds.empty()) std::memcpy(blob.data() + orr, reds.data(), reds.size() * sizeof(ReduceTask));
+  char* dblob = (char*)c.stage.put(blob.data(), blob.size(), c.s);
+  k_gemm<<<(unsigned)start.back(), 256, 0, c.s>>>((const GemmTask*)(dblob + ot), (const int64_t*)(dblob + os),
+                                                   (int)tasks.size());
   H2_LAUNCH_CHECK();
   if (!reds.empty()) {
     int64_t mx = 0;
     for (auto& r : reds) mx = std::max(mx, (int64_t)r.M * r.N);
+    const ReduceTask* dr = (const ReduceTask*)(dblob + orr);
     for (size_t i0 = 0; i0 < reds.size(); i0 += 65535) {
       const size_t cnt = std::min<size_t>(65535, reds.size() - i0);
-      auto* dr = (ReduceTask*)c.stage.put(reds.data() + i0, cnt * sizeof(ReduceTask), c.s);
       dim3 grid((unsigned)((mx + 255) / 256), (unsigned)cnt);
-      k_reduce_parts<<<grid, 256, 0, c.s>>>(dr, (int)cnt);
+      k_reduce_parts<<<grid, 256, 0, c.s>>>(dr + i0, (int)cnt);
       H2_LAUNCH_CHECK();
     }
   }
@@ -1328,16 +1335,19 @@ void qr_tall_batched(Ctx& c, const std::vector<QRDesc>& ds) {
   for (auto& M : mats) maxlev = std::max(maxlev, (int)M.Rs.size() - 1);
   std::vector<std::vector<std::vector<const double*>>> X(mats.size());
   std::vector<std::vector<std::vector<int>>> ldx(mats.size());
-  std::vector<double> eye;
+  // identities of every matrix's root, one upload
+  int wmax = 0;
+  for (auto& M : mats) wmax = std::max(wmax, M.d.n);
+  std::vector<double> eye((size_t)wmax * wmax, 0.0);
+  for (int i = 0; i < wmax; ++i) eye[(size_t)i * wmax + i] = 1.0;
+  const double* deye = (const double*)c.stage.put(eye.data(), eye.size() * sizeof(double), c.s);
   for (size_t mi = 0; mi < mats.size(); ++mi) {
     auto& M = mats[mi];
-    const int top = (int)M.Rs.size() - 1, w = M.d.n;
+    const int top = (int)M.Rs.size() - 1;
     X[mi].assign(top + 1, {});
     ldx[mi].assign(top + 1, {});
-    eye.assign((size_t)w * w, 0.0);
-    for (int i = 0; i < w; ++i) eye[(size_t)i * w + i] = 1.0;
-    X[mi][top] = {(const double*)c.stage.put(eye.data(), eye.size() * sizeof(double), c.s)};
-    ldx[mi][top] = {w};
+    X[mi][top] = {deye};
+    ldx[mi][top] = {wmax};
   }
   for (int lev = maxlev; lev >= 1; --lev) {
     std::vector<GemmDesc> g;
