@@ -38,6 +38,10 @@ h2_status h2_test_mfma_layout(int kind, double* out);
 /* out[lane] = the wave-wide sum of in[0..63] as the kernels' reduction returns
    it to each lane of one 64-lane wave (host arrays of 64 doubles) */
 h2_status h2_test_wave_sum(const double* in, double* out);
+/* polls a workgroup of the multi-workgroup Jacobi SVD makes before it stops
+   waiting for the blocks of its round (then the call's singular values are
+   NaN); negative: 0.  Restore the default with 4194304. */
+void h2_test_svd_spin_limit(int polls);
 /* y = A x (FP64, user order, ld n, device pointers) with the matrix-core tile
    width fixed to nt (1, 2, 4 sixteen-vector tiles per workgroup; 0: tuned) */
 h2_status h2_test_gemv_tile(const h2_matrix* A, int nv, const double* x, double* y, int nt);

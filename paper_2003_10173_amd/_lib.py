@@ -112,6 +112,7 @@ SIGNATURES = {
     "h2_test_svd_batch": (C.c_int, [C.c_int, vp, vp, vp, vp, vp, vp]),
     "h2_test_mfma_layout": (C.c_int, [C.c_int, vp]),
     "h2_test_wave_sum": (C.c_int, [vp, vp]),
+    "h2_test_svd_spin_limit": (None, [C.c_int]),
     "h2_test_gemv_tile": (C.c_int, [vp, C.c_int, vp, vp, C.c_int]),
     "h2_test_tuned_tile": (C.c_int, [vp, C.c_int]),
     "h2_test_cholqr": (C.c_int, [C.c_int, C.c_int, vp, vp, vp, C.c_int]),

@@ -109,6 +109,9 @@ void canonical_signs(Ctx& c, const std::vector<CopyDesc>& blocks);
 void scale_columns(Ctx& c, const std::vector<ScaleDesc>& d);
 void qr_batched(Ctx& c, const std::vector<QRDesc>& d);
 void svd_batched(Ctx& c, const std::vector<SVDDesc>& d);
+// polls before a wait of the multi-workgroup Jacobi gives up (singular values
+// of that call come out as NaN); the default is a few seconds
+extern int svd_spin_limit;
 void copy_batched(Ctx& c, const std::vector<CopyDesc>& d);
 // tall-skinny Householder QR by a TSQR tree (n <= 96, m >= n): explicit Q and R
 void qr_tall_batched(Ctx& c, const std::vector<QRDesc>& d);

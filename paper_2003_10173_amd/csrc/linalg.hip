@@ -523,9 +523,11 @@ __device__ inline void jacobi_cs(double al, double be, double ga, double& c, dou
   s = c * t;
 }
 
-// wait until *p >= v (device-scope load); false after a few seconds
-__device__ inline bool svd_wait(const int* p, int v) {
-  for (int it = 0; it < (1 << 22); ++it) {
+// wait until *p >= v (device-scope load); false after `limit` polls (the
+// default, SVD_SPIN, is a few seconds)
+constexpr int SVD_SPIN = 1 << 22;
+__device__ inline bool svd_wait(const int* p, int v, int limit) {
+  for (int it = 0; it < limit; ++it) {
     if (__hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= v) return true;
     __builtin_amdgcn_s_sleep(2);
   }
@@ -545,7 +547,8 @@ __device__ inline void wave_lds_sync() {
 // timeout (all zero at launch)
 __global__ __launch_bounds__(512) void k_svd_block(const SVDDesc* __restrict__ descs,
                                                    const int* __restrict__ wg_start, int nmat,
-                                                   int maxnb, int* flags, int* ver, int* status) {
+                                                   int maxnb, int* flags, int* ver, int* status,
+                                                   int spin) {
   cooperative_groups::grid_group grid = cooperative_groups::this_grid();
   __shared__ double L[SVD_PC * SVD_MMAX];
   __shared__ double Gp[8 * SVD_PC * SVD_PC];      // per-wave Gram partials
@@ -581,8 +584,8 @@ __global__ __launch_bounds__(512) void k_svd_block(const SVDDesc* __restrict__ d
         // gather the columns of both blocks (the dummy block has none)
         if (tid == 0) {
           bool ok = true;
-          if (bi < nb) ok = svd_wait(vb + bi, rq) && ok;
-          if (bj < nb) ok = svd_wait(vb + bj, rq) && ok;
+          if (bi < nb) ok = svd_wait(vb + bi, rq, spin) && ok;
+          if (bj < nb) ok = svd_wait(vb + bj, rq, spin) && ok;
           if (!ok) atomicOr(status + 1, 1);
           __threadfence();
           int c = 0;
@@ -868,6 +871,10 @@ __global__ __launch_bounds__(1024) void k_svd_final(const SVDDesc* __restrict__ 
 
 constexpr int SVD_COOP_MIN_N = 24;
 
+// polls before a block Jacobi wait gives up (tests lower it to exercise the
+// timeout path)
+int svd_spin_limit = SVD_SPIN;
+
 void svd_batched(Ctx& c, const std::vector<SVDDesc>& ds) {
   std::vector<SVDDesc> all, small, big;
   for (auto& d : ds) {
@@ -929,7 +936,8 @@ void svd_batched(Ctx& c, const std::vector<SVDDesc>& ds) {
       int* ver = flags + 3 * nm;
       int* sweeps = ver + (size_t)nm * maxnb;
       int nmi = nm;
-      void* args[] = {&dd, &dstart, &nmi, &maxnb, &flags, &ver, &status};
+      int spin = svd_spin_limit;
+      void* args[] = {&dd, &dstart, &nmi, &maxnb, &flags, &ver, &status, &spin};
       hipEvent_t e0 = nullptr, e1 = nullptr;
       if (verbose()) {
         H2_HIP(hipEventCreate(&e0));

@@ -183,6 +183,8 @@ h2_status h2_test_svd_batch(int count, const int* m, const int* n, const double*
   });
 }
 
+void h2_test_svd_spin_limit(int polls) { svd_spin_limit = polls < 0 ? 0 : polls; }
+
 h2_status h2_test_mfma_layout(int kind, double* out) {
   return guarded_status([&] {
     H2_CHECK(kind >= 0 && kind <= 2 && out, H2_EINVAL, "kind 0..2 and out needed");

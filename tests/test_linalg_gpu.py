@@ -92,6 +92,24 @@ def test_jacobi_svd_matches_lapack(m, n, decay):
     assert np.abs(U[:, keep] * s[keep] @ V[:, keep].T - A).max() <= 1e-12 * sl[0] * n
 
 
+def test_jacobi_wait_limit_reports_nan():
+    """The multi-workgroup Jacobi orders its rounds by bounded waits on
+    per-block round counters.  With the poll limit forced to zero from the
+    host every wait gives up at once: the kernel still ends normally and the
+    call's singular values are NaN.  The default limit restores exact results."""
+    g = np.random.default_rng(11)
+    A = g.standard_normal((200, 160))
+    L().h2_test_svd_spin_limit(0)
+    try:
+        s, _, _ = svd(A)
+    finally:
+        L().h2_test_svd_spin_limit(1 << 22)
+    assert np.all(np.isnan(s))
+    s2, _, _ = svd(A)
+    sl = np.linalg.svd(A, compute_uv=False)
+    assert np.abs(s2 - sl).max() <= 1e-14 * sl[0] * 160
+
+
 def test_jacobi_svd_batch_uneven():
     """Several matrices of uneven sizes in one call (small and multi-workgroup
     ones mixed, odd block counts, a ragged last block)."""
