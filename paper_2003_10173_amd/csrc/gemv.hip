@@ -603,89 +603,6 @@ __global__ void k_scatter(int n, int nv, const int32_t* __restrict__ perm, V alp
   *yp = beta == V(0) ? val : val + beta * *yp;
 }
 
-// FP64 leaf stage with the operands of each source (near block or leaf basis,
-// K <= LEAF_MAX = 64 columns) loaded into registers before its products: the
-// k index of lane l in step s is 16 (l / 16) + s, so every lane reads 16
-// consecutive elements of its A row and of its B column and all of a
-// source's loads are in flight together.  Same sums as k_leaf_direct up to
-// the order of the k terms.
-template <int NT>
-__global__ __launch_bounds__(256) void k_leaf_f64(
-    int L, const int32_t* __restrict__ cstart, const int32_t* __restrict__ csize,
-    const int32_t* __restrict__ rank, const int64_t* __restrict__ kpre,
-    const int64_t* __restrict__ Uoff, const double* __restrict__ U,
-    const int32_t* __restrict__ near_ptr, const int32_t* __restrict__ near_col,
-    const int64_t* __restrict__ Doff, const double* __restrict__ D, int nv, const double* __restrict__ yh,
-    const double* __restrict__ x, int ldx, double alpha, double beta, double* __restrict__ y, int ldy) {
-  constexpr int NC = 16 * NT;
-  const int i = blockIdx.x;
-  const int leaf_base = (1 << L) - 1;
-  const int c = leaf_base + i;
-  const int r0 = cstart[c], m = csize[c];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  if (16 * wave >= m) return;
-  const int v0 = blockIdx.y * NC;
-  const int nvc = min(NC, nv - v0);
-  const int k = rank[c];
-  const int g0 = near_ptr[i], nnear = near_ptr[i + 1] - g0;
-  const int arow = 16 * wave + (lane & 15);
-  const bool arow_ok = arow < m;
-  const int kb = 16 * (lane >> 4);
-  mf_d4 acc[NT];
-#pragma unroll
-  for (int ct = 0; ct < NT; ++ct)
-#pragma unroll
-    for (int r = 0; r < 4; ++r) acc[ct][r] = 0;
-  const int nsrc = nnear + (k > 0 ? 1 : 0);
-  for (int src = 0; src < nsrc; ++src) {
-    const double* Ap;
-    const double* Bp;
-    int K, ldb;
-    if (src < nnear) {
-      const int g = g0 + src;
-      const int sc = leaf_base + near_col[g];
-      Ap = D + Doff[g];
-      K = csize[sc];
-      Bp = x + (size_t)v0 * ldx + cstart[sc];
-      ldb = ldx;
-    } else {
-      Ap = U + Uoff[i];
-      K = k;
-      Bp = yh + kpre[c] * nv + (size_t)v0 * k;
-      ldb = k;
-    }
-    double av[16], bv[NT][16];
-    const double* ap = Ap + (size_t)arow * K + kb;
-#pragma unroll
-    for (int t = 0; t < 16; ++t) av[t] = (arow_ok && kb + t < K) ? ap[t] : 0.0;
-#pragma unroll
-    for (int ct = 0; ct < NT; ++ct) {
-      const int col = ct * 16 + (lane & 15);
-      const double* bp = Bp + (size_t)col * ldb + kb;
-#pragma unroll
-      for (int t = 0; t < 16; ++t) bv[ct][t] = (col < nvc && kb + t < K) ? bp[t] : 0.0;
-    }
-#pragma unroll
-    for (int t = 0; t < 16; ++t) {
-      if (t < K) {
-#pragma unroll
-        for (int ct = 0; ct < NT; ++ct) acc[ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[t], bv[ct][t], acc[ct], 0, 0, 0);
-      }
-    }
-  }
-#pragma unroll
-  for (int ct = 0; ct < NT; ++ct)
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int row = 16 * wave + mf_row<double>(r, lane), col = ct * 16 + (lane & 15);
-      if (row < m && col < nvc) {
-        double* yp = y + (size_t)(v0 + col) * ldy + r0 + row;
-        const double val = alpha * acc[ct][r];
-        *yp = beta == 0.0 ? val : val + beta * *yp;
-      }
-    }
-}
-
 // ------------------------------------------------------------------ drivers
 template <class M, class V>
 static constexpr bool has_mfma() {
@@ -718,13 +635,7 @@ static void leaf_nt(const h2_matrix* A, int nv, V alpha, const V* xt, int ldx, V
   const unsigned gy = (unsigned)((nv + 16 * NT - 1) / (16 * NT));
   // FP64: operands straight from memory (8-byte loads); FP32 / BF16: LDS tiles
   // (their 4- and 2-byte element loads would waste memory transactions)
-  if constexpr (std::is_same<M, double>::value && std::is_same<V, double>::value)
-    k_leaf_f64<NT><<<dim3(1 << t->L, gy), 256, 0, s>>>(
-        t->L, t->d_cstart.as<int32_t>(), t->d_csize.as<int32_t>(), A->d_rank.as<int32_t>(),
-        A->d_kpre.as<int64_t>(), A->d_U_off.as<int64_t>(), A->st.U.as<M>(),
-        t->d_near_ptr.as<int32_t>(), t->d_near_col.as<int32_t>(), A->d_D_off.as<int64_t>(),
-        A->st.D.as<M>(), nv, yh, xt, ldx, alpha, beta, yt, ldy);
-  else if constexpr (std::is_same<M, double>::value)
+  if constexpr (std::is_same<M, double>::value)
     k_leaf_direct<M, V, NT><<<dim3(1 << t->L, gy), 256, 0, s>>>(
         t->L, t->d_cstart.as<int32_t>(), t->d_csize.as<int32_t>(), A->d_rank.as<int32_t>(),
         A->d_kpre.as<int64_t>(), A->d_U_off.as<int64_t>(), A->st.U.as<M>(),
