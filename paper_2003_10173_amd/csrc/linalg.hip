@@ -1464,7 +1464,15 @@ void qr_auto(Ctx& c, const std::vector<QRDesc>& ds) {
   for (auto d : ds) {
     if (d.m <= 0 || d.n <= 0) continue;
     if (d.m < d.n) {
-      small.push_back(d);
+      // wide: Q depends only on the first m columns (the m reflectors come
+      // from them), so a Q-only factorisation runs as TSQR of those columns
+      if (d.R == nullptr && d.Q != nullptr && d.m <= TS_W) {
+        QRDesc e = d;
+        e.n = d.m;
+        tall.push_back(e);
+      } else {
+        small.push_back(d);
+      }
     } else if (d.n <= TS_W) {
       tall.push_back(d);
     } else {
