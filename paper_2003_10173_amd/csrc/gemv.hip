@@ -603,6 +603,78 @@ __global__ void k_scatter(int n, int nv, const int32_t* __restrict__ perm, V alp
   *yp = beta == V(0) ? val : val + beta * *yp;
 }
 
+// nested-basis transfers on matrix cores, one workgroup per (cluster, NC
+// vectors).  Upsweep: x^_p = E_c1^T x^_c1 + E_c2^T x^_c2 for the parents p of
+// level l (E_c row-major k_c x k_p, taken transposed).  Downsweep:
+// y^_c += E_c y^_p for the clusters c of level l.  Ranks <= 64.
+template <class M, class V, int NT>
+__global__ __launch_bounds__(256) void k_up_transfer_mfma(int l, const int32_t* __restrict__ rank,
+                                                          const int64_t* __restrict__ kpre,
+                                                          const int64_t* __restrict__ Eoff,
+                                                          const M* __restrict__ E, int nv,
+                                                          V* __restrict__ xh) {
+  MF_SHARED(M, NT)
+  const int p = blockIdx.x;
+  const int cp = (1 << l) - 1 + p;
+  const int kp = rank[cp];
+  if (kp == 0) return;
+  const int c1 = (1 << (l + 1)) - 1 + 2 * p;
+  const int v0 = blockIdx.y * NC_;
+  const int nvc = min(NC_, nv - v0);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  auto src = [&](int q, const M*& Ap, int& K, bool& tA, const V*& Bp, int& ldb) {
+    const int c = c1 + q;
+    tA = true;
+    K = rank[c];
+    Ap = E + Eoff[c];
+    Bp = xh + kpre[c] * nv + (size_t)v0 * K;
+    ldb = K;
+  };
+  blockrow_mfma<M, V, NT>(kp, 2, src, nvc, acc, As, Bs);
+  V* out = xh + kpre[cp] * nv;
+#pragma unroll
+  for (int ct = 0; ct < NT; ++ct)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = 16 * wave + mf_row<M>(r, lane), col = ct * 16 + (lane & 15);
+      if (row < kp && col < nvc) out[(size_t)(v0 + col) * kp + row] = (V)acc[ct][r];
+    }
+}
+
+template <class M, class V, int NT>
+__global__ __launch_bounds__(256) void k_down_transfer_mfma(int l, const int32_t* __restrict__ rank,
+                                                            const int64_t* __restrict__ kpre,
+                                                            const int64_t* __restrict__ Eoff,
+                                                            const M* __restrict__ E, int nv,
+                                                            V* __restrict__ yh) {
+  MF_SHARED(M, NT)
+  const int ch = blockIdx.x;
+  const int cc = (1 << l) - 1 + ch;
+  const int cp = (1 << (l - 1)) - 1 + ch / 2;
+  const int kc = rank[cc], kp = rank[cp];
+  if (kc == 0 || kp == 0) return;
+  const int v0 = blockIdx.y * NC_;
+  const int nvc = min(NC_, nv - v0);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  auto src = [&](int q, const M*& Ap, int& K, bool& tA, const V*& Bp, int& ldb) {
+    (void)q;
+    tA = false;
+    K = kp;
+    Ap = E + Eoff[cc];
+    Bp = yh + kpre[cp] * nv + (size_t)v0 * kp;
+    ldb = kp;
+  };
+  blockrow_mfma<M, V, NT>(kc, 1, src, nvc, acc, As, Bs);
+  V* out = yh + kpre[cc] * nv;
+#pragma unroll
+  for (int ct = 0; ct < NT; ++ct)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = 16 * wave + mf_row<M>(r, lane), col = ct * 16 + (lane & 15);
+      if (row < kc && col < nvc) out[(size_t)(v0 + col) * kc + row] += (V)acc[ct][r];
+    }
+}
+
 // ------------------------------------------------------------------ drivers
 template <class M, class V>
 static constexpr bool has_mfma() {
@@ -679,9 +751,19 @@ static void gemv_tree_run(const h2_matrix* A, int nv, V alpha, const V* xt, int 
     if (!mf)
       k_up_leaf<M, V><<<1 << L, 256, 0, s>>>(L, cstart, csize, rank, kpre,
                                               A->d_U_off.as<int64_t>(), U, xt, ldx, nv, xh);
-    for (int l = L - 1; l >= 1; --l)
+    for (int l = L - 1; l >= 1; --l) {
+      if constexpr (has_mfma<M, V>()) {
+        if (mf) {
+          const unsigned gy = (unsigned)((nv + 16 * nt - 1) / (16 * nt));
+          if (nt == 1) k_up_transfer_mfma<M, V, 1><<<dim3(1 << l, gy), 256, 0, s>>>(l, rank, kpre, A->d_E_off.as<int64_t>(), E, nv, xh);
+          else if (nt == 2) k_up_transfer_mfma<M, V, 2><<<dim3(1 << l, gy), 256, 0, s>>>(l, rank, kpre, A->d_E_off.as<int64_t>(), E, nv, xh);
+          else k_up_transfer_mfma<M, V, 4><<<dim3(1 << l, gy), 256, 0, s>>>(l, rank, kpre, A->d_E_off.as<int64_t>(), E, nv, xh);
+          continue;
+        }
+      }
       k_up_transfer<M, V><<<1 << l, 256, 0, s>>>(l, rank, kpre, A->d_E_off.as<int64_t>(), E, nv,
                                                   xh);
+    }
     if constexpr (has_mfma<M, V>()) {
       if (nt == 1) coupling_nt<M, V, 1>(A, nv, xh, yh, s);
       else if (nt == 2) coupling_nt<M, V, 2>(A, nv, xh, yh, s);
@@ -691,9 +773,19 @@ static void gemv_tree_run(const h2_matrix* A, int nv, V alpha, const V* xt, int 
       k_coupling<M, V><<<t->nclusters() - 1, 256, 0, s>>>(
           rank, kpre, t->d_far_ptr.as<int32_t>(), t->d_far_col.as<int32_t>(),
           A->d_S_off.as<int64_t>(), S, nv, xh, yh);
-    for (int l = 2; l <= L; ++l)
+    for (int l = 2; l <= L; ++l) {
+      if constexpr (has_mfma<M, V>()) {
+        if (mf) {
+          const unsigned gy = (unsigned)((nv + 16 * nt - 1) / (16 * nt));
+          if (nt == 1) k_down_transfer_mfma<M, V, 1><<<dim3(1 << l, gy), 256, 0, s>>>(l, rank, kpre, A->d_E_off.as<int64_t>(), E, nv, yh);
+          else if (nt == 2) k_down_transfer_mfma<M, V, 2><<<dim3(1 << l, gy), 256, 0, s>>>(l, rank, kpre, A->d_E_off.as<int64_t>(), E, nv, yh);
+          else k_down_transfer_mfma<M, V, 4><<<dim3(1 << l, gy), 256, 0, s>>>(l, rank, kpre, A->d_E_off.as<int64_t>(), E, nv, yh);
+          continue;
+        }
+      }
       k_down_transfer<M, V><<<1 << l, 256, 0, s>>>(l, rank, kpre, A->d_E_off.as<int64_t>(), E, nv,
                                                     yh);
+    }
   }
   if constexpr (has_mfma<M, V>()) {
     if (nt == 1) leaf_nt<M, V, 1>(A, nv, alpha, xt, ldx, beta, yt, ldy, yh, s);
