@@ -76,13 +76,12 @@ __device__ inline T wave_sum(T v) {
 }
 
 // DPP move of a double (both 32-bit halves); lanes whose row is outside
-// ROW_MASK keep their own value
+// ROW_MASK receive no defined value (the sums below never read them)
 template <int CTRL, int ROW_MASK>
 __device__ inline double dpp_f64(double v) {
   const uint64_t b = __builtin_bit_cast(uint64_t, v);
-  const int lo = __builtin_amdgcn_update_dpp((int)(uint32_t)b, (int)(uint32_t)b, CTRL, ROW_MASK, 0xf, false);
-  const int hi = __builtin_amdgcn_update_dpp((int)(uint32_t)(b >> 32), (int)(uint32_t)(b >> 32), CTRL, ROW_MASK,
-                                             0xf, false);
+  const int lo = __builtin_amdgcn_mov_dpp((int)(uint32_t)b, CTRL, ROW_MASK, 0xf, false);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(uint32_t)(b >> 32), CTRL, ROW_MASK, 0xf, false);
   return __builtin_bit_cast(double, ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
 }
 
