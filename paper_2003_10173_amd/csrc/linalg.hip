@@ -1461,14 +1461,23 @@ void qr_auto(Ctx& c, const std::vector<QRDesc>& ds) {
   std::vector<QRDesc> small, tall;
   std::vector<CholQRDesc> blocked;
   std::vector<CopyDesc> toq;
+  std::vector<GemmDesc> wide_r;   // R(:, m:) = Q^T A(:, m:) of wide matrices
   for (auto d : ds) {
     if (d.m <= 0 || d.n <= 0) continue;
     if (d.m < d.n) {
-      // wide: Q depends only on the first m columns (the m reflectors come
-      // from them), so a Q-only factorisation runs as TSQR of those columns
-      if (d.R == nullptr && d.Q != nullptr && d.m <= TS_W) {
+      // wide: the m reflectors come from the first m columns, so Q is the Q of
+      // those columns (TSQR) and R = [R_1, Q^T A(:, m:)] (one GEMM)
+      if (d.m <= TS_W) {
         QRDesc e = d;
         e.n = d.m;
+        if (d.R != nullptr) {
+          double* Q = d.Q ? d.Q : c.scratch.get((size_t)d.m * d.m);
+          const int ldq = d.Q ? d.ldq : d.m;
+          e.Q = Q;
+          e.ldq = ldq;
+          wide_r.push_back({Q, d.A + (size_t)d.m * d.lda, d.R + (size_t)d.m * d.ldr, d.m, d.n - d.m, d.m,
+                            ldq, d.lda, d.ldr, 1, 0, 1.0, 0.0});
+        }
         tall.push_back(e);
       } else {
         small.push_back(d);
@@ -1495,6 +1504,7 @@ void qr_auto(Ctx& c, const std::vector<QRDesc>& ds) {
   VTimer vt(c.s);
   qr_batched(c, small);
   qr_tall_batched(c, tall);
+  gemm_batched(c, wide_r);
   copy_batched(c, toq);
   qr_blocked(c, blocked);
   if (vt.on() && !(small.empty() && tall.empty() && blocked.empty())) {
