@@ -120,9 +120,9 @@ void qr_tall_batched(Ctx& c, const std::vector<QRDesc>& d);
 // replaced by Q (m x n) and R (n x n, upper) is written to R
 void qr_blocked(Ctx& c, const std::vector<CholQRDesc>& d);
 // QR of each matrix by the fastest applicable kernel: TSQR for m >= n and
-// n <= 96 (and for wide matrices with m <= 96: TSQR of the first m columns,
-// R(:, m:) = Q^T A(:, m:) by GEMM), blocked QR for m >= n and n > 96, one
-// workgroup otherwise.  A is
+// n <= 96, blocked QR for m >= n and n > 96; a wide matrix (m < n) is
+// factorised through its first m columns (TSQR for m <= 96, blocked QR
+// otherwise) with R(:, m:) = Q^T A(:, m:) by GEMM.  A is
 // overwritten; Q (thin, optional) and R (optional, min(m,n) x n upper) as in
 // QRDesc.
 void qr_auto(Ctx& c, const std::vector<QRDesc>& d);

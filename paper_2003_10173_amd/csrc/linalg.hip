@@ -1461,7 +1461,8 @@ void qr_auto(Ctx& c, const std::vector<QRDesc>& ds) {
   std::vector<QRDesc> small, tall;
   std::vector<CholQRDesc> blocked;
   std::vector<CopyDesc> toq;
-  std::vector<GemmDesc> wide_r;   // R(:, m:) = Q^T A(:, m:) of wide matrices
+  std::vector<GemmDesc> wide_r, wide_r2;   // R(:, m:) = Q^T A(:, m:) of wide matrices
+  std::vector<CopyDesc> toq2;
   for (auto d : ds) {
     if (d.m <= 0 || d.n <= 0) continue;
     if (d.m < d.n) {
@@ -1480,7 +1481,14 @@ void qr_auto(Ctx& c, const std::vector<QRDesc>& ds) {
         }
         tall.push_back(e);
       } else {
-        small.push_back(d);
+        // blocked QR of the first m columns in place (A(:, :m) becomes Q)
+        double* R = d.R ? d.R : c.scratch.get((size_t)d.m * d.m);
+        const int ldr = d.R ? d.ldr : d.m;
+        blocked.push_back({d.A, d.lda, d.m, d.m, R, ldr});
+        if (d.R)
+          wide_r2.push_back({d.A, d.A + (size_t)d.m * d.lda, d.R + (size_t)d.m * d.ldr, d.m, d.n - d.m, d.m,
+                             d.lda, d.lda, d.ldr, 1, 0, 1.0, 0.0});
+        if (d.Q) toq2.push_back({d.A, d.lda, d.Q, d.ldq, d.m, d.m, 1.0, 0.0, 0});
       }
     } else if (d.n <= TS_W) {
       tall.push_back(d);
@@ -1507,6 +1515,8 @@ void qr_auto(Ctx& c, const std::vector<QRDesc>& ds) {
   gemm_batched(c, wide_r);
   copy_batched(c, toq);
   qr_blocked(c, blocked);
+  gemm_batched(c, wide_r2);
+  copy_batched(c, toq2);
   if (vt.on() && !(small.empty() && tall.empty() && blocked.empty())) {
     int mm = 0, mn = 0;
     for (auto& d : ds) { mm = std::max(mm, d.m); mn = std::max(mn, d.n); }
