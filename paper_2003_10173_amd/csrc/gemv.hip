@@ -467,7 +467,7 @@ __global__ __launch_bounds__(256) void k_leaf_direct(
       ldb = k;
     }
     const M* arow_p = Ap + (size_t)arow * K;
-#pragma unroll 4
+#pragma unroll 16
     for (int k0 = 0; k0 < K; k0 += T::KS) {
       const int kk = k0 + kq;
       if constexpr (BF) {
