@@ -224,7 +224,7 @@ def cpu_baseline(cfg, gpu_iters):
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(problems would shard by independent Hessians or subtrees); use --gpus 1",
               file=sys.stderr)
         sys.exit(2)
