@@ -356,8 +356,9 @@ h2_status h2_records_read(int64_t* count, float* features, float* targets);
  * the kernel runs on; h2_timing_enable(0) stops.  h2_timing_read waits for
  * the recorded launches of `kernel` (its name without namespace, e.g.
  * "k_svd_block") and returns their number, summed duration (ms) and summed
- * algorithmic work (flops for the Jacobi SVD: sweeps * n(n-1)/2 * (12m + 6n)
- * per m x n matrix).  Unknown names read as zero launches. */
+ * algorithmic work (flops for the SVD: 14 m n^2 + 8 n^3 per m x n matrix, the
+ * Golub-Van Loan count of a thin SVD with both factors, independent of the
+ * number of Jacobi sweeps).  Unknown names read as zero launches. */
 h2_status h2_timing_enable(int on);
 h2_status h2_timing_read(const char* kernel, int64_t* launches, double* total_ms, double* work);
 /* dst[0:n] = src[0:n] (device FP64 arrays) by a plain grid-stride kernel

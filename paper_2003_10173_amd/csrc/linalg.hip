@@ -797,7 +797,12 @@ __global__ __launch_bounds__(512) void k_svd_block(const SVDDesc* __restrict__ d
           }
           if (tid == 0) atomicOr(&fl[mi], 1);
         }
-        // both blocks have been through round rq: publish after all writes
+        // both blocks have been through round rq: publish after all writes.
+        // Every wave releases its own stores of A and V at device scope
+        // before the barrier, so that the counter written after it (by one
+        // thread, itself ordered by a device-scope fence) is only seen once
+        // all of them are visible to the other workgroups
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
         __syncthreads();
         if (tid == 0) {
           __threadfence();
@@ -815,6 +820,9 @@ __global__ __launch_bounds__(512) void k_svd_block(const SVDDesc* __restrict__ d
     }
   }
 }
+
+// ranking key of a singular value: NaN ranks below every number
+__device__ inline double svd_rank_key(double s) { return s == s ? s : -__builtin_inf(); }
 
 // singular values = column norms, sorted descending; U = normalised columns;
 // V columns permuted accordingly (through A, which is no longer needed)
@@ -837,11 +845,15 @@ __global__ __launch_bounds__(1024) void k_svd_final(const SVDDesc* __restrict__ 
   }
   __syncthreads();
   // descending order, equal values by index: position of i = number of
-  // values ranked before it
+  // values ranked before it.  A value that is not a number ranks as -inf, so
+  // the ranking is a total order and order[] a permutation for any input
   for (int i = tid; i < n; i += 1024) {
-    const double si = sig[i];
+    const double si = svd_rank_key(sig[i]);
     int r = 0;
-    for (int j = 0; j < n; ++j) r += (sig[j] > si) || (sig[j] == si && j < i);
+    for (int j = 0; j < n; ++j) {
+      const double sj = svd_rank_key(sig[j]);
+      r += (sj > si) || (sj == si && j < i);
+    }
     order[r] = i;
   }
   __syncthreads();
@@ -944,15 +956,18 @@ void svd_batched(Ctx& c, const std::vector<SVDDesc>& ds) {
         H2_HIP(hipEventCreate(&e1));
         H2_HIP(hipEventRecord(e0, c.s));
       }
-      double per_sweep = 0;
+      // algorithmic work of a thin SVD with both factors (m x n, U1 m x n
+      // and V n x n): 14 m n^2 + 8 n^3 flops (the Golub-Reinsch count of
+      // Golub and Van Loan), independent of how many sweeps Jacobi takes
+      double work = 0;
       for (int j = 0; j < nm; ++j) {
         const double n = big[i0 + j].n, m = big[i0 + j].m;
-        per_sweep += 0.5 * n * (n - 1) * (12.0 * m + 6.0 * n);
+        work += 14.0 * m * n * n + 8.0 * n * n * n;
       }
       const int tok = timing_begin(c.s);
       H2_HIP(hipLaunchCooperativeKernel((const void*)k_svd_block, dim3(start[nm]), dim3(512), args,
                                         0, c.s));
-      timing_end(tok, "k_svd_block", c.s, 0.0, status, per_sweep);
+      timing_end(tok, "k_svd_block", c.s, work, nullptr, 0.0);
       if (verbose()) {
         H2_HIP(hipEventRecord(e1, c.s));
         H2_HIP(hipEventSynchronize(e1));

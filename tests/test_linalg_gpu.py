@@ -92,6 +92,22 @@ def test_jacobi_svd_matches_lapack(m, n, decay):
     assert np.abs(U[:, keep] * s[keep] @ V[:, keep].T - A).max() <= 1e-12 * sl[0] * n
 
 
+def test_svd_ordering_with_nan_column_is_a_permutation():
+    """Singular values are ordered by a ranking that treats NaN as below every
+    number, so the ordering is a permutation even for non-finite input: the
+    finite values come first, descending, the NaN last, and the factors of the
+    finite columns are untouched (one-workgroup Jacobi path: a pair with a
+    NaN column is never rotated)."""
+    g = np.random.default_rng(5)
+    A = g.standard_normal((40, 6)) * np.array([1.0, 3.0, 0.5, 2.0, 5.0, 0.25])
+    A[:, 2] = np.nan
+    s, U, V = svd(A)
+    assert np.isnan(s[-1]) and np.all(np.isfinite(s[:-1]))
+    assert np.all(np.diff(s[:-1]) <= 0)
+    B = np.delete(A, 2, axis=1)
+    assert np.abs(s[:-1] - np.linalg.svd(B, compute_uv=False)).max() <= 1e-13 * s[0]
+
+
 def test_jacobi_wait_limit_reports_nan():
     """The multi-workgroup Jacobi orders its rounds by bounded waits on
     per-block round counters.  With the poll limit forced to zero from the

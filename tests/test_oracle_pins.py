@@ -351,6 +351,30 @@ def kernel_small():
     return T, H, lam
 
 
+def test_power_norm_matches_eigvalsh():
+    """nu from the power method (Sec. 3.2 norms) against the largest eigenvalue
+    of the dense Hessian from LAPACK: to 1e-10 when run to a relative change
+    of 1e-12, and within two digits (from below: ||A v|| <= lambda_max for a
+    unit v) at the default stopping rule.  Both workloads whose thresholds and
+    starting iterates use nu are checked."""
+    cases = []
+    cfg = si.config_kernel1d(512)
+    K = KernelHessian(cfg["points"], cfg["ell"], cfg["shift"])
+    cases.append((K.apply, K.dense(), cfg["points"], 32))
+    dcfg = si.config_diffusion2d(16)
+    G = DiffusionGN(dcfg)
+    cases.append((G.apply, dense_from_apply(G.apply, dcfg["n"]), dcfg["points"], 32))
+    for apply_user, Hd, pts, leaf in cases:
+        T = Tree(pts, leaf, 0.7)
+        A = tree_order(apply_user, T.perm)
+        lam_max = float(np.linalg.eigvalsh(Hd)[-1])
+        nu, it = power_norm(A, T.n, 1, rel=1e-12, max_it=500)
+        assert abs(nu - lam_max) <= 1e-10 * lam_max, (nu, lam_max, it)
+        nu2, it2 = power_norm(A, T.n, 1)
+        assert 3 <= it2 <= 30
+        assert 0.95 * lam_max <= nu2 <= lam_max * (1 + 1e-14), (nu2, lam_max)
+
+
 def test_residual_norm_matches_dense(kernel_small):
     T, H, lam = kernel_small
     X = H2Matrix.scaled_identity(T, 1.0 / lam[-1] * 0.9)

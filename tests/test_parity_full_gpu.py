@@ -1,0 +1,183 @@
+"""GPU parity at the workloads' full sizes, in the launch configuration the
+benchmark times.
+
+  * 1D kernel Hessian (N = 1024, leaf 32, cap 16, one round per level):
+    build, then the literal 20 Newton-Schulz iterations from X0 = A^T / nu^2
+    (Appendix A, Alg. 1 and Alg. 2) with a static construction threshold,
+    against the oracle run inside the test.
+  * diffusion Gauss-Newton Hessian on the 64 x 64 grid (N = 4096): build at
+    1e-4 and Newton-Schulz from I / nu to 1e-4 with the dynamic threshold,
+    against values the oracle stored (tests/golden/make_golden.py; the
+    oracle's run takes minutes).
+  * 2D kernel Hessian on the 256 x 256 grid (N = 65536, leaf 64, cap 32): the
+    GPU-built H2 is exported and the oracle's four-stage product (Sec. 3.2)
+    applied to the same 64 vectors; FP64 element-wise, FP32 and BF16 storage
+    reported against it.
+  * 8 of the 256 uneven 2D kernel Hessians (smallest, largest, 6 seeded
+    picks), built in one batched call, against stored oracle builds.
+
+Tolerances.  FP64 builds: equal ranks, rounds and applies; sampled entries of
+the operator within 1e-10 of the largest entry of its product (the FP64 parity
+bar).  Newton-Schulz: equal iteration counts and applies; residual history
+within 1e-8 relative plus 1e-10 absolute (E = ||I - A X||, and A X agreeing to
+1e-10 relative moves E by at most 1e-10); iterates within 1e-9 of the largest
+entry.  HGEMV FP64: element-wise within 1e-12 of max |y| (reordered sums of at
+most a few thousand terms).
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import seeded_inputs as si
+from oracle.hessians import KernelHessian, tree_order
+from oracle.ns import build as obuild, newton_schulz as ons, power_norm
+from oracle.tree import Tree as OTree
+from tests.h2_helpers import packed_to_oracle
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+h2 = pytest.importorskip("paper_2003_10173_amd")
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def dev(a):
+    return torch.tensor(np.ascontiguousarray(np.asarray(a).T), device="cuda")
+
+
+def host(t):
+    return t.cpu().numpy().T
+
+
+def check_sampled(G, rec, tol):
+    """Sampled entries of G applied to the stored probes against the oracle's."""
+    n = G.tree.n
+    P = si.gaussian_vectors(n, len(rec["values"]), rec["probe_seed"])
+    Y = host(G.gemv(dev(P)))
+    rows = np.asarray(rec["rows"])
+    for j, want in enumerate(rec["values"]):
+        got = Y[rows, j]
+        err = float(np.max(np.abs(got - np.asarray(want))))
+        assert err <= tol * rec["max_abs"][j], (j, err, rec["max_abs"][j])
+
+
+def check_build(st, G, rec):
+    assert st["norm"] == pytest.approx(rec["nu"], rel=1e-12)
+    assert st["applies"] == rec["applies"]
+    assert st["rounds"] == rec["rounds"]
+    assert st["range_cols"] == rec["range_cols"]
+    assert st["weak_rank"] == rec["weak_rank"]
+    assert G.ranks().tolist() == rec["ranks"]
+
+
+def test_kernel1d_literal_newton_schulz_matches_oracle():
+    """20 iterations from X0 = A^T / nu^2 with the static threshold eps / 10."""
+    cfg = si.config_kernel1d()
+    T = OTree(cfg["points"], cfg["leaf"], cfg["eta"])
+    K = KernelHessian(cfg["points"], cfg["ell"], cfg["shift"])
+    A = tree_order(K.apply, T.perm)
+    nu, _ = power_norm(A, T.n, cfg["seed"])
+    H, pr = obuild(A, T, cfg["tol"], nu, cfg["cap"], cfg["p"], adaptive=False,
+                   seed=cfg["seed"])
+    Xo, info = ons(H, 0.0, cfg["ns_iters"], T.leaf_size, cfg["p"], x0="scaled", dynamic=False,
+                   eps_build=cfg["tol"] / 10, adaptive=True, seed=cfg["seed"], nu_rel=1e-12)
+    gt = h2.Tree(cfg["points"], cfg["leaf"], cfg["eta"])
+    G, st = h2.build(gt, h2.KernelSampler(cfg["points"], cfg["ell"], cfg["shift"]),
+                     h2.opts(rank_cap=cfg["cap"], oversample=cfg["p"], tol=cfg["tol"],
+                             adaptive=0, seed=cfg["seed"]))
+    assert st["applies"] == pr.applies == 167
+    X, g = h2.newton_schulz(G, h2.ns_opts(eps=0.0, max_iter=cfg["ns_iters"], x0=1, dynamic=0,
+                                          eps_build=cfg["tol"] / 10, norm_rel=1e-12,
+                                          rank_cap=0, oversample=cfg["p"], adaptive=1,
+                                          seed=cfg["seed"]))
+    assert g["status"] == 1                 # budget exhausted, as the literal run intends
+    assert g["iterations"] == info["iterations"] == 20
+    assert g["norm"] == pytest.approx(info["nu"], rel=1e-12)
+    assert g["applies"] == info["applies"]
+    assert np.allclose(g["resid"], info["E"], rtol=1e-8, atol=1e-10)
+    # from A / nu^2 twenty iterations leave E close to 1 (kappa = 1.3e4)
+    assert 0.9 < g["resid"][-1] < 1.0
+    x = si.gaussian_vectors(T.n, 8, 5)
+    y = host(X.gemv(dev(x)))
+    want = Xo.matvec(x)
+    assert np.max(np.abs(y - want)) <= 1e-9 * np.max(np.abs(want))
+
+
+@pytest.fixture(scope="module")
+def diffusion64_golden():
+    with open(os.path.join(GOLDEN, "diffusion64_build_ns.json")) as f:
+        return json.load(f)
+
+
+def test_diffusion64_build_and_newton_schulz_match_oracle(diffusion64_golden):
+    gold = diffusion64_golden
+    cfg = si.config_diffusion2d(64)
+    gt = h2.Tree(cfg["points"], cfg["leaf"], cfg["eta"])
+    G, st = h2.build(gt, h2.DiffusionSampler(cfg),
+                     h2.opts(rank_cap=cfg["cap"], oversample=cfg["p"], tol=cfg["tol"],
+                             adaptive=1, max_rounds=16, seed=cfg["seed"]),
+                     allow_not_converged=False)
+    check_build(st, G, gold["build"])
+    check_sampled(G, gold["build_products"], 1e-10)
+    ns = gold["ns"]
+    X, g = h2.newton_schulz(G, h2.ns_opts(eps=ns["eps"], max_iter=ns["max_iter"], x0=0,
+                                          dynamic=1, rank_cap=0, oversample=ns["oversample"],
+                                          adaptive=1, max_rounds=16, seed=ns["seed"]))
+    assert g["status"] == 0 and ns["status"] == "converged"
+    assert g["iterations"] == ns["iterations"]
+    assert g["norm"] == pytest.approx(ns["nu"], rel=1e-12)
+    assert g["applies"] == ns["applies"]
+    assert np.allclose(g["resid"], ns["E"], rtol=1e-8, atol=1e-10)
+    assert g["resid"][-1] <= 1e-4
+    check_sampled(X, gold["ns_products"], 1e-9)
+
+
+def test_kernel2d_256_hgemv_elementwise_against_oracle():
+    cfg = si.config_kernel2d(256)
+    gt = h2.Tree(cfg["points"], cfg["leaf"], cfg["eta"])
+    G, st = h2.build(gt, h2.KernelSampler(cfg["points"], cfg["ell"], cfg["shift"]),
+                     h2.opts(rank_cap=cfg["cap"], oversample=cfg["p"], tol=cfg["tol"],
+                             adaptive=1, max_rounds=16, seed=cfg["seed"]))
+    T = OTree(cfg["points"], cfg["leaf"], cfg["eta"])
+    H = packed_to_oracle(T, *G.export())
+    x = si.gaussian_vectors(T.n, cfg["nv"], cfg["vec_seed"])
+    want = H.matvec(x)
+    scale = np.max(np.abs(want))
+    xd = dev(x)
+    y64 = host(G.gemv(xd))
+    err64 = float(np.max(np.abs(y64 - want))) / scale
+    assert err64 <= 1e-12, err64
+    errs = {}
+    for prec, name in ((h2.H2_FP32, "fp32"), (h2.H2_BF16, "bf16")):
+        B = G.convert(prec)
+        y = host(B.gemv(xd.float())).astype(np.float64)
+        errs[name] = float(np.max(np.abs(y - want))) / scale
+    print("HGEMV N=65536 nv=64 element-wise error vs oracle: fp64 %.2e fp32 %.2e bf16 %.2e"
+          % (err64, errs["fp32"], errs["bf16"]))
+    # FP32: operands and sums rounded at 2^-24 over ~2k-term sums;
+    # BF16: matrix entries and vectors rounded at 2^-9, FP32 sums
+    assert errs["fp32"] <= 1e-5
+    assert errs["bf16"] <= 2e-2
+
+
+@pytest.fixture(scope="module")
+def batch8_golden():
+    with open(os.path.join(GOLDEN, "batch8_build.json")) as f:
+        return json.load(f)
+
+
+def test_batch8_builds_match_oracle(batch8_golden):
+    recs = batch8_golden["problems"]
+    assert len(recs) == 8
+    ps = [si.batch_problem(r["index"]) for r in recs]
+    trees = [h2.Tree(p["points"], p["leaf"], p["eta"]) for p in ps]
+    samp = [h2.KernelSampler(p["points"], p["ell"], p["shift"]) for p in ps]
+    opts = [h2.opts(rank_cap=p["cap"], oversample=p["p"], tol=p["tol"], adaptive=1,
+                    max_rounds=16, seed=p["seed"]) for p in ps]
+    mats, stats, rc = h2.build_batched(trees, samp, opts)
+    assert rc == 0
+    for G, st, rec in zip(mats, stats, recs):
+        check_build(st, G, rec)
+        check_sampled(G, rec["products"], 1e-10)
