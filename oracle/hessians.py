@@ -11,6 +11,8 @@ Sec. 3.3).  All apply to user-ordered columns V of shape (N, nv).
                      observations at several times; F^T by exact adjoint steps
   AdvDiffGN          H = F^T F / sigma^2 with first-order upwind advection-diffusion
                      and bilinear point observations (misfit only, as in Sec. 4.2)
+  MinimalSurface     Hessian of the discrete minimal-surface area at a given surface
+                     (Appendix A, the shape-optimisation example)
 """
 import numpy as np
 
@@ -220,6 +222,99 @@ class AdvDiffGN:
         vec = V.ndim == 1
         V = V.reshape(self.n, -1)
         out = self.adjoint(self.forward(V)) / (self.sigma * self.sigma)
+        return out.ravel() if vec else out
+
+
+class MinimalSurface:
+    """Minimal-surface example of Appendix A (the surface-area objective
+    minimised over the height m of a surface over the unit square, with the
+    boundary heights fixed), discretised on a uniform grid.
+
+    Reading (the paper names finite differences on a 128 x 128 grid and says
+    the Hessian is exact up to discretisation): nodes (iy, ix), 0..g+1 on each
+    axis, spacing h = 1/(g+1); the g x g interior heights are the unknowns
+    (user index iy*g + ix), the boundary heights are data.  Each grid cell is
+    cut along its anti-diagonal into a lower triangle (iy,ix),(iy,ix+1),
+    (iy+1,ix) and an upper triangle (iy+1,ix+1),(iy+1,ix),(iy,ix+1); on each
+    triangle the height is linear, so its gradient is the pair of one-sided
+    differences along the triangle's legs, and
+        J(m) = sum_T (h^2 / 2) sqrt(1 + |grad m|_T^2).
+    The Hessian is exact for this J: with f(g) = sqrt(1 + |g|^2),
+        d^2 f / dg^2 = ((1 + |g|^2) I - g g^T) / (1 + |g|^2)^(3/2),
+    H v = sum_T (h^2 / 2) B_T^T f''(B_T m) B_T v, B_T the difference map of
+    triangle T.  At a flat surface H is the 5-point Laplacian stencil
+    (4 on the diagonal, -1 to each grid neighbour).
+    """
+
+    def __init__(self, cfg):
+        self.g = cfg["grid"]
+        self.n = self.g * self.g
+        self.h = 1.0 / (self.g + 1)
+        self.M = np.asarray(cfg["heights"], dtype=np.float64).reshape(self.g + 2, self.g + 2)
+
+    def _pad(self, V):
+        """Interior columns (n, nv) -> node array (g+2, g+2, nv), zero boundary."""
+        nv = V.shape[1]
+        P = np.zeros((self.g + 2, self.g + 2, nv))
+        P[1:-1, 1:-1] = V.reshape(self.g, self.g, nv)
+        return P
+
+    def _diffs(self, P):
+        """Leg differences / h on the lower and upper triangle of every cell."""
+        h = self.h
+        gx_lo = (P[:-1, 1:] - P[:-1, :-1]) / h
+        gy_lo = (P[1:, :-1] - P[:-1, :-1]) / h
+        gx_up = (P[1:, 1:] - P[1:, :-1]) / h
+        gy_up = (P[1:, 1:] - P[:-1, 1:]) / h
+        return gx_lo, gy_lo, gx_up, gy_up
+
+    def _scatter(self, qx_lo, qy_lo, qx_up, qy_up):
+        """sum_T (h^2/2) B_T^T q_T onto the nodes; interior part as (n, nv)."""
+        h = self.h
+        w = 0.5 * h * h / h
+        out = np.zeros((self.g + 2, self.g + 2) + qx_lo.shape[2:])
+        out[:-1, 1:] += w * qx_lo
+        out[:-1, :-1] -= w * (qx_lo + qy_lo)
+        out[1:, :-1] += w * qy_lo
+        out[1:, 1:] += w * (qx_up + qy_up)
+        out[1:, :-1] -= w * qx_up
+        out[:-1, 1:] -= w * qy_up
+        return out[1:-1, 1:-1].reshape(self.n, -1)
+
+    def _with_interior(self, m):
+        M = self.M.copy()
+        M[1:-1, 1:-1] = np.asarray(m).reshape(self.g, self.g)
+        return M
+
+    def objective(self, m=None):
+        M = self.M if m is None else self._with_interior(m)
+        gx_lo, gy_lo, gx_up, gy_up = self._diffs(M)
+        a = 0.5 * self.h * self.h
+        return float(a * np.sum(np.sqrt(1 + gx_lo ** 2 + gy_lo ** 2))
+                     + a * np.sum(np.sqrt(1 + gx_up ** 2 + gy_up ** 2)))
+
+    def gradient(self, m=None):
+        M = self.M if m is None else self._with_interior(m)
+        gx_lo, gy_lo, gx_up, gy_up = self._diffs(M)
+        s_lo = np.sqrt(1 + gx_lo ** 2 + gy_lo ** 2)
+        s_up = np.sqrt(1 + gx_up ** 2 + gy_up ** 2)
+        q = [a[..., None] for a in (gx_lo / s_lo, gy_lo / s_lo, gx_up / s_up, gy_up / s_up)]
+        return self._scatter(*q)[:, 0]
+
+    def apply(self, V):
+        V = np.asarray(V, dtype=np.float64)
+        vec = V.ndim == 1
+        V = V.reshape(self.n, -1)
+        gx_lo, gy_lo, gx_up, gy_up = self._diffs(self.M)
+        dx_lo, dy_lo, dx_up, dy_up = self._diffs(self._pad(V))
+        q = []
+        for gx, gy, dx, dy in ((gx_lo, gy_lo, dx_lo, dy_lo), (gx_up, gy_up, dx_up, dy_up)):
+            s2 = 1 + gx * gx + gy * gy
+            s3 = (s2 * np.sqrt(s2))[..., None]
+            gx, gy = gx[..., None], gy[..., None]
+            q.append(((1 + gy * gy) * dx - gx * gy * dy) / s3)
+            q.append((-gx * gy * dx + (1 + gx * gx) * dy) / s3)
+        out = self._scatter(q[0], q[1], q[2], q[3])
         return out.ravel() if vec else out
 
 

@@ -18,6 +18,18 @@ Readings taken here:
     accuracy eps_k / ||A||_2 -- the scale at which its error enters I - A X
   * stop when E <= eps or after max_iter iterations; divergence when E grows
     above 1 from one iteration to the next
+
+Higher-order forms (Appendix A.2 and A.3):
+  * hyperpower iteration of order l: X_{k+1} = X_k (I + R_k + ... + R_k^(l-1)),
+    R_k = I - A X_k; its sampler applies the sum Horner-style (Alg. 4):
+    Y = R = Omega, then l - 1 times R <- R - A (X_k R), Y <- Y + R, and
+    finally Y <- X_k Y.  l = 2 is Newton-Schulz, sampled by Alg. 3.
+  * unrolled iterations from a warm start: u Newton-Schulz steps written in
+    terms of X_0 give X_u = X_0 sum_{i < 2^u} (I - A X_0)^i (the printed
+    binomial form is garbled: its sum is the residual (I - A X_0)^(2^u), and
+    its sign is flipped), i.e. one hyperpower step of order 2^u, built in a
+    single construction.
+  * warm start: X0 is a given H2 matrix (the previous inverse).
 """
 import numpy as np
 
@@ -81,21 +93,50 @@ def build(apply_tree, tree, tol, nu, rank_cap, oversample, adaptive=True,
     return H, pr
 
 
+def ns_eval(Xk, A, Om):
+    """Samples of the Newton-Schulz iterate (Alg. 3): (2I - X_k A) X_k Omega."""
+    W = Xk.matvec_tree(Om)
+    return 2.0 * W - Xk.matvec_tree(A.matvec_tree(W))
+
+
+def hyperpower_eval(Xk, A, Om, order):
+    """Samples of the order-l hyperpower iterate (Alg. 4):
+    X_k (I + R + ... + R^(l-1)) Omega with R = I - A X_k."""
+    Y = Om.copy()
+    R = Om.copy()
+    for _ in range(order - 1):
+        R = R - A.matvec_tree(Xk.matvec_tree(R))
+        Y = Y + R
+    return Xk.matvec_tree(Y)
+
+
 def newton_schulz(A, eps, max_iter, rank_cap, oversample, x0="identity",
                   dynamic=False, eps_build=None, adaptive=True, max_rounds=16,
-                  seed=1, nu_rel=1e-2, resid_rel=1e-2):
+                  seed=1, nu_rel=1e-2, resid_rel=1e-2, order=2, unroll=0):
     """Hierarchical Newton-Schulz for a symmetric positive definite H2 A.
 
+    x0: "identity" (I / nu), "scaled" (A^T / nu^2) or an H2Matrix on A's tree
+    (warm start).  order: hyperpower order l >= 2 of every step (2 is
+    Newton-Schulz); unroll = u >= 1 builds u unrolled Newton-Schulz steps per
+    construction (order 2^u).
     Returns (X, info) with info holding the residual history, per-iteration
     sample counts and the status string.
     """
+    if unroll:
+        order = 2 ** unroll
+    if order < 2:
+        raise ValueError(order)
     tree = A.tree
     n = tree.n
     if eps_build is None:
         eps_build = eps / 10.0
     nuA, _ = power_norm(A.matvec_tree, n, seed, 0, rel=nu_rel,
                         max_it=30 if nu_rel >= 1e-2 else 500)
-    if x0 == "identity":
+    if isinstance(x0, H2Matrix):
+        if x0.tree is not tree:
+            raise ValueError("warm start must share A's tree")
+        X = x0
+    elif x0 == "identity":
         X = H2Matrix.scaled_identity(tree, 1.0 / nuA)
     elif x0 == "scaled":
         X = A.copy_scaled(1.0 / (nuA * nuA))
@@ -119,9 +160,12 @@ def newton_schulz(A, eps, max_iter, rank_cap, oversample, x0="identity",
         info["eps_k"].append(eps_k)
         Xk = X
 
-        def sampler(Om, Xk=Xk):
-            W = Xk.matvec_tree(Om)
-            return 2.0 * W - Xk.matvec_tree(A.matvec_tree(W))
+        if order == 2:
+            def sampler(Om, Xk=Xk):
+                return ns_eval(Xk, A, Om)
+        else:
+            def sampler(Om, Xk=Xk):
+                return hyperpower_eval(Xk, A, Om, order)
         X, pr = build(sampler, tree, eps_k, 1.0 / nuA, rank_cap, oversample,
                       adaptive, max_rounds, seed, k + 1)
         info["applies"].append(pr.applies)

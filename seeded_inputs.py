@@ -13,6 +13,8 @@ leaf 64, eps = 1e-4; Sec. 4.1, 4.2 and Appendix A):
   kernel2d      N = nx*ny cell centres of a grid; H = exp(-r/ell) + shift I
   batch         256 uneven 2D kernel problems on random-aspect grids
   advdiff2d     misfit Gauss-Newton Hessian of upwind advection-diffusion
+  minsurf2d     Hessian of the discrete minimal-surface area at a smooth surface
+                (two successive surfaces, as two steps of an optimisation)
 """
 import math
 
@@ -129,3 +131,24 @@ def learned_training_problem(i, base_seed=10000):
     return dict(name="kernel2d", n=side * side, points=points_grid_cell_centres(side, side),
                 ell=float(g.uniform(0.02, 0.2)), shift=float(10 ** g.uniform(-3, -2)),
                 leaf=64, eta=0.7, cap=32, p=10, tol=eps, seed=base_seed + i)
+
+
+def minsurf_heights(n, step=0):
+    """Node heights ((n+2) x (n+2), [iy, ix], boundary included) of a smooth
+    synthetic surface over the unit square, spacing h = 1/(n+1): a saddle
+    frame (x-1/2)^2 - (y-1/2)^2 on the boundary with an interior bump
+    0.1 sin(pi x) sin(2 pi y); step 1 adds an interior change
+    0.05 sin(2 pi x) sin(pi y), standing in for the next iterate of an
+    optimisation (the boundary stays fixed)."""
+    t = np.arange(n + 2, dtype=np.float64) / (n + 1)
+    Y, X = np.meshgrid(t, t, indexing="ij")
+    M = (X - 0.5) ** 2 - (Y - 0.5) ** 2 + 0.1 * np.sin(np.pi * X) * np.sin(2 * np.pi * Y)
+    if step >= 1:
+        M = M + 0.05 * np.sin(2 * np.pi * X) * np.sin(np.pi * Y)
+    return M
+
+
+def config_minsurf2d(n=128, step=0):
+    return dict(name="minsurf2d", grid=n, n=n * n, points=points_grid_interior(n),
+                heights=minsurf_heights(n, step), leaf=64, eta=0.7, cap=32, p=10,
+                adaptive=True, tol=1e-6, seed=7, eps=1e-4, eps_build=1e-6)
