@@ -1,9 +1,10 @@
 """Pins of the oracle's higher-order inversion forms (Appendix A.2 hyperpower
-iteration, Appendix A.3 unrolled iterations from a warm start) and of the
-minimal-surface Hessian of the Appendix A example, against what the
-mathematics fixes: closed forms through eigvalsh, equality with plain
-Newton-Schulz steps, finite differences of the objective, and the flat-surface
-stencil."""
+iteration, Appendix A.3 unrolled iterations from a warm start), of the
+minimal-surface Hessian of the Appendix A example and of the global low-rank
+pre-pass of Sec. 3.3, against what the mathematics fixes: closed forms through
+eigvalsh, equality with plain Newton-Schulz steps, finite differences of the
+objective, the flat-surface stencil, exactness for rank-r operators and the
+Halko-Martinsson-Tropp error bound."""
 import math
 
 import numpy as np
@@ -170,3 +171,82 @@ def test_minsurf_hessian_symmetric_positive_definite():
     # the flat-surface Laplacian bounds: lambda_max < 8 times the largest
     # coefficient 1 / s (s >= 1), so below 8
     assert lam[-1] < 8.0
+
+
+# ----------------------------------------------------------------- global low rank
+def _psd_with_decay(n, seed, rate):
+    g = np.random.default_rng(seed)
+    Q = np.linalg.qr(g.standard_normal((n, n)))[0]
+    lam = np.exp(-rate * np.arange(n))
+    return (Q * lam) @ Q.T, lam
+
+
+def test_global_lowrank_exact_for_rank_r():
+    """For H of rank r the range finder with r + p columns is exact:
+    B B^T = H to rounding and B has r columns."""
+    from oracle.lowrank import global_lowrank
+    g = np.random.default_rng(3)
+    C = g.standard_normal((300, 12))
+    H = C @ C.T
+    B, applies = global_lowrank(lambda V: H @ V, 300, 20, 10, seed=5)
+    assert applies == 2 * 30
+    assert B.shape[1] == 12
+    assert np.linalg.norm(B @ B.T - H, 2) <= 1e-12 * np.linalg.norm(H, 2)
+
+
+def test_global_lowrank_within_hmt_bound():
+    """||H - B B^T|| <= 2 (1 + 11 sqrt(r + p) sqrt(n)) lam_{r+1} + lam_{r+1}:
+    Halko-Martinsson-Tropp's bound for ||(I - Q Q^T) H||, taken twice for the
+    two-sided projection, plus the dropped eigenvalues of T (at most lam_{r+1}
+    by interlacing)."""
+    from oracle.lowrank import global_lowrank
+    n, r, p = 200, 15, 10
+    H, lam = _psd_with_decay(n, 4, 0.3)
+    B, _ = global_lowrank(lambda V: H @ V, n, r, p, seed=6)
+    err = np.linalg.norm(H - B @ B.T, 2)
+    assert err <= (2 * (1 + 11 * np.sqrt(r + p) * np.sqrt(n)) + 1) * lam[r]
+    # and, as typical for a decaying spectrum, within a small factor of the best
+    assert err <= 10 * lam[r]
+
+
+def test_build_lowrank_recovers_misfit_plus_sparse():
+    """Misfit-like global low rank plus a sparse regularisation (diffusion
+    Gauss-Newton Hessian on a 16 x 16 grid): the construction of H - B B^T
+    with B B^T added back meets the tolerance against the dense Hessian, and
+    its Hessian products are the global ones plus the residual construction's."""
+    from oracle.hessians import DiffusionGN
+    from oracle.lowrank import build_lowrank
+    cfg = si.config_diffusion2d(16)
+    G = DiffusionGN(cfg)
+    T = Tree(cfg["points"], 32, 0.7)
+    A = tree_order(G.apply, T.perm)
+    H, info = build_lowrank(A, T, 1e-6, 40, 24, 10, seed=2)
+    Hd = dense_from_apply(G.apply, cfg["n"])
+    err = np.linalg.norm(H.dense_user() - Hd, 2) / np.linalg.norm(Hd, 2)
+    assert err <= 1e-6
+    assert info["global_rank"] == 40 and info["global_applies"] == 100
+    assert info["applies"] == info["global_applies"] + info["residual_applies"]
+    # the residual has lost the dominant misfit directions
+    Rd = info["residual"].dense_user()
+    assert np.linalg.norm(Rd - (Hd - info_B_dense(info, T)), 2) <= 1e-6 * np.linalg.norm(Hd, 2)
+
+
+def info_B_dense(info, T):
+    B = np.empty_like(info["B"])
+    B[T.perm] = info["B"]
+    return B @ B.T
+
+
+def test_build_lowrank_exactly_low_rank_operator():
+    """An exactly rank-r operator: the residual is zero, so its construction
+    finds no rank anywhere and the result is B B^T."""
+    from oracle.lowrank import build_lowrank
+    T = Tree(si.points_1d_cell_centres(256), 32, 0.7)
+    C = np.random.default_rng(9).standard_normal((256, 8))
+    H = C @ C.T
+    Hs, info = build_lowrank(lambda V: H @ V, T, 1e-8, 16, 16, 10, seed=3)
+    pr = info["residual_peel"]
+    assert all(int(pr.kw[l].max()) == 0 for l in range(1, T.L + 1))
+    assert info["global_rank"] == 8
+    Ht = H[np.ix_(T.perm, T.perm)]
+    assert np.linalg.norm(Hs.dense_tree() - Ht, 2) <= 1e-10 * np.linalg.norm(H, 2)
