@@ -123,6 +123,9 @@ typedef struct {
   int cap_hit;                     /* 1 if the rank cap truncated a basis */
   double time_ms[8];               /* norm, sample, range, project, diag, recompress, sampler, total */
   int first_cols[H2_MAX_LEVELS];   /* width of the first sampling round at level l */
+  int global_rank;                 /* h2_build_lowrank: columns of B (else 0) */
+  int64_t global_applies;          /* h2_build_lowrank: sampler columns of the range finder */
+  int64_t update_applies;          /* h2_build_lowrank: H2 + low-rank columns of the update */
 } h2_build_stats;
 
 /*
@@ -151,6 +154,31 @@ void h2_opts_default(h2_opts* opts);
  */
 h2_status h2_build(const h2_tree* tree, h2_sampler_fn sampler, void* ctx, const h2_opts* opts,
                    hipStream_t stream, h2_matrix** out, h2_build_stats* stats);
+
+/*
+ * Construction combined with a global low-rank approximation (Sec. 3.3, the
+ * paragraph on combining with global low-rank approximations: for a data
+ * misfit of small global rank, B B^T first, the hierarchical construction of
+ * the residual H - B B^T next, and B B^T added back as a low-rank update).
+ *   1. nu = ||H||_2 by the power method through `sampler` (unless opts->norm > 0)
+ *   2. B (at most global_rank columns) by the two-pass randomized range finder
+ *      with global_rank + oversample Gaussian columns: Y = H Omega, Q = qr(Y),
+ *      T = Q^T H Q, T = V diag(s) V^T; the s above 1e-13 s_1 give
+ *      B = Q V diag(sqrt(s)), so B B^T = Q T Q^T (H symmetric positive
+ *      semi-definite)
+ *   3. h2_build of the residual, sampler H Omega - B (B^T Omega), threshold
+ *      tol * nu / (4 L), basis ranks capped at rank_cap + (columns of B): a
+ *      global rank-r term adds up to r to every block's rank
+ *   4. the update: h2_build from the sampler A_res Omega + B (B^T Omega) (no
+ *      Hessian products), same threshold; its result is *out
+ * stats: applies = the Hessian columns of steps 2 and 3 (norm_applies those of
+ * step 1), global_rank and global_applies as named, update_applies the
+ * columns of step 4; per-level weak ranks and rounds of step 3, strong ranks
+ * of the result.  global_rank + oversample <= 1024.
+ */
+h2_status h2_build_lowrank(const h2_tree* tree, h2_sampler_fn sampler, void* ctx,
+                           const h2_opts* opts, int global_rank, hipStream_t stream,
+                           h2_matrix** out, h2_build_stats* stats);
 
 /*
  * y = alpha * A x + beta * y for nv columns (Sec. 3.2, four-stage product:
@@ -197,7 +225,9 @@ h2_status h2_matrix_words(const h2_matrix* A, int64_t* words, int64_t* bytes);
 typedef struct {
   double eps;          /* stop when E = ||I - A X||_2 <= eps (0: never) */
   int max_iter;        /* iteration budget */
-  int x0;              /* 0: X0 = I / ||A||_2;  1: X0 = A^T / ||A||_2^2 */
+  int x0;              /* 0: X0 = I / ||A||_2;  1: X0 = A^T / ||A||_2^2;
+                          2: warm start X0 = x0_matrix (Appendix A.1: the
+                          inverse from the previous optimisation step) */
   int dynamic;         /* 1: eps_k = clamp(0.1 E^2, eps_build, 1e-2); 0: eps_build */
   double eps_build;    /* static construction threshold (0: eps / 10) */
   double norm_rel;     /* power-method relative change for ||A||_2 (0: 1e-2) */
@@ -213,7 +243,16 @@ typedef struct {
                           FP64, and the iterations after the switch (the
                           refinement) are FP64.  BF16 is refused: BF16 iterates
                           carry 2^-9 relative rounding, a residual floor of about
-                          4e-3 cond(A). */
+                          4e-3 cond(A).  Orders above 2 need FP64. */
+  int order;           /* hyperpower order l of every step (Appendix A.2):
+                          X_{k+1} = X_k (I + R_k + ... + R_k^(l-1)), R_k = I - A X_k,
+                          sampled Horner-style (Alg. 4, 2l - 1 HGEMVs per block of
+                          samples); 0 or 2: Newton-Schulz (Alg. 3, 3 HGEMVs) */
+  int unroll;          /* u > 0: each construction builds u Newton-Schulz steps
+                          unrolled in terms of the current iterate (Appendix A.3),
+                          X_{k+u} = X_k sum_{i < 2^u} R_k^i, i.e. order 2^u
+                          (1 <= u <= 10; order must then be 0) */
+  const h2_matrix* x0_matrix; /* x0 = 2: FP64 H2 on A's tree (not modified) */
 } h2_ns_opts;
 
 #define H2_MAX_NS_ITERS 128
@@ -295,6 +334,19 @@ h2_status h2_sampler_advdiff_create(int g, double kappa, int steps, const int32_
                                     double sigma, const int32_t* mode_a, const int32_t* mode_b,
                                     const double* mode_s, int n_modes, void** ctx);
 int h2_sampler_advdiff_apply(void* ctx, int n, int ncols, const double* omega, int ld_omega,
+                             double* y, int ld_y, hipStream_t stream);
+/*
+ * minsurf: Hessian of the discrete minimal-surface area (Appendix A, the
+ * shape-optimisation example: surface area over the unit square with the
+ * boundary heights fixed, on a g x g interior grid, h = 1/(g+1)).
+ * heights_host: (g+2) x (g+2) node heights, row-major [iy][ix], boundary
+ * included; unknowns are the interior nodes, user index (iy-1) g + (ix-1).
+ * Each cell is cut along its anti-diagonal into two triangles on which the
+ * height is linear; J = sum_T (h^2/2) sqrt(1 + |grad m|^2) and the sampler
+ * applies its exact Hessian at the given surface (a sparse SPD operator).
+ */
+h2_status h2_sampler_minsurf_create(int g, const double* heights_host, void** ctx);
+int h2_sampler_minsurf_apply(void* ctx, int n, int ncols, const double* omega, int ld_omega,
                              double* y, int ld_y, hipStream_t stream);
 /* sampler that applies an H2 matrix (h2_gemv) -- ctx is the h2_matrix pointer */
 int h2_sampler_h2_apply(void* ctx, int n, int ncols, const double* omega, int ld_omega,

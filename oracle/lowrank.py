@@ -16,7 +16,10 @@ Readings taken here (the paper gives no formulas):
     Hessians are symmetric positive semi-definite.  2 (r + p) products.
   * nu = ||H||_2 by the power method on H (as for a plain build) sets the
     threshold eps nu / (4 L) of both constructions below
-  * the construction of the residual uses the sampler H Omega - B (B^T Omega)
+  * the construction of the residual uses the sampler H Omega - B (B^T Omega);
+    its recompression caps basis ranks at rank_cap + r' (r' the columns of
+    B): a global rank-r' term adds up to r' to the rank of every block, so
+    the residual's blocks need that much room even where H's do not
   * the low-rank update A_res + B B^T is recompressed by the same construction
     applied to the sampler A_res Omega + B (B^T Omega): products with the H2
     and with B only, no Hessian products
@@ -25,6 +28,7 @@ import numpy as np
 
 from . import rng
 from .ns import build, power_norm
+from .peel import peel, recompress
 
 PHASE_GLOBAL = 7
 EIG_CUT = 1e-13
@@ -63,7 +67,8 @@ def build_lowrank(apply_tree, tree, tol, rank, rank_cap, oversample, adaptive=Tr
 
     def residual(Om):
         return apply_tree(Om) - B @ (B.T @ Om)
-    Hres, pr = build(residual, tree, tol, nu, rank_cap, oversample, adaptive, max_rounds, seed)
+    pr = peel(residual, tree, tol, nu, rank_cap, oversample, adaptive, max_rounds, seed)
+    Hres = recompress(tree, pr, tol, nu, rank_cap + B.shape[1])
 
     def total(Om):
         return Hres.matvec_tree(Om) + B @ (B.T @ Om)

@@ -15,7 +15,7 @@ from ._lib import (H2_BF16, H2_FP32, H2_FP64, H2BuildStats, H2Error, H2NSOpts, H
                    H2Opts, SAMPLER_FN, check, lib)
 
 __all__ = ["Tree", "H2Matrix", "build", "newton_schulz", "residual_norm", "KernelSampler",
-           "DiffusionSampler", "AdvDiffSampler", "H2Sampler", "PythonSampler", "opts",
+           "DiffusionSampler", "AdvDiffSampler", "MinSurfSampler", "H2Sampler", "PythonSampler", "opts",
            "ns_opts", "H2_FP64", "H2_FP32", "H2_BF16", "H2Error", "lib"]
 
 
@@ -253,6 +253,21 @@ class AdvDiffSampler(_NativeSampler):
         self._finish(h)
 
 
+class MinSurfSampler(_NativeSampler):
+    """Hessian of the discrete minimal-surface area at the surface
+    cfg["heights"] ((g+2) x (g+2) node heights, boundary included)."""
+    apply_name = "h2_sampler_minsurf_apply"
+
+    def __init__(self, cfg):
+        g = int(cfg["grid"])
+        hts = np.ascontiguousarray(cfg["heights"], dtype=np.float64)
+        if hts.shape != (g + 2, g + 2):
+            raise ValueError("heights must be (g+2) x (g+2)")
+        h = C.c_void_p()
+        check(lib().h2_sampler_minsurf_create(g, hts.ctypes.data, C.byref(h)), "minsurf")
+        self._finish(h)
+
+
 class H2Sampler(_SamplerBase):
     """Sampler applying an existing H2 matrix (for rebuild / idempotence checks)."""
 
@@ -322,9 +337,14 @@ def opts(**kw):
 
 
 def ns_opts(**kw):
+    """h2_ns_opts with defaults; x0_matrix takes an H2Matrix (warm start,
+    x0 = 2), kept alive with the options."""
     o = H2NSOpts()
     lib().h2_ns_opts_default(C.byref(o))
     for k, v in kw.items():
+        if k == "x0_matrix":
+            o._x0 = v
+            v = v.handle.value if v is not None else None
         setattr(o, k, v)
     return o
 
@@ -336,7 +356,9 @@ def stats_dict(st, levels):
                 strong_rank=list(st.strong_rank[:levels + 1]), applies=st.applies,
                 norm_applies=st.norm_applies,
                 norm=st.norm, converged=bool(st.converged), cap_hit=bool(st.cap_hit),
-                time_ms=list(st.time_ms), first_cols=list(st.first_cols[1:levels + 1]))
+                time_ms=list(st.time_ms), first_cols=list(st.first_cols[1:levels + 1]),
+                global_rank=st.global_rank, global_applies=st.global_applies,
+                update_applies=st.update_applies)
 
 
 def build(tree, sampler, o=None, stream=None, allow_not_converged=True):
@@ -348,6 +370,20 @@ def build(tree, sampler, o=None, stream=None, allow_not_converged=True):
     allow = (0, 1) if allow_not_converged else (0,)
     check(lib().h2_build(tree.handle, C.cast(sampler.fn, C.c_void_p), sampler.ctx, C.byref(o),
                          _stream(stream), C.byref(h), C.byref(st)), "h2_build", allow)
+    return H2Matrix(h, tree), stats_dict(st, tree.L)
+
+
+def build_lowrank(tree, sampler, global_rank, o=None, stream=None, allow_not_converged=True):
+    """Global low-rank pre-pass B B^T, construction of H - B B^T, and B B^T
+    added back (h2_build_lowrank); returns (H2Matrix, stats dict)."""
+    if o is None:
+        o = opts()
+    h = C.c_void_p()
+    st = H2BuildStats()
+    allow = (0, 1) if allow_not_converged else (0,)
+    check(lib().h2_build_lowrank(tree.handle, C.cast(sampler.fn, C.c_void_p), sampler.ctx,
+                                 C.byref(o), int(global_rank), _stream(stream), C.byref(h),
+                                 C.byref(st)), "h2_build_lowrank", allow)
     return H2Matrix(h, tree), stats_dict(st, tree.L)
 
 

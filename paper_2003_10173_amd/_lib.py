@@ -34,14 +34,16 @@ class H2BuildStats(C.Structure):
                 ("strong_rank", C.c_int * H2_MAX_LEVELS), ("applies", i64),
                 ("norm_applies", i64), ("norm", dbl),
                 ("converged", C.c_int), ("cap_hit", C.c_int), ("time_ms", dbl * 8),
-                ("first_cols", C.c_int * H2_MAX_LEVELS)]
+                ("first_cols", C.c_int * H2_MAX_LEVELS), ("global_rank", C.c_int),
+                ("global_applies", i64), ("update_applies", i64)]
 
 
 class H2NSOpts(C.Structure):
     _fields_ = [("eps", dbl), ("max_iter", C.c_int), ("x0", C.c_int), ("dynamic", C.c_int),
                 ("eps_build", dbl), ("norm_rel", dbl), ("resid_rel", dbl), ("rank_cap", C.c_int),
                 ("oversample", C.c_int), ("adaptive", C.c_int), ("max_rounds", C.c_int),
-                ("seed", u64), ("prec", C.c_int)]
+                ("seed", u64), ("prec", C.c_int), ("order", C.c_int), ("unroll", C.c_int),
+                ("x0_matrix", vp)]
 
 
 class H2NSStats(C.Structure):
@@ -63,6 +65,7 @@ SIGNATURES = {
     "h2_tree_pairs": (C.c_int, [vp, C.c_int, vp]),
     "h2_opts_default": (None, [P(H2Opts)]),
     "h2_build": (C.c_int, [vp, vp, vp, P(H2Opts), vp, P(vp), P(H2BuildStats)]),
+    "h2_build_lowrank": (C.c_int, [vp, vp, vp, P(H2Opts), C.c_int, vp, P(vp), P(H2BuildStats)]),
     "h2_gemv": (C.c_int, [vp, C.c_int, dbl, vp, C.c_int, dbl, vp, C.c_int, vp]),
     "h2_gemv_f32": (C.c_int, [vp, C.c_int, flt, vp, C.c_int, flt, vp, C.c_int, vp]),
     "h2_norm2": (C.c_int, [vp, C.c_int, dbl, u64, vp, P(dbl)]),
@@ -102,6 +105,8 @@ SIGNATURES = {
     "h2_sampler_advdiff_create": (C.c_int, [C.c_int, dbl, C.c_int, vp, C.c_int, vp, C.c_int, dbl,
                                             vp, vp, vp, C.c_int, P(vp)]),
     "h2_sampler_advdiff_apply": (C.c_int, [vp, C.c_int, C.c_int, vp, C.c_int, vp, C.c_int, vp]),
+    "h2_sampler_minsurf_create": (C.c_int, [C.c_int, vp, P(vp)]),
+    "h2_sampler_minsurf_apply": (C.c_int, [vp, C.c_int, C.c_int, vp, C.c_int, vp, C.c_int, vp]),
     "h2_sampler_h2_apply": (C.c_int, [vp, C.c_int, C.c_int, vp, C.c_int, vp, C.c_int, vp]),
     "h2_sampler_destroy": (None, [vp]),
     # test hooks (include/h2_testing.h)

@@ -23,6 +23,7 @@ SOURCES = [
     "gemv.hip",
     "linalg.hip",
     "build.hip",
+    "lowrank.hip",
     "ns.hip",
     "samplers.hip",
     "mlp.hip",

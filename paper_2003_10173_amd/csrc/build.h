@@ -40,6 +40,9 @@ struct BuildParams {
   // numerical-rank cut of the range basis, relative to the largest singular
   // value of the samples: above the sampler's rounding level
   double rank_cut = 1e-13;
+  // basis rank cap of the recompression (0: rank_cap, which also sets the
+  // sampling width rank_cap + oversample)
+  int dest_cap = 0;
 };
 
 // Peeling on the weak partition + recompression into the strong H2 of `t`.

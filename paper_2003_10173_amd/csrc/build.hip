@@ -1032,7 +1032,8 @@ void build_h2_multi(std::vector<BuildJob>& jobs, Ctx& c) {
           const double* sv = sgh.data() + u.goff[i];
           H2_CHECK(std::isfinite(sv[0]), H2_ENUMERIC, "non-finite singular values in recompression");
           while (k < r && sv[k] > s.tau) ++k;
-          if (k > s.prm->rank_cap) { k = s.prm->rank_cap; s.cap_hit = true; }
+          const int cap = s.prm->dest_cap > 0 ? s.prm->dest_cap : s.prm->rank_cap;
+          if (k > cap) { k = cap; s.cap_hit = true; }
         }
         s.rank[cid(lev, i)] = k;
       }

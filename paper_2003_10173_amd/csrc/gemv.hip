@@ -721,15 +721,20 @@ static void leaf_nt(const h2_matrix* A, int nv, V alpha, const V* xt, int ldx, V
         A->st.D.as<M>(), nv, yh, xt, ldx, alpha, beta, yt, ldy);
 }
 
+// coef: 2 * (sum of ranks) * nv coefficient words (x-hat, y-hat); nullptr:
+// the matrix's own workspace, grown on demand
 template <class M, class V>
 static void gemv_tree_run(const h2_matrix* A, int nv, V alpha, const V* xt, int ldx, V beta,
-                          V* yt, int ldy, hipStream_t s, int nt) {
+                          V* yt, int ldy, hipStream_t s, int nt, V* coef = nullptr) {
   const h2_tree* t = A->tree;
   const int L = t->L;
   const int64_t ktot = A->kpre.back();
-  const size_t need = (size_t)2 * ktot * nv * sizeof(V);
-  A->ws.reserve(std::max<size_t>(need, 256));
-  V* xh = A->ws.as<V>();
+  if (!coef) {
+    const size_t need = (size_t)2 * ktot * nv * sizeof(V);
+    A->ws.reserve(std::max<size_t>(need, 256));
+    coef = A->ws.as<V>();
+  }
+  V* xh = coef;
   V* yh = xh + ktot * nv;
   const M* U = A->st.U.as<M>();
   const M* E = A->st.E.as<M>();

