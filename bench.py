@@ -38,6 +38,11 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--hgemv-nv", type=int, default=34)
     ap.add_argument("--hgemv-reps", type=int, default=50)
+    ap.add_argument("--appendix-grid", type=int, default=64,
+                    help="grid side of the minimal-surface inversion form (the paper's is 128)")
+    ap.add_argument("--forms-only", action="store_true",
+                    help="measure only the named forms (comma list in --only) and print them")
+    ap.add_argument("--only", default="appendix_a,global_lowrank")
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the mixed-precision form and the 256x256 precision ladder")
     return ap.parse_args()
@@ -223,6 +228,94 @@ def blas_threads():
     return int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
 
 
+# the paper's inversion times for its minimal-surface example (n = 16,384,
+# one P100; Appendix A): context for the appendix form, not a target
+PAPER_APPENDIX_A_S = {"static": 178.0, "dynamic": 51.0, "hyperpower8": 20.0,
+                      "hyperpower16": 20.0, "warm_static": 32.0, "warm_dynamic": 14.0,
+                      "warm_unrolled": 4.0}
+
+
+def appendix_a_form(h2, torch, si, grid):
+    """Newton-Schulz inversion of the minimal-surface Hessian (Appendix A
+    example) on a grid x grid mesh, leaf 64, construction threshold 1e-6,
+    stop at ||I - A X||_2 <= 1e-4.  First optimisation step from X0 = I/nu:
+    static threshold, dynamic threshold (from 1e-2), hyperpower orders 8 and
+    16 (dynamic).  Second step (the next surface): from I/nu, warm-started
+    from the first step's inverse, and warm-started with the warm run's
+    Newton-Schulz steps unrolled into one construction."""
+    out = {"workload": "minsurf2d %dx%d (N=%d), leaf 64, eps_k 1e-6, stop 1e-4, X0 = I/nu"
+                       % (grid, grid, grid * grid),
+           "paper_p100_s_at_128x128": PAPER_APPENDIX_A_S}
+    cfgs = [si.config_minsurf2d(grid, 0), si.config_minsurf2d(grid, 1)]
+    tree = h2.Tree(cfgs[0]["points"], cfgs[0]["leaf"], cfgs[0]["eta"])
+    mats = []
+    for c in cfgs:
+        A, st = h2.build(tree, h2.MinSurfSampler(c),
+                         h2.opts(rank_cap=c["cap"], oversample=c["p"], tol=c["tol"], adaptive=1,
+                                 max_rounds=16, seed=c["seed"]))
+        mats.append(A)
+    c = cfgs[0]
+
+    def run(name, A, **kw):
+        o = h2.ns_opts(eps=c["eps"], max_iter=60, eps_build=c["eps_build"], rank_cap=0,
+                       oversample=c["p"], adaptive=1, max_rounds=16, seed=c["seed"], **kw)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        X, info = h2.newton_schulz(A, o)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        out[name] = {"s": round(dt, 3), "iterations": info["iterations"],
+                     "applies": int(sum(info["applies"])), "residual": info["resid"][-1],
+                     "ok": info["status"] == 0}
+        print("appendix A %s: %.2f s, %d iterations, %d samples, E %.2e" % (
+            name, dt, info["iterations"], out[name]["applies"], info["resid"][-1]),
+            file=sys.stderr, flush=True)
+        return X, info
+    run("static", mats[0], x0=0, dynamic=0)
+    Xprev, info = run("dynamic", mats[0], x0=0, dynamic=1)
+    run("hyperpower8", mats[0], x0=0, dynamic=1, order=8)
+    run("hyperpower16", mats[0], x0=0, dynamic=1, order=16)
+    run("step2_identity_dynamic", mats[1], x0=0, dynamic=1)
+    run("warm_static", mats[1], x0=2, x0_matrix=Xprev, dynamic=0)
+    _, iw = run("warm_dynamic", mats[1], x0=2, x0_matrix=Xprev, dynamic=1)
+    # every Newton-Schulz step the warm run took, unrolled into one
+    # construction (at most 6: 2^6 - 1 powers of the residual per sample)
+    u = min(max(iw["iterations"], 1), 6)
+    run("warm_unrolled", mats[1], x0=2, x0_matrix=Xprev, dynamic=1, unroll=u)
+    out["unroll"] = u
+    return out
+
+
+def lowrank_form(h2, torch, si, rank=500):
+    """Hessian products of the plain construction against the global
+    low-rank pre-pass + construction of H - B B^T (Sec. 3.3) on the
+    misfit-only advection-diffusion Gauss-Newton Hessian (128 x 128, 4000
+    observations: a data misfit of limited global rank), both at 1e-4."""
+    cfg = si.config_advdiff2d(128)
+    S = h2.AdvDiffSampler(cfg)
+    tree = h2.Tree(cfg["points"], cfg["leaf"], cfg["eta"])
+    o = h2.opts(rank_cap=cfg["cap"], oversample=cfg["p"], tol=1e-4, adaptive=1, max_rounds=16,
+                seed=6)
+    out = {"workload": "advdiff2d 128x128 (N=16384) misfit-only, cap 32, eps 1e-4, global rank %d"
+                       % rank}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, st = h2.build(tree, S, o)
+    torch.cuda.synchronize()
+    out["plain"] = {"s": round(time.perf_counter() - t0, 3), "applies": st["applies"],
+                    "converged": st["converged"]}
+    t0 = time.perf_counter()
+    _, sl = h2.build_lowrank(tree, S, rank, o)
+    torch.cuda.synchronize()
+    out["lowrank"] = {"s": round(time.perf_counter() - t0, 3), "applies": sl["applies"],
+                      "global_applies": sl["global_applies"], "global_rank": sl["global_rank"],
+                      "residual_applies": sl["applies"] - sl["global_applies"],
+                      "converged": sl["converged"]}
+    print("global low rank: plain %d products, low rank + residual %d (%d global)" % (
+        st["applies"], sl["applies"], sl["global_applies"]), file=sys.stderr, flush=True)
+    return out
+
+
 def cpu_baseline(cfg):
     """The oracle, as it stands, timed on the same workload: the full FP64
     build of the diffusion Hessian and the full Newton-Schulz run from I / nu
@@ -269,6 +362,14 @@ def main():
 
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
+    if args.forms_only:
+        fns = {"appendix_a": lambda: appendix_a_form(h2, torch, si, args.appendix_grid),
+               "global_lowrank": lambda: lowrank_form(h2, torch, si),
+               "precision_ladder": lambda: precision_ladder(h2, torch, si, stream),
+               "learned": lambda: learned_form(h2, torch, si),
+               "batched": lambda: batched_form(h2, torch, si)}
+        print(json.dumps({k: fns[k]() for k in args.only.split(",")}), flush=True)
+        return
     cfg = si.config_diffusion2d(args.grid)
     tree = h2.Tree(cfg["points"], cfg["leaf"], cfg["eta"])
     sampler = h2.DiffusionSampler(cfg)
@@ -362,7 +463,9 @@ def main():
                  "mixed_residual": nm["resid"][-1], "mixed_valid": mixed_ok,
                  "precision_ladder": precision_ladder(h2, torch, si, stream),
                  "learned": learned_form(h2, torch, si),
-                 "batched": batched_form(h2, torch, si)}
+                 "batched": batched_form(h2, torch, si),
+                 "appendix_a": appendix_a_form(h2, torch, si, args.appendix_grid),
+                 "global_lowrank": lowrank_form(h2, torch, si)}
 
     cpu = None
     if not args.no_cpu_baseline:

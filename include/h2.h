@@ -64,6 +64,21 @@ typedef enum { H2_FP64 = 0, H2_FP32 = 1, H2_BF16 = 2 } h2_precision;
 typedef int (*h2_sampler_fn)(void* ctx, int n, int ncols, const double* omega, int ld_omega,
                              double* y, int ld_y, hipStream_t stream);
 
+/*
+ * Batched sampler: one call applies the operators of many problems at once
+ * (the batched construction below, for callers whose Hessian-vector products
+ * of many problems run best as one multi-right-hand-side launch).  Packed
+ * layout: problem i owns rows row_off[i] .. row_off[i+1] - 1 (its user
+ * ordering) of the column-major device blocks omega and y, leading dimension
+ * ld = row_off[nprob]; every problem has the same ncols columns.  active[i] = 0:
+ * problem i needs no product in this call (its rows of omega are zero and its
+ * rows of y are not read).  row_off and active are host arrays, valid during
+ * the call.  Only enqueue work on `stream`; nonzero return = H2_ECALLBACK.
+ */
+typedef int (*h2_batched_sampler_fn)(void* ctx, int nprob, const int64_t* row_off,
+                                     const int32_t* active, int ncols, const double* omega,
+                                     int ld, double* y, hipStream_t stream);
+
 /* ------------------------------------------------------------------ tree */
 /*
  * Cluster tree by KD binary space partition (Sec. 4.2: KD-tree ordering with
@@ -141,6 +156,23 @@ typedef struct {
 h2_status h2_build_batched(int nprob, const h2_tree* const* trees, const h2_sampler_fn* samplers,
                            void* const* ctxs, const h2_opts* opts, hipStream_t stream,
                            h2_matrix** out, h2_build_stats* stats);
+
+/*
+ * The same batched construction with ONE batched sampler for all problems:
+ * each phase of each level (the rounds of sampling, the projections, the
+ * leaf diagonal, every power-method step of the norm estimates) calls
+ * `sampler` once for every problem that needs products in it, over the
+ * packed layout (row_off[i] = n_0 + ... + n_{i-1}), with the largest column
+ * count requested in that phase (a problem that needs fewer columns gets
+ * zero columns beyond its own, whose products are discarded).  So the number
+ * of calls grows with levels and rounds, not with problems.  Results equal
+ * h2_build_batched with per-problem samplers of the same operators.
+ * sampler_calls (nullable) receives the number of calls made.
+ */
+h2_status h2_build_batched_packed(int nprob, const h2_tree* const* trees,
+                                  h2_batched_sampler_fn sampler, void* ctx, const h2_opts* opts,
+                                  hipStream_t stream, h2_matrix** out, h2_build_stats* stats,
+                                  int64_t* sampler_calls);
 
 /* default options: cap 32, p 10, tol 1e-4, adaptive, 16 rounds, seed 1 */
 void h2_opts_default(h2_opts* opts);
@@ -348,6 +380,21 @@ int h2_sampler_advdiff_apply(void* ctx, int n, int ncols, const double* omega, i
 h2_status h2_sampler_minsurf_create(int g, const double* heights_host, void** ctx);
 int h2_sampler_minsurf_apply(void* ctx, int n, int ncols, const double* omega, int ld_omega,
                              double* y, int ld_y, hipStream_t stream);
+/*
+ * kernel_batched: h2_batched_sampler_fn for nprob kernel matrices (the
+ * kernel sampler's H_ij = exp(-|p_i - p_j| / ell_b) + shift_b delta_ij per
+ * problem b) in one launch over the packed layout.  points_host: the
+ * problems' points stacked in row_off order (row_off[nprob] x dim); ell and
+ * shift: one per problem.  Each problem's product equals
+ * h2_sampler_kernel_apply's for the same points.
+ */
+h2_status h2_sampler_kernel_batched_create(int nprob, const int64_t* row_off_host,
+                                           const double* points_host, int dim,
+                                           const double* ell_host, const double* shift_host,
+                                           void** ctx);
+int h2_sampler_kernel_batched_apply(void* ctx, int nprob, const int64_t* row_off,
+                                    const int32_t* active, int ncols, const double* omega, int ld,
+                                    double* y, hipStream_t stream);
 /* sampler that applies an H2 matrix (h2_gemv) -- ctx is the h2_matrix pointer */
 int h2_sampler_h2_apply(void* ctx, int n, int ncols, const double* omega, int ld_omega,
                         double* y, int ld_y, hipStream_t stream);

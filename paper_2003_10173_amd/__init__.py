@@ -11,8 +11,8 @@ import ctypes as C
 import numpy as np
 
 from . import _lib
-from ._lib import (H2_BF16, H2_FP32, H2_FP64, H2BuildStats, H2Error, H2NSOpts, H2NSStats,
-                   H2Opts, SAMPLER_FN, check, lib)
+from ._lib import (BATCHED_SAMPLER_FN, H2_BF16, H2_FP32, H2_FP64, H2BuildStats, H2Error,
+                   H2NSOpts, H2NSStats, H2Opts, SAMPLER_FN, check, lib)
 
 __all__ = ["Tree", "H2Matrix", "build", "newton_schulz", "residual_norm", "KernelSampler",
            "DiffusionSampler", "AdvDiffSampler", "MinSurfSampler", "H2Sampler", "PythonSampler", "opts",
@@ -403,6 +403,57 @@ def build_batched(trees, samplers, opts_list, stream=None):
     check(rc, "h2_build_batched", (0, 1))
     mats = [H2Matrix(C.c_void_p(out[i]), trees[i]) for i in range(n)]
     return mats, [stats_dict(st[i], trees[i].L) for i in range(n)], rc
+
+
+class KernelBatchSampler:
+    """One h2_batched_sampler_fn for several kernel matrices (packed layout;
+    one HIP launch per call).  calls counts the calls."""
+
+    def __init__(self, point_sets, ells, shifts):
+        pts = [np.asarray(p, dtype=np.float64).reshape(len(p), -1) for p in point_sets]
+        dim = pts[0].shape[1]
+        self.row_off = np.concatenate([[0], np.cumsum([len(p) for p in pts])]).astype(np.int64)
+        P = np.ascontiguousarray(np.concatenate(pts))
+        e = np.ascontiguousarray(ells, dtype=np.float64)
+        sh = np.ascontiguousarray(shifts, dtype=np.float64)
+        h = C.c_void_p()
+        check(lib().h2_sampler_kernel_batched_create(len(pts), self.row_off.ctypes.data,
+                                                     P.ctypes.data, dim, e.ctypes.data,
+                                                     sh.ctypes.data, C.byref(h)), "kernel_batched")
+        self.ctx = h
+        self.calls = 0
+        native = C.cast(lib()._dll.h2_sampler_kernel_batched_apply, C.c_void_p).value
+        self._native = BATCHED_SAMPLER_FN(native)
+
+        def counted(ctx, nprob, off, act, ncols, om, ld, y, stream):
+            self.calls += 1
+            return self._native(ctx, nprob, off, act, ncols, om, ld, y, stream)
+        self.fn = BATCHED_SAMPLER_FN(counted)
+
+    def __del__(self):
+        if getattr(self, "ctx", None) is not None and self.ctx.value:
+            try:
+                lib().h2_sampler_destroy(self.ctx)
+            except Exception:  # noqa: BLE001 - interpreter shutdown
+                pass
+            self.ctx = None
+
+
+def build_batched_packed(trees, sampler, opts_list, stream=None):
+    """Batched construction with one batched sampler over the packed layout
+    (h2_build_batched_packed); returns ([H2Matrix], [stats dict], status,
+    sampler calls)."""
+    n = len(trees)
+    th = (C.c_void_p * n)(*[t.handle.value for t in trees])
+    oa = (H2Opts * n)(*opts_list)
+    out = (C.c_void_p * n)()
+    st = (H2BuildStats * n)()
+    calls = C.c_int64()
+    rc = lib().h2_build_batched_packed(n, th, C.cast(sampler.fn, C.c_void_p), sampler.ctx, oa,
+                                       _stream(stream), out, st, C.byref(calls))
+    check(rc, "h2_build_batched_packed", (0, 1))
+    mats = [H2Matrix(C.c_void_p(out[i]), trees[i]) for i in range(n)]
+    return mats, [stats_dict(st[i], trees[i].L) for i in range(n)], rc, calls.value
 
 
 def newton_schulz_batched(As, opts_list, stream=None):

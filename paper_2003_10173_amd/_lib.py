@@ -20,6 +20,7 @@ i32, i64, u32, u64, dbl, flt = C.c_int32, C.c_int64, C.c_uint32, C.c_uint64, C.c
 P = C.POINTER
 
 SAMPLER_FN = C.CFUNCTYPE(C.c_int, vp, C.c_int, C.c_int, vp, C.c_int, vp, C.c_int, vp)
+BATCHED_SAMPLER_FN = C.CFUNCTYPE(C.c_int, vp, C.c_int, vp, vp, C.c_int, vp, C.c_int, vp, vp)
 
 
 class H2Opts(C.Structure):
@@ -65,6 +66,10 @@ SIGNATURES = {
     "h2_tree_pairs": (C.c_int, [vp, C.c_int, vp]),
     "h2_opts_default": (None, [P(H2Opts)]),
     "h2_build": (C.c_int, [vp, vp, vp, P(H2Opts), vp, P(vp), P(H2BuildStats)]),
+    "h2_build_batched_packed": (C.c_int, [C.c_int, vp, vp, vp, vp, vp, vp, vp, P(i64)]),
+    "h2_sampler_kernel_batched_create": (C.c_int, [C.c_int, vp, vp, C.c_int, vp, vp, P(vp)]),
+    "h2_sampler_kernel_batched_apply": (C.c_int, [vp, C.c_int, vp, vp, C.c_int, vp, C.c_int, vp,
+                                                  vp]),
     "h2_build_lowrank": (C.c_int, [vp, vp, vp, P(H2Opts), C.c_int, vp, P(vp), P(H2BuildStats)]),
     "h2_gemv": (C.c_int, [vp, C.c_int, dbl, vp, C.c_int, dbl, vp, C.c_int, vp]),
     "h2_gemv_f32": (C.c_int, [vp, C.c_int, flt, vp, C.c_int, flt, vp, C.c_int, vp]),

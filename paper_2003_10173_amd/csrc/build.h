@@ -8,12 +8,54 @@
 
 namespace h2 {
 
+struct PackedBatch;
+
 // Operator to be compressed, applied to tree-ordered column-major blocks
 // (ld = n): Y = A Omega.  `applies` counts columns.
 struct Sampler {
   int64_t applies = 0;
   virtual ~Sampler() = default;
   virtual void apply(Ctx& c, int ncols, const double* om, double* y) = 0;
+  // samplers of one problem of a batch served by one batched user callback
+  virtual PackedBatch* batch() { return nullptr; }
+  virtual int batch_index() const { return -1; }
+};
+
+// One product request of a phase: y (n x ncols) = S (om), tree order, ld n.
+struct ApplyReq {
+  Sampler* S;
+  int ncols;
+  const double* om;
+  double* y;
+};
+// Serves every request; requests whose samplers belong to one PackedBatch
+// are served by one call of its batched user callback.
+void apply_requests(Ctx& c, const std::vector<ApplyReq>& reqs);
+
+// The problems of h2_build_batched_packed: one h2_batched_sampler_fn over the
+// packed layout (problem i owns user-ordered rows off[i] .. off[i+1] - 1),
+// all requested problems sharing the column count of the call.
+struct PackedBatch {
+  h2_batched_sampler_fn fn = nullptr;
+  void* ctx = nullptr;
+  std::vector<const h2_tree*> trees;
+  std::vector<int64_t> off;
+  DevBuf om, y;
+  int64_t calls = 0;
+  // (problem index, ncols, om, y) per request, tree order
+  void apply(Ctx& c, const std::vector<std::tuple<int, int, const double*, double*>>& reqs);
+};
+
+struct PackedSampler : Sampler {
+  PackedBatch* B;
+  int idx;
+  PackedSampler(PackedBatch* b, int i) : B(b), idx(i) {}
+  void apply(Ctx& c, int ncols, const double* om, double* y) override {
+    B->apply(c, {{idx, ncols, om, y}});
+    applies += ncols;
+  }
+  PackedBatch* batch() override { return B; }
+  int batch_index() const override { return idx; }
 };
 
 // Wraps a user h2_sampler_fn (user ordering) with the tree permutation.

@@ -59,6 +59,59 @@ void UserSampler::apply(Ctx& c, int ncols, const double* om, double* y) {
   applies += ncols;
 }
 
+void PackedBatch::apply(Ctx& c,
+                        const std::vector<std::tuple<int, int, const double*, double*>>& reqs) {
+  if (reqs.empty()) return;
+  const int nprob = (int)trees.size();
+  const int64_t ld = off[nprob];
+  int ncols = 0;
+  for (const auto& r : reqs) ncols = std::max(ncols, std::get<1>(r));
+  if (ncols <= 0) return;
+  H2_CHECK(ld <= INT32_MAX, H2_EINVAL, "packed rows exceed the int range");
+  om.reserve((size_t)ld * ncols * sizeof(double));
+  y.reserve((size_t)ld * ncols * sizeof(double));
+  double* O = om.as<double>();
+  double* Y = y.as<double>();
+  // inactive problems and columns beyond a problem's own count stay zero
+  zero_block(c, O, (int)ld, ncols, (int)ld);
+  std::vector<int32_t> active(nprob, 0);
+  for (const auto& r : reqs) {
+    const int i = std::get<0>(r), nc = std::get<1>(r);
+    active[i] = 1;
+    if (nc > 0) scatter_rows(trees[i], nc, 1.0, std::get<2>(r), trees[i]->n, 0.0, O + off[i], (int)ld, c.s);
+  }
+  const int rc = fn(ctx, nprob, off.data(), active.data(), ncols, O, (int)ld, Y, c.s);
+  if (rc != 0) throw Error(H2_ECALLBACK, "batched sampler callback returned " + std::to_string(rc));
+  H2_HIP(hipGetLastError());
+  ++calls;
+  for (const auto& r : reqs) {
+    const int i = std::get<0>(r), nc = std::get<1>(r);
+    if (nc > 0) gather_rows(trees[i], nc, Y + off[i], (int)ld, std::get<3>(r), trees[i]->n, c.s);
+  }
+}
+
+void apply_requests(Ctx& c, const std::vector<ApplyReq>& reqs) {
+  std::vector<PackedBatch*> order;
+  std::map<PackedBatch*, std::vector<std::tuple<int, int, const double*, double*>>> groups;
+  std::map<PackedBatch*, std::vector<Sampler*>> members;
+  for (const auto& r : reqs) {
+    if (r.ncols <= 0) continue;
+    PackedBatch* b = r.S->batch();
+    if (!b) {
+      r.S->apply(c, r.ncols, r.om, r.y);
+      continue;
+    }
+    if (!groups.count(b)) order.push_back(b);
+    groups[b].push_back({r.S->batch_index(), r.ncols, r.om, r.y});
+    members[b].push_back(r.S);
+  }
+  for (PackedBatch* b : order) {
+    b->apply(c, groups[b]);
+    auto& g = groups[b];
+    for (size_t k = 0; k < g.size(); ++k) members[b][k]->applies += std::get<1>(g[k]);
+  }
+}
+
 // ------------------------------------------------------------------ kernels
 // Omega of level l: Gaussian on the rows of even (left) clusters, zero elsewhere
 __global__ void k_fill_left(uint64_t key, int n, int ncols, int nclus,
@@ -441,17 +494,40 @@ void build_h2_multi(std::vector<BuildJob>& jobs, Ctx& c) {
   }
   if (jobs.size() == 1) reset_factors();
 
-  // ---- norm estimates (power method through each sampler)
+  // ---- norm estimates (power method through each sampler, in lock step;
+  // the products of one step go out as one request list)
   double t0 = now_ms();
+  {
+    std::vector<PowerJob> pj;
+    std::vector<JobState*> pw;
+    for (auto& s : js) {
+      if (s.prm->norm > 0) continue;
+      PowerJob J;
+      J.n = s.n;
+      J.seed = s.prm->seed;
+      J.iteration = s.prm->iteration;
+      J.rel = s.prm->norm_rel;
+      J.min_it = 3;
+      J.max_it = s.prm->norm_rel >= 1e-2 ? 30 : 500;
+      pj.push_back(J);
+      pw.push_back(&s);
+    }
+    for (auto* s : pw) s->applies1 = s->S->applies;
+    if (!pj.empty()) {
+      PowerBatchOp op = [&](const std::vector<int>& ids, const std::vector<const double*>& v,
+                            const std::vector<double*>& w, hipStream_t) {
+        std::vector<ApplyReq> reqs;
+        for (size_t k = 0; k < ids.size(); ++k) reqs.push_back({pw[ids[k]]->S, 1, v[k], w[k]});
+        apply_requests(c, reqs);
+      };
+      power_norm_multi(pj, c.s, false, &op);
+    }
+    for (size_t k = 0; k < pw.size(); ++k) pw[k]->nu = pj[k].result;
+  }
   for (auto& s : js) {
     const BuildParams& prm = *s.prm;
-    const int64_t a0 = s.S->applies;
-    double nu = prm.norm;
-    if (!(nu > 0)) {
-      nu = power_norm_device(s.n, [&](const double* v, double* w) { s.S->apply(c, 1, v, w); },
-                             prm.seed, prm.iteration, prm.norm_rel, 3,
-                             prm.norm_rel >= 1e-2 ? 30 : 500, c.s, nullptr);
-    }
+    const int64_t a0 = prm.norm > 0 ? s.S->applies : s.applies1;
+    double nu = prm.norm > 0 ? prm.norm : s.nu;
     H2_CHECK(std::isfinite(nu), H2_ENUMERIC, "norm estimate is not finite");
     s.nu = nu;
     s.J->stats.norm = nu;
@@ -479,6 +555,7 @@ void build_h2_multi(std::vector<BuildJob>& jobs, Ctx& c) {
         if (s->sampling) sj.push_back(s);
       if (sj.empty()) break;
       std::vector<SubReq> sub;
+      std::vector<ApplyReq> reqs;
       for (JobState* s : sj) {
         const int bw = s->r == 0 ? s->b0 : s->b;  // the first round may be wider (learned)
         const uint64_t key = stream_key(s->prm->seed, PHASE_RANGE, l, s->r, s->prm->iteration);
@@ -486,9 +563,10 @@ void build_h2_multi(std::vector<BuildJob>& jobs, Ctx& c) {
         k_fill_left<<<(unsigned)((tot + 255) / 256), 256, 0, c.s>>>(
             key, s->n, bw, 1 << l, s->t->d_cstart.as<int32_t>() + cid(l, 0), s->om);
         H2_LAUNCH_CHECK();
-        s->S->apply(c, bw, s->om, s->y);
+        reqs.push_back({s->S, bw, s->om, s->y});
         sub.push_back({s, l, s->om, s->y, bw});
       }
+      apply_requests(c, reqs);
       subtract_multi(c, sub);
       {
         std::vector<std::pair<const double*, int64_t>> fin;
@@ -690,6 +768,7 @@ void build_h2_multi(std::vector<BuildJob>& jobs, Ctx& c) {
     t0 = now_ms();
     {
       std::vector<SubReq> sub;
+      std::vector<ApplyReq> reqs;
       for (JobState* s : lj) {
         Level& LV = s->lv[l];
         LV.k.assign(s->np, 0);
@@ -706,9 +785,10 @@ void build_h2_multi(std::vector<BuildJob>& jobs, Ctx& c) {
           if (s->k0[p] > 0)
             put.push_back({s->Q0[p], s->pr[p].m2, s->om + s->pr[p].a2, n, s->pr[p].m2, s->k0[p], 1.0, 0.0, 0});
         copy_batched(c, put);
-        s->S->apply(c, s->K0, s->om, s->y);
+        reqs.push_back({s->S, s->K0, s->om, s->y});
         sub.push_back({s, l, s->om, s->y, s->K0});
       }
+      apply_requests(c, reqs);
       subtract_multi(c, sub);
     }
     // truncated SVD of B0 (m1 x k0) by one-sided Jacobi:
@@ -857,6 +937,7 @@ void build_h2_multi(std::vector<BuildJob>& jobs, Ctx& c) {
     std::vector<SubReq> sub;
     std::vector<std::pair<const double*, int64_t>> fin;
     std::vector<SymDesc> sd;
+    std::vector<ApplyReq> reqs;
     for (auto& s : js) {
       const int n = s.n, L = s.L, nleaf = 1 << L, mmax = s.t->max_leaf;
       s.om_buf.reserve((size_t)n * mmax * sizeof(double));
@@ -867,7 +948,7 @@ void build_h2_multi(std::vector<BuildJob>& jobs, Ctx& c) {
       k_fill_diag<<<(unsigned)((tot + 255) / 256), 256, 0, c.s>>>(
           n, mmax, nleaf, s.t->d_cstart.as<int32_t>() + cid(L, 0), s.om);
       H2_LAUNCH_CHECK();
-      s.S->apply(c, mmax, s.om, s.y);
+      reqs.push_back({s.S, mmax, s.om, s.y});
       sub.push_back({&s, L + 1, s.om, s.y, mmax});
       fin.push_back({s.y, tot});
       s.Ddiag.resize(nleaf);
@@ -877,6 +958,7 @@ void build_h2_multi(std::vector<BuildJob>& jobs, Ctx& c) {
         sd.push_back({s.y + s.t->cstart[cid(L, i)], n, m, s.Ddiag[i].as<double>()});
       }
     }
+    apply_requests(c, reqs);
     subtract_multi(c, sub);
     check_finite_multi(c, fin, "diagonal samples");
     auto* dsd = (SymDesc*)c.stage.put(sd.data(), sd.size() * sizeof(SymDesc), c.s);
@@ -1256,6 +1338,46 @@ h2_status h2_build_batched(int nprob, const h2_tree* const* trees, const h2_samp
       conv = conv && jobs[i].converged;
       out[i] = jobs[i].out.release();
     }
+  });
+  if (st == H2_OK && !conv) return H2_ENOTCONVERGED;
+  return st;
+}
+
+h2_status h2_build_batched_packed(int nprob, const h2_tree* const* trees,
+                                  h2_batched_sampler_fn sampler, void* ctx, const h2_opts* opts,
+                                  hipStream_t stream, h2_matrix** out, h2_build_stats* stats,
+                                  int64_t* sampler_calls) {
+  bool conv = true;
+  h2_status st = guarded_status([&] {
+    H2_CHECK(nprob >= 0 && (nprob == 0 || (trees && sampler && opts && out)), H2_EINVAL,
+             "null argument");
+    PackedBatch B;
+    B.fn = sampler;
+    B.ctx = ctx;
+    B.off.assign(nprob + 1, 0);
+    for (int i = 0; i < nprob; ++i) {
+      H2_CHECK(trees[i], H2_EINVAL, "null tree");
+      out[i] = nullptr;
+      B.trees.push_back(trees[i]);
+      B.off[i + 1] = B.off[i] + trees[i]->n;
+    }
+    std::vector<std::unique_ptr<PackedSampler>> S;
+    std::vector<BuildJob> jobs(nprob);
+    for (int i = 0; i < nprob; ++i) {
+      S.push_back(std::make_unique<PackedSampler>(&B, i));
+      jobs[i].t = trees[i];
+      jobs[i].S = S.back().get();
+      jobs[i].prm = params_from(&opts[i]);
+    }
+    Ctx c;
+    c.s = stream;
+    build_h2_multi(jobs, c);
+    for (int i = 0; i < nprob; ++i) {
+      if (stats) stats[i] = jobs[i].stats;
+      conv = conv && jobs[i].converged;
+      out[i] = jobs[i].out.release();
+    }
+    if (sampler_calls) *sampler_calls = B.calls;
   });
   if (st == H2_OK && !conv) return H2_ENOTCONVERGED;
   return st;

@@ -798,11 +798,15 @@ __global__ __launch_bounds__(512) void k_svd_block(const SVDDesc* __restrict__ d
           if (tid == 0) atomicOr(&fl[mi], 1);
         }
         // both blocks have been through round rq: publish after all writes.
-        // Every wave releases its own stores of A and V at device scope
-        // before the barrier, so that the counter written after it (by one
-        // thread, itself ordered by a device-scope fence) is only seen once
-        // all of them are visible to the other workgroups
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        // The barrier alone does not wait for other waves' global stores
+        // (its workgroup-scope fence needs no such wait within one compute
+        // unit), so every wave first waits until its own stores of A and V
+        // have completed at the L2; thread 0's device-scope release then
+        // writes the L2 back, covering every wave's stores, before the
+        // counter is published (a workgroup that acquires the counter at
+        // device scope reads them from memory)
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
         if (tid == 0) {
           __threadfence();

@@ -35,15 +35,15 @@ struct KernelCtx {
 constexpr int KT = 64;   // tile of rows / columns of H
 constexpr int KC = 16;   // vectors per block
 
-__global__ __launch_bounds__(256) void k_kernel_apply(int n, int ncols, const double* __restrict__ P,
-                                                      double inv_ell, double shift,
-                                                      const double* __restrict__ om, int ldo,
-                                                      double* __restrict__ y, int ldy) {
+// rows r0 .. r0 + KT - 1 and columns c0 .. c0 + KC - 1 of y = H om for one
+// kernel matrix (points P, n x 3): the whole of one workgroup's work
+__device__ __forceinline__ void kernel_tile(int r0, int c0, int n, int ncols,
+                                            const double* __restrict__ P, double inv_ell,
+                                            double shift, const double* __restrict__ om, int ldo,
+                                            double* __restrict__ y, int ldy) {
   __shared__ double Ht[KT][KT + 1];
   __shared__ double Ot[KT][KC];
   __shared__ double pr[KT][3];
-  const int r0 = blockIdx.x * KT;
-  const int c0 = blockIdx.y * KC;
   const int nc = min(KC, ncols - c0);
   const int tid = threadIdx.x;
   for (int e = tid; e < KT * 3; e += 256) {
@@ -83,6 +83,36 @@ __global__ __launch_bounds__(256) void k_kernel_apply(int n, int ncols, const do
   if (r0 + ri < n)
     for (int q = 0; q < 4; ++q)
       if (cj + q < nc) y[(size_t)(c0 + cj + q) * ldy + r0 + ri] = acc[q];
+}
+
+__global__ __launch_bounds__(256) void k_kernel_apply(int n, int ncols, const double* __restrict__ P,
+                                                      double inv_ell, double shift,
+                                                      const double* __restrict__ om, int ldo,
+                                                      double* __restrict__ y, int ldy) {
+  kernel_tile(blockIdx.x * KT, blockIdx.y * KC, n, ncols, P, inv_ell, shift, om, ldo, y, ldy);
+}
+
+// Several kernel matrices in one launch over the packed layout (problem i
+// owns rows off[i] .. off[i+1] - 1 of om, y and P): one workgroup per row
+// tile of one problem; each tile is computed exactly as k_kernel_apply does
+struct KernelBatchCtx {
+  int kind = 5;
+  int nprob;
+  std::vector<int64_t> off;
+  DevBuf pts, tiles, prm;  // points (rows x 3); tile -> (problem, r0); (1/ell, shift) per problem
+  DevBuf tiles_off;        // row offsets (nprob + 1) on the device
+  int ntiles;
+};
+
+__global__ __launch_bounds__(256) void k_kernel_apply_batched(
+    const int32_t* __restrict__ tiles, const int64_t* __restrict__ off,
+    const double* __restrict__ prm, const double* __restrict__ P, int ncols,
+    const double* __restrict__ om, int ld, double* __restrict__ y) {
+  const int i = tiles[2 * blockIdx.x], r0 = tiles[2 * blockIdx.x + 1];
+  const int64_t o = off[i];
+  const int n = (int)(off[i + 1] - o);
+  kernel_tile(r0, blockIdx.y * KC, n, ncols, P + (size_t)o * 3, prm[2 * i], prm[2 * i + 1],
+              om + o, ld, y + o, ld);
 }
 
 // ------------------------------------------------------------------ explicit stepping
@@ -447,6 +477,61 @@ int h2_sampler_kernel_apply(void* ctx, int n, int ncols, const double* omega, in
   return hipGetLastError() == hipSuccess ? 0 : 2;
 }
 
+h2_status h2_sampler_kernel_batched_create(int nprob, const int64_t* row_off_host,
+                                           const double* points_host, int dim,
+                                           const double* ell_host, const double* shift_host,
+                                           void** ctx) {
+  return guarded_status([&] {
+    H2_CHECK(nprob >= 1 && row_off_host && points_host && ell_host && shift_host && ctx &&
+             dim >= 1 && dim <= 3, H2_EINVAL, "bad batched kernel sampler arguments");
+    H2_CHECK(row_off_host[0] == 0, H2_EINVAL, "row offsets must start at 0");
+    auto k = std::make_unique<KernelBatchCtx>();
+    k->nprob = nprob;
+    k->off.assign(row_off_host, row_off_host + nprob + 1);
+    const int64_t rows = k->off[nprob];
+    std::vector<double> p((size_t)rows * 3, 0.0), prm(2 * (size_t)nprob);
+    std::vector<int32_t> tiles;
+    for (int i = 0; i < nprob; ++i) {
+      H2_CHECK(k->off[i + 1] > k->off[i] && ell_host[i] > 0, H2_EINVAL,
+               "empty problem or non-positive length scale");
+      prm[2 * i] = 1.0 / ell_host[i];
+      prm[2 * i + 1] = shift_host[i];
+      for (int64_t r0 = 0; r0 < k->off[i + 1] - k->off[i]; r0 += KT) {
+        tiles.push_back(i);
+        tiles.push_back((int32_t)r0);
+      }
+    }
+    for (int64_t r = 0; r < rows; ++r)
+      for (int d = 0; d < dim; ++d) p[(size_t)r * 3 + d] = points_host[(size_t)r * dim + d];
+    k->ntiles = (int)(tiles.size() / 2);
+    upload(k->pts, p);
+    upload(k->tiles, tiles);
+    upload(k->prm, prm);
+    std::vector<int64_t> off(k->off);
+    DevBuf doff;
+    upload(doff, off);
+    k->tiles_off = std::move(doff);
+    *ctx = k.release();
+  });
+}
+
+int h2_sampler_kernel_batched_apply(void* ctx, int nprob, const int64_t* row_off,
+                                    const int32_t* active, int ncols, const double* omega, int ld,
+                                    double* y, hipStream_t stream) {
+  auto* k = (KernelBatchCtx*)ctx;
+  if (!k || k->kind != 5 || nprob != k->nprob || !row_off || ncols < 0) return 1;
+  for (int i = 0; i <= nprob; ++i)
+    if (row_off[i] != k->off[i]) return 1;
+  if (ld < k->off[nprob]) return 1;
+  (void)active;  // inactive problems have zero rows in omega: their products are zero
+  if (ncols == 0) return 0;
+  dim3 grid((unsigned)k->ntiles, (unsigned)((ncols + KC - 1) / KC));
+  k_kernel_apply_batched<<<grid, 256, 0, stream>>>(k->tiles.as<int32_t>(),
+                                                   k->tiles_off.as<int64_t>(), k->prm.as<double>(),
+                                                   k->pts.as<double>(), ncols, omega, ld, y);
+  return hipGetLastError() == hipSuccess ? 0 : 2;
+}
+
 h2_status h2_sampler_diffusion_create(int g, double kappa, double dt, int steps,
                                       const int32_t* obs_steps, int n_obs_steps,
                                       const int32_t* obs_index, int obs_count, double sigma,
@@ -611,6 +696,7 @@ void h2_sampler_destroy(void* ctx) {
   const int kind = *(int*)ctx;
   if (kind == 1) delete (KernelCtx*)ctx;
   else if (kind == 4) delete (MinSurfCtx*)ctx;
+  else if (kind == 5) delete (KernelBatchCtx*)ctx;
   else delete (StepCtx*)ctx;
 }
 

