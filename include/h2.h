@@ -222,6 +222,24 @@ h2_status h2_gemv(const h2_matrix* A, int nv, double alpha, const double* x, int
 h2_status h2_gemv_f32(const h2_matrix* A, int nv, float alpha, const float* x, int ldx,
                       float beta, float* y, int ldy, hipStream_t stream);
 
+/*
+ * h2_gemv for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same product (FP64 matrix and vectors, device pointers, user order,
+ * column-major) without any allocation.  Its workspace -- tree-order x and y
+ * and the basis coefficients, 2 (n + sum of cluster ranks) nv FP64 words --
+ * is a fixed array of 2^23 words (64 MiB) that the library holds on every
+ * GPU it runs on until the process ends.  A product needing more returns
+ * H2_EINVAL before any work is enqueued.  Every call on one GPU uses that
+ * GPU's array: calls that overlap in time on one GPU (other streams, other
+ * host threads) race and must be serialised by the caller.  The matrix-core
+ * tile width is the one an earlier h2_gemv autotuned on the tree, else a
+ * fixed rule (no timing runs); every width sums the same products in the
+ * same order, so results equal h2_gemv's.
+ */
+h2_status h2_gemv_noalloc(const h2_matrix* A, int nv, double alpha, const double* x, int ldx,
+                          double beta, double* y, int ldy, hipStream_t stream);
+
 /* ||A||_2 by the power method stopped at relative change rel (Sec. 3.2) */
 h2_status h2_norm2(const h2_matrix* A, int max_iter, double rel, uint64_t seed,
                    hipStream_t stream, double* out);

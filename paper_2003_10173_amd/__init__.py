@@ -166,6 +166,20 @@ class H2Matrix:
             raise TypeError("vectors must be float64 or float32")
         return y
 
+    def gemv_noalloc(self, x, y, alpha=1.0, beta=0.0, stream=None):
+        """y = alpha A x + beta y (FP64) through h2_gemv_noalloc: no device
+        allocation; the library's fixed per-GPU workspace is used instead."""
+        import torch
+        xv = x.reshape(-1, self.tree.n)
+        yv = y.reshape(-1, self.tree.n)
+        assert xv.is_contiguous() and yv.is_contiguous() and xv.is_cuda and yv.is_cuda
+        assert xv.dtype == torch.float64 and yv.dtype == torch.float64
+        assert xv.shape == yv.shape
+        check(lib().h2_gemv_noalloc(self.handle, xv.shape[0], float(alpha), _ptr(xv),
+                                    self.tree.n, float(beta), _ptr(yv), self.tree.n,
+                                    _stream(stream)), "h2_gemv_noalloc")
+        return y
+
     def norm2(self, max_iter=30, rel=1e-2, seed=1, stream=None):
         out = C.c_double()
         check(lib().h2_norm2(self.handle, max_iter, rel, seed, _stream(stream), C.byref(out)),

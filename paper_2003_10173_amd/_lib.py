@@ -73,6 +73,7 @@ SIGNATURES = {
     "h2_build_lowrank": (C.c_int, [vp, vp, vp, P(H2Opts), C.c_int, vp, P(vp), P(H2BuildStats)]),
     "h2_gemv": (C.c_int, [vp, C.c_int, dbl, vp, C.c_int, dbl, vp, C.c_int, vp]),
     "h2_gemv_f32": (C.c_int, [vp, C.c_int, flt, vp, C.c_int, flt, vp, C.c_int, vp]),
+    "h2_gemv_noalloc": (C.c_int, [vp, C.c_int, dbl, vp, C.c_int, dbl, vp, C.c_int, vp]),
     "h2_norm2": (C.c_int, [vp, C.c_int, dbl, u64, vp, P(dbl)]),
     "h2_matrix_convert": (C.c_int, [vp, C.c_int, P(vp)]),
     "h2_matrix_scale": (C.c_int, [vp, dbl, P(vp)]),

@@ -13,6 +13,8 @@
 #include <algorithm>
 #include <cstdio>
 #include <cstring>
+#include <functional>
+#include <mutex>
 #include <type_traits>
 
 #include "internal.h"
@@ -978,3 +980,75 @@ void matrix_identity(h2_matrix* A, const h2_tree* t, double alpha, hipStream_t s
 }
 
 }  // namespace h2
+
+// ------------------------------------------------------------------ no-allocation product
+namespace h2 {
+
+// Workspace of h2_gemv_noalloc: tree-order x and y (n * nv words each) and
+// the coefficient vectors (2 * sum of ranks * nv words).  One copy per GPU,
+// held until the process ends; every call on a GPU shares it.
+constexpr int64_t NOALLOC_WORDS = (int64_t)1 << 23;   // 64 MiB of FP64
+static __device__ __align__(256) double scratch[NOALLOC_WORDS];
+
+namespace {
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[NOALLOC_MAX_DEVICES] = {};
+
+// device address of this GPU's copy of `scratch`, looked up once per device
+// with that device current (the array's name is only a host-side stand-in)
+double* scratch_ptr() {
+  int dev = 0;
+  H2_HIP(hipGetDevice(&dev));
+  H2_CHECK(dev >= 0 && dev < NOALLOC_MAX_DEVICES, H2_EINVAL, "device index out of range");
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    H2_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    H2_CHECK(p != nullptr, H2_EDEVICE, "no device address for the workspace array");
+    g_scratch_ptr[dev] = static_cast<double*>(p);
+  }
+  return g_scratch_ptr[dev];
+}
+}  // namespace
+
+h2_status guarded_status(const std::function<void()>& f);
+
+int64_t gemv_noalloc_words(const h2_matrix* A, int nv) {
+  return 2 * ((int64_t)A->tree->n + A->kpre.back()) * (int64_t)nv;
+}
+
+}  // namespace h2
+
+using namespace h2;
+
+extern "C" h2_status h2_gemv_noalloc(const h2_matrix* A, int nv, double alpha, const double* x,
+                                     int ldx, double beta, double* y, int ldy, hipStream_t s) {
+  return guarded_status([&] {
+    H2_CHECK(A, H2_EINVAL, "null matrix");
+    const h2_tree* t = A->tree;
+    const int n = t->n;
+    H2_CHECK(nv >= 0 && ldx >= n && ldy >= n, H2_EINVAL, "bad vector count or leading dimension");
+    if (nv == 0) return;
+    H2_CHECK(x && y, H2_EINVAL, "null vector");
+    H2_CHECK(A->st.prec == H2_FP64, H2_EINVAL, "h2_gemv_noalloc needs FP64 storage");
+    H2_CHECK(t->device_ready, H2_EINVAL, "tree has no device index arrays");
+    H2_CHECK(gemv_noalloc_words(A, nv) <= NOALLOC_WORDS, H2_EINVAL,
+             "h2_gemv_noalloc: 2 (n + sum of ranks) nv exceeds the 2^23-word workspace");
+    double* ws = scratch_ptr();
+    double* xt = ws;
+    double* yt = xt + (size_t)n * nv;
+    double* coef = yt + (size_t)n * nv;
+    // tile width: the autotuned one if this tree has it, else the rule the
+    // tuner falls back to (no timing run: it would allocate)
+    int nt = 0;
+    if (A->kmax <= LEAF_MAX) {
+      const std::tuple<int, int, int> key{std::min((nv + 15) / 16, 4), 8, 8};
+      auto it = t->tuned_nt.find(key);
+      nt = it != t->tuned_nt.end() ? it->second : (nv <= 16 ? 1 : (nv <= 32 ? 2 : 4));
+    }
+    gather_rows(t, nv, x, ldx, xt, n, s);
+    gemv_tree_run<double, double>(A, nv, 1.0, xt, n, 0.0, yt, n, s, nt, coef);
+    scatter_rows(t, nv, alpha, yt, n, beta, y, ldy, s);
+  });
+}
