@@ -286,18 +286,19 @@ def appendix_a_form(h2, torch, si, grid):
     return out
 
 
-def lowrank_form(h2, torch, si, rank=500):
+def lowrank_form(h2, torch, si, rank=220):
     """Hessian products of the plain construction against the global
-    low-rank pre-pass + construction of H - B B^T (Sec. 3.3) on the
-    misfit-only advection-diffusion Gauss-Newton Hessian (128 x 128, 4000
-    observations: a data misfit of limited global rank), both at 1e-4."""
-    cfg = si.config_advdiff2d(128)
+    low-rank pre-pass + construction of H - B B^T (Sec. 3.3) on a misfit-only
+    advection-diffusion Gauss-Newton Hessian with limited data (128 x 128
+    grid, 20 observation points at 10 times: a misfit of global rank at most
+    200), both at 1e-4."""
+    cfg = si.config_advdiff2d(128, nobs=20)
     S = h2.AdvDiffSampler(cfg)
     tree = h2.Tree(cfg["points"], cfg["leaf"], cfg["eta"])
     o = h2.opts(rank_cap=cfg["cap"], oversample=cfg["p"], tol=1e-4, adaptive=1, max_rounds=16,
                 seed=6)
-    out = {"workload": "advdiff2d 128x128 (N=16384) misfit-only, cap 32, eps 1e-4, global rank %d"
-                       % rank}
+    out = {"workload": "advdiff2d 128x128 (N=16384) misfit-only, 20 points x 10 times, cap 32, "
+                       "eps 1e-4, global rank %d" % rank}
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     _, st = h2.build(tree, S, o)
@@ -457,7 +458,27 @@ def main():
         print("mixed step: %.1f ms, %d iterations (%d FP32), residual %.2e" % (
             1e3 * t_mixed, nm["iterations"], nm["low_iterations"], nm["resid"][-1]),
             file=sys.stderr, flush=True)
+        # the same step with hyperpower iterations of order 4 and 8 (Appendix A.2):
+        # fewer, wider constructions -- the work moves from compression to sampling
+        hyper = {}
+        for order in (4, 8):
+            hopts = h2.ns_opts(eps=1e-4, max_iter=60, x0=0, dynamic=1, rank_cap=0,
+                               oversample=cfg["p"], adaptive=1, max_rounds=16, seed=cfg["seed"],
+                               order=order)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            Ah, bh = h2.build(tree, sampler, bopts)
+            Xh, nh = h2.newton_schulz(Ah, hopts)
+            torch.cuda.synchronize()
+            th = time.perf_counter() - t1
+            hyper["order%d" % order] = {
+                "s": round(th, 4), "iterations": nh["iterations"], "residual": nh["resid"][-1],
+                "samples": int(sum(nh["applies"])),
+                "valid": bool(bh["converged"]) and nh["status"] == 0 and nh["resid"][-1] <= 1e-4}
+            print("hyperpower order %d step: %.1f ms, %d iterations, residual %.2e" % (
+                order, 1e3 * th, nh["iterations"], nh["resid"][-1]), file=sys.stderr, flush=True)
         forms = {"plain_fp64_s": round(ms_per_step / 1e3, 4),
+                 "hyperpower": hyper,
                  "mixed_fp32_s": round(t_mixed, 4),
                  "mixed_iterations": nm["iterations"], "mixed_fp32_iterations": nm["low_iterations"],
                  "mixed_residual": nm["resid"][-1], "mixed_valid": mixed_ok,

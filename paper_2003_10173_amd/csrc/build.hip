@@ -636,9 +636,10 @@ void build_h2_multi(std::vector<BuildJob>& jobs, Ctx& c) {
       // append this round's samples; extend Qe with the projected block: QR,
       // one more projection, QR again
       {
-        std::vector<CopyDesc> app, put;
-        std::vector<QRDesc> q1, q2, t1, t2;
-        std::vector<GemmDesc> g1, g2;
+        std::vector<CopyDesc> app, put, lost;
+        std::vector<uint64_t> lost_keys;
+        std::vector<QRDesc> q1, q2, q3, t1, t2, t3;
+        std::vector<GemmDesc> g1, g2, g3, g4;
         for (JobState* s : sj) {
           const int bw = s->r == 0 ? s->b0 : s->b;
           for (int p : s->act) {
@@ -658,8 +659,21 @@ void build_h2_multi(std::vector<BuildJob>& jobs, Ctx& c) {
               double* Wq = c.scratch.get((size_t)q * kn);
               g1.push_back({s->Qe + s->qoff[p], Qn, Wq, q, kn, m2, m2, m2, q, 1, 0, 1.0, 0.0});
               g2.push_back({s->Qe + s->qoff[p], Wq, Qn, m2, kn, q, m2, q, m2, 0, 0, -1.0, 1.0});
-              (tall ? t2 : q2).push_back({Qn, m2, m2, kn, Qn2, m2, nullptr, 0});
-              put.push_back({Qn2, m2, s->Qe + s->qoff[p] + (size_t)q * m2, m2, m2, take, 1.0, 0.0, 0});
+              double* R2 = c.scratch.get((size_t)kn * kn);
+              (tall ? t2 : q2).push_back({Qn, m2, m2, kn, Qn2, m2, R2, kn});
+              // a round that adds fewer directions than columns (exactly
+              // low-rank blocks) leaves columns of Qn2 dependent on Qe or on
+              // each other (small R2_jj): they become Gaussian, are projected
+              // once more and the block is orthonormalised again
+              lost.push_back({Qn2, m2, R2, kn, m2, kn, 1.0, 0.0, 0});
+              lost_keys.push_back(stream_key(s->prm->seed, PHASE_LOST, (uint32_t)l,
+                                             (uint32_t)(s->r * 4096 + p), s->prm->iteration));
+              double* Wr = c.scratch.get((size_t)q * kn);
+              g3.push_back({s->Qe + s->qoff[p], Qn2, Wr, q, kn, m2, m2, m2, q, 1, 0, 1.0, 0.0});
+              g4.push_back({s->Qe + s->qoff[p], Wr, Qn2, m2, kn, q, m2, q, m2, 0, 0, -1.0, 1.0});
+              double* Qn3 = c.scratch.get((size_t)m2 * kn);
+              (tall ? t3 : q3).push_back({Qn2, m2, m2, kn, Qn3, m2, nullptr, 0});
+              put.push_back({Qn3, m2, s->Qe + s->qoff[p] + (size_t)q * m2, m2, m2, take, 1.0, 0.0, 0});
             } else {
               put.push_back({Qn, m2, s->Qe + s->qoff[p], m2, m2, take, 1.0, 0.0, 0});
             }
@@ -673,6 +687,11 @@ void build_h2_multi(std::vector<BuildJob>& jobs, Ctx& c) {
         gemm_batched(c, g2);
         qr_auto(c, q2);
         qr_tall_batched(c, t2);
+        replace_lost_columns(c, lost, lost_keys);
+        gemm_batched(c, g3);
+        gemm_batched(c, g4);
+        qr_auto(c, q3);
+        qr_tall_batched(c, t3);
         copy_batched(c, put);
       }
       H2_HIP(hipStreamSynchronize(c.s));

@@ -171,6 +171,6 @@ void scatter_rows_f32(const h2_tree* t, int nv, float alpha, const float* yt, in
 
 // counter-based Gaussian fill (splitmix64 + Box-Muller); see h2_build
 uint64_t stream_key(uint64_t seed, uint32_t phase, uint32_t level, uint32_t round, uint32_t iter);
-enum { PHASE_NORM = 1, PHASE_RANGE = 2, PHASE_PROBE = 5, PHASE_RESID = 6 };
+enum { PHASE_NORM = 1, PHASE_RANGE = 2, PHASE_PROBE = 5, PHASE_RESID = 6, PHASE_LOST = 8 };
 
 }  // namespace h2

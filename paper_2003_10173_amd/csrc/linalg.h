@@ -126,6 +126,13 @@ void qr_blocked(Ctx& c, const std::vector<CholQRDesc>& d);
 // overwritten; Q (thin, optional) and R (optional, min(m,n) x n upper) as in
 // QRDesc.
 void qr_auto(Ctx& c, const std::vector<QRDesc>& d);
+// columns of the blocks (CopyDesc src/lds/rows/cols, written in place) that
+// lie in a span projected out become Gaussian vectors of about unit norm,
+// keyed by keys[i], row and column: with dst == nullptr the columns of norm
+// below 1/2; with dst/ldd the R of a QR whose Q the block is, the columns
+// whose |R_jj| is below 1/2
+void replace_lost_columns(Ctx& c, const std::vector<CopyDesc>& blocks,
+                          const std::vector<uint64_t>& keys);
 // out[i] = max_j || X_i[:, j] || for blocks X_i (rows_i x cols_i, ld_i)
 void colnorm_max_batched(Ctx& c, const std::vector<CopyDesc>& blocks, double* out);
 // zero a column-major block

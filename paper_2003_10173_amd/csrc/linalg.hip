@@ -1421,7 +1421,11 @@ void qr_blocked(Ctx& c, const std::vector<CholQRDesc>& ds) {
   // block Gram-Schmidt with reorthogonalisation of the normalised block
   // (BCGS2):  S1 = Q^T P, P -= Q S1, P = Q1 R1;  S2 = Q^T Q1, Q1 -= Q S2,
   // Q1 = Q2 R2;  R_jj = R2 R1,  R[0:j0, j] = S1 + S2 R1.  Stable when the
-  // panel is numerically dependent on the previous ones.
+  // panel is numerically dependent on the previous ones, except for the
+  // columns of Q1 that lie in the span of Q (a rank-deficient panel's QR
+  // completes its basis with such columns, whose rows of R1 are at rounding
+  // level): those are replaced by Gaussian directions and projected once more
+  // (S3 = Q^T Q1, Q1 -= Q S3, S2 += S3) before Q1 = Q2 R2.
   constexpr int W = 64;
   int maxp = 0;
   std::vector<CholQRDesc> v;
@@ -1434,9 +1438,10 @@ void qr_blocked(Ctx& c, const std::vector<CholQRDesc>& ds) {
   if (v.empty()) return;
   for (auto& d : v) zero_block(c, d.R, d.n, d.n, d.ldr);
   for (int j = 0; j < maxp; ++j) {
-    std::vector<GemmDesc> p1, p2, p3, p4, rr, rs;
+    std::vector<GemmDesc> p1, p2, p3, p4, p6, p7, rr, rs;
     std::vector<QRDesc> tq1, tq2;
-    std::vector<CopyDesc> back;
+    std::vector<CopyDesc> back, lost, adds;
+    std::vector<uint64_t> lost_keys;
     for (auto& d : v) {
       const int j0 = j * W;
       if (j0 >= d.n) continue;
@@ -1453,12 +1458,21 @@ void qr_blocked(Ctx& c, const std::vector<CholQRDesc>& ds) {
       double* R1 = c.scratch.get((size_t)w * w);
       double* R2 = c.scratch.get((size_t)w * w);
       double* S2 = c.scratch.get((size_t)j0 * w);
+      double* S3 = c.scratch.get((size_t)j0 * w);
       double* Q2 = c.scratch.get((size_t)d.m * w);
       p1.push_back({d.P, Pj, Rj, j0, w, d.m, d.ld, d.ld, d.ldr, 1, 0, 1.0, 0.0});      // S1
       p2.push_back({d.P, Rj, Pj, d.m, w, j0, d.ld, d.ldr, d.ld, 0, 0, -1.0, 1.0});     // P -= Q S1
       tq1.push_back({Pj, d.ld, d.m, w, Q1, d.m, R1, w});                                // P = Q1 R1
       p3.push_back({d.P, Q1, S2, j0, w, d.m, d.ld, d.m, j0, 1, 0, 1.0, 0.0});          // S2
       p4.push_back({d.P, S2, Q1, d.m, w, j0, d.ld, j0, d.m, 0, 0, -1.0, 1.0});         // Q1 -= Q S2
+      // columns of Q1 that the projection removed (dependent panel) become
+      // Gaussian; one more projection, whose coefficients join S2
+      lost.push_back({Q1, d.m, nullptr, 0, d.m, w, 1.0, 0.0, 0});
+      lost_keys.push_back(stream_key(0x9e3779b97f4a7c15ull ^ (uint64_t)d.m, PHASE_LOST, (uint32_t)j,
+                                     (uint32_t)d.n, (uint32_t)v.size()));
+      p6.push_back({d.P, Q1, S3, j0, w, d.m, d.ld, d.m, j0, 1, 0, 1.0, 0.0});          // S3 = Q^T Q1
+      p7.push_back({d.P, S3, Q1, d.m, w, j0, d.ld, j0, d.m, 0, 0, -1.0, 1.0});         // Q1 -= Q S3
+      adds.push_back({S3, j0, S2, j0, j0, w, 1.0, 1.0, 0});                             // S2 += S3
       tq2.push_back({Q1, d.m, d.m, w, Q2, d.m, R2, w});                                 // Q1 = Q2 R2
       rr.push_back({R2, R1, Rjj, w, w, w, w, w, d.ldr, 0, 0, 1.0, 0.0});                // R_jj
       rs.push_back({S2, R1, Rj, j0, w, w, j0, w, d.ldr, 0, 0, 1.0, 1.0});               // S1 += S2 R1
@@ -1469,6 +1483,10 @@ void qr_blocked(Ctx& c, const std::vector<CholQRDesc>& ds) {
     qr_tall_batched(c, tq1);
     gemm_batched(c, p3);
     gemm_batched(c, p4);
+    replace_lost_columns(c, lost, lost_keys);
+    gemm_batched(c, p6);
+    gemm_batched(c, p7);
+    copy_batched(c, adds);
     qr_tall_batched(c, tq2);
     gemm_batched(c, rr);
     gemm_batched(c, rs);
@@ -1592,6 +1610,51 @@ __global__ __launch_bounds__(256) void k_colnorm_max(const CopyDesc* __restrict_
   if (lane == 0) red[wave] = best;
   __syncthreads();
   if (threadIdx.x == 0) out[blockIdx.x] = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+}
+
+// Columns of a projected orthonormal block that lie (numerically) in the
+// span that was projected out carry no direction of their own: for a
+// rank-deficient block, Householder QR completes the basis with unit vectors
+// of the block's own coordinates, which may lie in that span.  A column is
+// lost when its norm fell below 1/2 (dst == nullptr: the block itself is
+// tested), or, for the Q factor of a QR of the projected block, when the
+// diagonal entry of its R (dst, ldd) is below 1/2 in magnitude (dependent on
+// the span or on the block's earlier columns).  A lost column is replaced by
+// a Gaussian vector of about unit norm (keyed by the block's key, row and
+// column), so that the projection and QR that follow give a direction
+// orthogonal to the span.  One wave per column.
+__global__ __launch_bounds__(256) void k_replace_lost_columns(const CopyDesc* __restrict__ ds,
+                                                              const uint64_t* __restrict__ keys) {
+  const CopyDesc d = ds[blockIdx.x];
+  const uint64_t key = keys[blockIdx.x];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  double* X = const_cast<double*>(d.src);
+  const double sc = 1.0 / sqrt((double)max(d.rows, 1));
+  for (int j = wave + 4 * blockIdx.y; j < d.cols; j += 4 * gridDim.y) {
+    double* col = X + (size_t)j * d.lds;
+    bool lost;
+    if (d.dst) {
+      lost = fabs(d.dst[(size_t)j * d.ldd + j]) < 0.5;
+    } else {
+      double s = 0;
+      for (int i = lane; i < d.rows; i += 64) s += col[i] * col[i];
+      lost = wave_sum(s) < 0.25;
+    }
+    if (lost)
+      for (int i = lane; i < d.rows; i += 64) col[i] = sc * gauss_entry(key, (uint64_t)i, (uint64_t)j);
+  }
+}
+
+void replace_lost_columns(Ctx& c, const std::vector<CopyDesc>& blocks,
+                          const std::vector<uint64_t>& keys) {
+  if (blocks.empty()) return;
+  H2_CHECK(blocks.size() == keys.size(), H2_EINVAL, "one key per block");
+  auto* dd = (CopyDesc*)c.stage.put(blocks.data(), blocks.size() * sizeof(CopyDesc), c.s);
+  auto* dk = (uint64_t*)c.stage.put(keys.data(), keys.size() * sizeof(uint64_t), c.s);
+  int mc = 1;
+  for (auto& b : blocks) mc = std::max(mc, b.cols);
+  k_replace_lost_columns<<<dim3((unsigned)blocks.size(), (unsigned)((mc + 3) / 4)), 256, 0, c.s>>>(dd, dk);
+  H2_LAUNCH_CHECK();
 }
 
 void colnorm_max_batched(Ctx& c, const std::vector<CopyDesc>& blocks, double* out) {
