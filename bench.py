@@ -364,6 +364,13 @@ def main():
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
     if args.forms_only:
+        # reference copy of known size (512 MiB each way) for scaling byte counters
+        src = torch.ones(1 << 26, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            h2.stream_copy(src, dst)
+        torch.cuda.synchronize()
+        del src, dst
         fns = {"appendix_a": lambda: appendix_a_form(h2, torch, si, args.appendix_grid),
                "global_lowrank": lambda: lowrank_form(h2, torch, si),
                "precision_ladder": lambda: precision_ladder(h2, torch, si, stream),

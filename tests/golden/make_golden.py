@@ -22,7 +22,9 @@ difference between the oracle's sampled values and those of a second oracle
 run whose samples carry a seeded relative perturbation of 1e-14 (the
 rounding level of FP64 sums over a few thousand terms, as in the samplers'
 time stepping and the subtraction of peeled levels): the spread two correct
-FP64 implementations may show.
+FP64 implementations may show.  For the Newton-Schulz record the second run
+inverts the perturbed build with perturbed samples in every iterate, and its
+history of E_k and products per iteration is stored beside the first run's.
 
 Usage: python tests/golden/make_golden.py [diffusion64] [batch8]
 """
@@ -109,13 +111,15 @@ def diffusion64():
                   adaptive=True, max_rounds=16, seed=cfg["seed"])
     print("diffusion64 Newton-Schulz %.1f s, %d iterations" % (time.time() - t0,
                                                               info["iterations"]), flush=True)
-    # the same Newton-Schulz with every iterate's samples perturbed
+    # the whole pipeline perturbed: Newton-Schulz of the perturbed build Hp
+    # with every iterate's samples perturbed too (the spread of the inverse
+    # includes what the build's spread does to it)
     import oracle.ns as ns_mod
     plain_build = ns_mod.build
     ns_mod.build = lambda f, *a, **k: plain_build(perturbed(f), *a, **k)
     try:
-        Xp, _ = ons(H, 1e-4, 60, T.leaf_size, cfg["p"], x0="identity", dynamic=True,
-                    adaptive=True, max_rounds=16, seed=cfg["seed"])
+        Xp, infop = ons(Hp, 1e-4, 60, T.leaf_size, cfg["p"], x0="identity", dynamic=True,
+                        adaptive=True, max_rounds=16, seed=cfg["seed"])
     finally:
         ns_mod.build = plain_build
     out = {"_about": "oracle build + Newton-Schulz of the 64 x 64 diffusion Gauss-Newton "
@@ -125,7 +129,10 @@ def diffusion64():
            "ns": {"eps": 1e-4, "max_iter": 60, "rank_cap": T.leaf_size, "oversample": cfg["p"],
                   "x0": "identity", "dynamic": True, "seed": cfg["seed"], "nu": info["nu"],
                   "iterations": info["iterations"], "E": info["E"],
-                  "applies": [int(a) for a in info["applies"]], "status": info["status"]},
+                  "applies": [int(a) for a in info["applies"]], "status": info["status"],
+                  "eps_k": [float(e) for e in info["eps_k"]],
+                  "E_perturbed": infop["E"],
+                  "applies_perturbed": [int(a) for a in infop["applies"]]},
            "ns_products": dict(sampled_products(X, T.n), spread=spread(X, Xp, T.n))}
     with open(os.path.join(HERE, "diffusion64_build_ns.json"), "w") as f:
         json.dump(out, f)
