@@ -416,92 +416,171 @@ __global__ __launch_bounds__(256) void k_leaf_mfma(
     }
 }
 
-// Leaf stage with the matrix-core operands read straight from memory into
-// registers (no LDS, no barriers: every wave streams its own 16 rows of each
-// block, so many waves stay resident and hide the latency of each other's
-// loads).  Same products, accumulated in the same order, as the tile kernel.
+// FP64 block-row product, pipelined through LDS: out (rows x nvc) = sum over
+// sources q of A_q B_q (A_q row-major rows x K_q, B_q column-major K_q x nvc
+// with leading dimension ldb_q; rows, K_q <= 64).  Each source is read with
+// coalesced loads (A a row at a time, B a column at a time) into registers
+// two sources ahead of its use, stored into one of two LDS tile buffers, and
+// multiplied on the matrix cores from there after a single barrier, so that
+// the loads of the next sources overlap the products of this one.  The
+// products and their order are those of blockrow_mfma (sources ascending, k
+// ascending in steps of 4); wave w owns rows 16 w..16 w + 15 and NT 16-column
+// tiles.
+// (global-memory pointers: their loads then count only against the vector
+// memory counter, not against the LDS one that the tile accesses wait on)
+typedef const double __attribute__((address_space(1)))* gdptr;
+struct PipeSrc {
+  gdptr A;
+  gdptr B;
+  int K, ldb;
+};
+constexpr int PIPE_MAXSRC = 64, PIPE_ALD = 64 + 2;
+template <int NT> struct PipeTiles {
+  static constexpr int NC = 16 * NT, BLD = NC + 2;
+  static constexpr int RA = 16, RB = NC / 4;    // registers per thread
+  double A[2][64 * PIPE_ALD];
+  double B[2][64 * BLD];
+};
+
+template <int NT>
+__device__ inline void blockrow_lds_pipe(int rows, int nsrc, const PipeSrc* __restrict__ ps,
+                                         int nvc, mf_d4 (&acc)[NT], PipeTiles<NT>& tl) {
+  using P = PipeTiles<NT>;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  // A: wave w, register j holds row 4 j + w, k = lane (one row of the
+  // row-major block per load instruction); B: register j holds column
+  // 4 j + w, k = lane (one column per instruction).  Loads use clamped,
+  // in-range addresses; the positions outside the block are zeroed when
+  // stored to LDS.
+  auto gload = [&](int q, double (&ra)[P::RA], double (&rb)[P::RB]) {
+    // (straight-line loads: an empty block, K = 0, carries pointers to valid
+    // memory and reads its first element, stored as zeros)
+    const PipeSrc S = ps[q < nsrc ? q : nsrc - 1];
+    const int kl = (S.K > 0 ? S.K : 1) - 1;
+    const int kc = lane < kl ? lane : kl;
+#pragma unroll
+    for (int j = 0; j < P::RA; ++j) {
+      const int r = 4 * j + wave;
+      ra[j] = S.A[(size_t)(r < rows ? r : rows - 1) * S.K + kc];
+    }
+#pragma unroll
+    for (int j = 0; j < P::RB; ++j) {
+      const int cb = 4 * j + wave;
+      rb[j] = S.B[(size_t)(cb < nvc ? cb : nvc - 1) * S.ldb + kc];
+    }
+  };
+  auto lstore = [&](int q, int buf, const double (&ra)[P::RA], const double (&rb)[P::RB]) {
+    const int K = q < nsrc ? ps[q].K : 0;
+#pragma unroll
+    for (int j = 0; j < P::RA; ++j) {
+      const int r = 4 * j + wave;
+      tl.A[buf][r * PIPE_ALD + lane] = (r < rows && lane < K) ? ra[j] : 0.0;
+    }
+#pragma unroll
+    for (int j = 0; j < P::RB; ++j) {
+      const int cb = 4 * j + wave;
+      tl.B[buf][lane * P::BLD + cb] = (cb < nvc && lane < K) ? rb[j] : 0.0;
+    }
+  };
+  // the k-steps in groups of four (16 k-values), each group's LDS reads
+  // issued together ahead of its products; groups wholly past K are skipped
+  auto mma = [&](int q, int buf) {
+    if (16 * wave >= rows || q >= nsrc) return;
+    const int KP = (ps[q].K + 3) & ~3;
+    const double* As = tl.A[buf] + (16 * wave + (lane & 15)) * PIPE_ALD + (lane >> 4);
+    const double* Bs = tl.B[buf] + (lane >> 4) * P::BLD + (lane & 15);
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+      if (16 * g >= KP) break;
+      double a[4], b[NT][4];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        a[t] = As[16 * g + 4 * t];
+#pragma unroll
+        for (int ct = 0; ct < NT; ++ct) b[ct][t] = Bs[(16 * g + 4 * t) * P::BLD + 16 * ct];
+      }
+      // (a group always takes its four k-steps: the tiles are zero past K,
+      // so the extra steps add exact zeros)
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int ct = 0; ct < NT; ++ct)
+          acc[ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[t], b[ct][t], acc[ct], 0, 0, 0);
+    }
+  };
+  if (nsrc <= 0) return;
+  double ra0[P::RA], rb0[P::RB], ra1[P::RA], rb1[P::RB];
+  gload(0, ra0, rb0);
+  gload(1, ra1, rb1);
+  // (sources in pairs, an odd count padded by an empty one: the loop body
+  // has no exit in the middle, so each register set keeps its place)
+  for (int q = 0; q < nsrc; q += 2) {
+    // buffer 0 was last read by the products of source q - 2, which every
+    // wave finished before the barrier of source q - 1
+    lstore(q, 0, ra0, rb0);
+    __syncthreads();
+    gload(q + 2, ra0, rb0);
+    mma(q, 0);
+    lstore(q + 1, 1, ra1, rb1);
+    __syncthreads();
+    gload(q + 3, ra1, rb1);
+    mma(q + 1, 1);
+  }
+}
+
+// leaf stage in FP64: y_t = alpha (U_t y^_t + sum_near D_ts x_s) + beta y_t
 template <class M, class V, int NT>
-__global__ __launch_bounds__(256) void k_leaf_direct(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))) void k_leaf_direct(
     int L, const int32_t* __restrict__ cstart, const int32_t* __restrict__ csize,
     const int32_t* __restrict__ rank, const int64_t* __restrict__ kpre,
     const int64_t* __restrict__ Uoff, const M* __restrict__ U,
     const int32_t* __restrict__ near_ptr, const int32_t* __restrict__ near_col,
     const int64_t* __restrict__ Doff, const M* __restrict__ D, int nv, const V* __restrict__ yh,
     const V* __restrict__ x, int ldx, V alpha, V beta, V* __restrict__ y, int ldy) {
-  using T = MfmaTraits<M>;
-  using Acc = typename T::Acc;
-  constexpr bool BF = T::KS == 16;
+  static_assert(std::is_same<M, double>::value && std::is_same<V, double>::value, "FP64 only");
   constexpr int NC = 16 * NT;
+  __shared__ PipeSrc ps[PIPE_MAXSRC];
+  __shared__ PipeTiles<NT> tl;
   const int i = blockIdx.x;
   const int leaf_base = (1 << L) - 1;
   const int c = leaf_base + i;
   const int r0 = cstart[c], m = csize[c];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  if (16 * wave >= m) return;
   const int v0 = blockIdx.y * NC;
   const int nvc = min(NC, nv - v0);
   const int k = rank[c];
   const int g0 = near_ptr[i], nnear = near_ptr[i + 1] - g0;
-  const int arow = 16 * wave + (lane & 15);        // A row of this lane
-  const bool arow_ok = arow < m;
-  const int kq = BF ? 4 * (lane >> 4) : (lane >> 4);  // k offset of this lane within a step
-  Acc acc[NT];
+  const int nsrc = nnear + (k > 0 ? 1 : 0);
+  mf_d4 acc[NT];
 #pragma unroll
   for (int ct = 0; ct < NT; ++ct)
 #pragma unroll
     for (int r = 0; r < 4; ++r) acc[ct][r] = 0;
-  const int nsrc = nnear + (k > 0 ? 1 : 0);
-  for (int src = 0; src < nsrc; ++src) {
-    const M* Ap;
-    const V* Bp;
-    int K, ldb;
-    if (src < nnear) {
-      const int g = g0 + src;
-      const int sc = leaf_base + near_col[g];
-      Ap = D + Doff[g];
-      K = csize[sc];
-      Bp = x + (size_t)v0 * ldx + cstart[sc];
-      ldb = ldx;
-    } else {
-      Ap = U + Uoff[i];
-      K = k;
-      Bp = yh + kpre[c] * nv + (size_t)v0 * k;
-      ldb = k;
-    }
-    const M* arow_p = Ap + (size_t)arow * K;
-#pragma unroll 16
-    for (int k0 = 0; k0 < K; k0 += T::KS) {
-      const int kk = k0 + kq;
-      if constexpr (BF) {
-        mf_s4 a;
-#pragma unroll
-        for (int e = 0; e < 4; ++e)
-          a[e] = (short)((arow_ok && kk + e < K) ? mf_a(arow_p[kk + e]) : (uint16_t)0);
-#pragma unroll
-        for (int ct = 0; ct < NT; ++ct) {
-          const int col = ct * 16 + (lane & 15);
-          const V* bp = Bp + (size_t)col * ldb + kk;
-          mf_s4 b;
-#pragma unroll
-          for (int e = 0; e < 4; ++e)
-            b[e] = (short)((col < nvc && kk + e < K) ? mf_b<uint16_t, V>(bp[e]) : (uint16_t)0);
-          acc[ct] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[ct], 0, 0, 0);
-        }
+  for (int q0 = 0; q0 < nsrc; q0 += PIPE_MAXSRC) {
+    const int nb = min(PIPE_MAXSRC, nsrc - q0);
+    __syncthreads();
+    if ((int)threadIdx.x < nb) {
+      const int q = q0 + (int)threadIdx.x;
+      PipeSrc d;
+      if (q < nnear) {
+        const int g = g0 + q;
+        const int sc = leaf_base + near_col[g];
+        d.A = (gdptr)(D + Doff[g]);
+        d.K = csize[sc];
+        d.B = (gdptr)(x + (size_t)v0 * ldx + cstart[sc]);
+        d.ldb = ldx;
       } else {
-        const typename T::SA a = (arow_ok && kk < K) ? mf_a(arow_p[kk]) : typename T::SA(0);
-#pragma unroll
-        for (int ct = 0; ct < NT; ++ct) {
-          const int col = ct * 16 + (lane & 15);
-          const typename T::SB b = (col < nvc && kk < K) ? mf_b<typename T::SB, V>(Bp[(size_t)col * ldb + kk])
-                                                           : typename T::SB(0);
-          if constexpr (sizeof(typename T::SA) == 8)
-            acc[ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[ct], 0, 0, 0);
-          else
-            acc[ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[ct], 0, 0, 0);
-        }
+        d.A = (gdptr)(U + Uoff[i]);
+        d.K = k;
+        d.B = (gdptr)(yh + kpre[c] * nv + (size_t)v0 * k);
+        d.ldb = k;
       }
+      ps[threadIdx.x] = d;
     }
+    __syncthreads();
+    blockrow_lds_pipe<NT>(m, nb, ps, nvc, acc, tl);
   }
+  if (16 * wave >= m) return;
 #pragma unroll
   for (int ct = 0; ct < NT; ++ct)
 #pragma unroll
@@ -582,6 +661,59 @@ __global__ __launch_bounds__(256) void k_coupling_mfma(
     for (int r = 0; r < 4; ++r) {
       const int row = 16 * wave + mf_row<M>(r, lane), col = ct * 16 + (lane & 15);
       if (row < kt && col < nvc) out[(size_t)(v0 + col) * kt + row] = (V)acc[ct][r];
+    }
+}
+
+// couplings in FP64 by the pipelined block-row product (same products, in
+// the same order, as k_coupling_mfma)
+template <int NT>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))) void k_coupling_direct(
+    const int32_t* __restrict__ rank, const int64_t* __restrict__ kpre,
+    const int32_t* __restrict__ far_ptr, const int32_t* __restrict__ far_col,
+    const int64_t* __restrict__ Soff, const double* __restrict__ S, int nv,
+    const double* __restrict__ xh, double* __restrict__ yh) {
+  constexpr int NC = 16 * NT;
+  __shared__ PipeSrc ps[PIPE_MAXSRC];
+  __shared__ PipeTiles<NT> tl;
+  const int c = blockIdx.x + 1;
+  const int kt = rank[c];
+  if (kt == 0) return;
+  const int l = 31 - __clz(c + 1);
+  const int base = (1 << l) - 1;
+  const int pb = far_ptr[c + l], pe = far_ptr[c + l + 1];
+  const int v0 = blockIdx.y * NC;
+  const int nvc = min(NC, nv - v0);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  mf_d4 acc[NT];
+#pragma unroll
+  for (int ct = 0; ct < NT; ++ct)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) acc[ct][r] = 0;
+  for (int q0 = 0; q0 < pe - pb; q0 += PIPE_MAXSRC) {
+    const int nb = min(PIPE_MAXSRC, pe - pb - q0);
+    __syncthreads();
+    if ((int)threadIdx.x < nb) {
+      const int g = pb + q0 + (int)threadIdx.x;
+      const int cs = base + far_col[g];
+      PipeSrc d;
+      d.K = rank[cs];
+      // (an empty block points at the start of the arrays, valid memory)
+      d.A = (gdptr)(d.K > 0 ? S + Soff[g] : S);
+      d.B = (gdptr)(d.K > 0 ? xh + kpre[cs] * nv + (size_t)v0 * d.K : xh);
+      d.ldb = d.K;
+      ps[threadIdx.x] = d;
+    }
+    __syncthreads();
+    blockrow_lds_pipe<NT>(kt, nb, ps, nvc, acc, tl);
+  }
+  if (16 * wave >= kt) return;
+  double* out = yh + kpre[c] * nv;
+#pragma unroll
+  for (int ct = 0; ct < NT; ++ct)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = 16 * wave + mf_row<double>(r, lane), col = ct * 16 + (lane & 15);
+      if (row < kt && col < nvc) out[(size_t)(v0 + col) * kt + row] = acc[ct][r];
     }
 }
 
@@ -698,9 +830,14 @@ template <class M, class V, int NT>
 static void coupling_nt(const h2_matrix* A, int nv, const V* xh, V* yh, hipStream_t s) {
   const h2_tree* t = A->tree;
   const unsigned gy = (unsigned)((nv + 16 * NT - 1) / (16 * NT));
-  k_coupling_mfma<M, V, NT><<<dim3(t->nclusters() - 1, gy), 256, 0, s>>>(
-      A->d_rank.as<int32_t>(), A->d_kpre.as<int64_t>(), t->d_far_ptr.as<int32_t>(),
-      t->d_far_col.as<int32_t>(), A->d_S_off.as<int64_t>(), A->st.S.as<M>(), nv, xh, yh);
+  if constexpr (std::is_same<M, double>::value && std::is_same<V, double>::value)
+    k_coupling_direct<NT><<<dim3(t->nclusters() - 1, gy), 256, 0, s>>>(
+        A->d_rank.as<int32_t>(), A->d_kpre.as<int64_t>(), t->d_far_ptr.as<int32_t>(),
+        t->d_far_col.as<int32_t>(), A->d_S_off.as<int64_t>(), A->st.S.as<M>(), nv, xh, yh);
+  else
+    k_coupling_mfma<M, V, NT><<<dim3(t->nclusters() - 1, gy), 256, 0, s>>>(
+        A->d_rank.as<int32_t>(), A->d_kpre.as<int64_t>(), t->d_far_ptr.as<int32_t>(),
+        t->d_far_col.as<int32_t>(), A->d_S_off.as<int64_t>(), A->st.S.as<M>(), nv, xh, yh);
 }
 template <class M, class V, int NT>
 static void leaf_nt(const h2_matrix* A, int nv, V alpha, const V* xt, int ldx, V beta, V* yt,

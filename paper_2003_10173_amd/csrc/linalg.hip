@@ -80,7 +80,7 @@ void Scratch::clear() {
 }
 
 // ------------------------------------------------------------------ GEMM
-constexpr int TM = 64, TN = 64, TK = 16;
+constexpr int TM = 64, TN = 64, TK = 32, TQ = TM * TK / 256;
 
 struct GemmTask {
   GemmDesc d;
@@ -91,10 +91,16 @@ struct GemmTask {
   double beta;          // applied to `out`
 };
 
+// One 64 x 64 output tile per workgroup.  The K range is walked in blocks
+// of TK: every block is read from memory into registers one block ahead of
+// its use (clamped, in-range addresses; the positions outside the operands
+// are zeroed when stored), stored into one of two LDS tile buffers and
+// multiplied there on the matrix cores after a single barrier, so that the
+// loads of the next block overlap the products of this one.
 __global__ __launch_bounds__(256) void k_gemm(const GemmTask* __restrict__ tasks,
                                               const int64_t* __restrict__ tile_start, int ntasks) {
-  __shared__ double As[TK][TM + 1];
-  __shared__ double Bs[TK][TN + 1];
+  __shared__ double As[2][TK][TM + 1];
+  __shared__ double Bs[2][TK][TN + 1];
   // locate the task of this block
   int lo = 0, hi = ntasks - 1;
   const int64_t b = blockIdx.x;
@@ -116,43 +122,77 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmTask* __restrict__ tasks
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
-  for (int k0 = t.k0; k0 < t.k1; k0 += TK) {
+  // this thread's elements of a block: A (i, k) and B (k, j) for q < TQ
+  // (consecutive threads along the operand's contiguous dimension)
+  int ai[TQ], ak[TQ], bj[TQ], bk[TQ];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int e = tid + 256 * q;
-      int i, k;
-      if (!d.ta) { i = e & 63; k = e >> 6; } else { k = e & 15; i = e >> 4; }
-      const int gi = bm + i, gk = k0 + k;
-      double v = 0;
-      if (gi < d.M && gk < t.k1)
-        v = d.ta ? d.A[(size_t)gi * d.lda + gk] : d.A[(size_t)gk * d.lda + gi];
-      As[k][i] = v;
-      int j, kk;
-      if (!d.tb) { kk = e & 15; j = e >> 4; } else { j = e & 63; kk = e >> 6; }
-      const int gj = bn + j, gk2 = k0 + kk;
-      double w = 0;
-      if (gj < d.N && gk2 < t.k1)
-        w = d.tb ? d.B[(size_t)gk2 * d.ldb + gj] : d.B[(size_t)gj * d.ldb + gk2];
-      Bs[kk][j] = w;
+  for (int q = 0; q < TQ; ++q) {
+    const int e = tid + 256 * q;
+    if (!d.ta) { ai[q] = e % TM; ak[q] = e / TM; } else { ak[q] = e % TK; ai[q] = e / TK; }
+    if (!d.tb) { bk[q] = e % TK; bj[q] = e / TK; } else { bj[q] = e % TN; bk[q] = e / TN; }
+  }
+  const int mc = d.M - 1, nc = d.N - 1;
+  // (global-memory pointers: their loads count only against the vector
+  // memory counter, not against the LDS one that the tile reads wait on)
+  typedef const double __attribute__((address_space(1)))* gptr;
+  const gptr Ag = (gptr)d.A, Bg = (gptr)d.B;
+  double va[TQ], vb[TQ];
+  auto gload = [&](int k0) {
+    const int kl = t.k1 - 1;
+#pragma unroll
+    for (int q = 0; q < TQ; ++q) {
+      const int gi = min(bm + ai[q], mc), gk = min(k0 + ak[q], kl);
+      va[q] = d.ta ? Ag[(size_t)gi * d.lda + gk] : Ag[(size_t)gk * d.lda + gi];
+      const int gj = min(bn + bj[q], nc), gk2 = min(k0 + bk[q], kl);
+      vb[q] = d.tb ? Bg[(size_t)gk2 * d.ldb + gj] : Bg[(size_t)gj * d.ldb + gk2];
     }
+  };
+  auto lstore = [&](int k0, int buf) {
+#pragma unroll
+    for (int q = 0; q < TQ; ++q) {
+      As[buf][ak[q]][ai[q]] = (bm + ai[q] < d.M && k0 + ak[q] < t.k1) ? va[q] : 0.0;
+      Bs[buf][bk[q]][bj[q]] = (bn + bj[q] < d.N && k0 + bk[q] < t.k1) ? vb[q] : 0.0;
+    }
+  };
+  if (t.k0 < t.k1) gload(t.k0);
+  int buf = 0;
+  for (int k0 = t.k0; k0 < t.k1; k0 += TK) {
+    // buffer buf was last read by the products of block k0 - 2 TK, which
+    // every wave finished before the barrier of block k0 - TK
+    lstore(k0, buf);
     __syncthreads();
+    if (k0 + TK < t.k1) gload(k0 + TK);
 #pragma unroll
     for (int ks = 0; ks < TK; ks += 4) {
       const int kk = ks + (lane >> 4);
       double a[2], bb[2];
 #pragma unroll
-      for (int i = 0; i < 2; ++i) a[i] = As[kk][wr + 16 * i + (lane & 15)];
+      for (int i = 0; i < 2; ++i) a[i] = As[buf][kk][wr + 16 * i + (lane & 15)];
 #pragma unroll
-      for (int j = 0; j < 2; ++j) bb[j] = Bs[kk][wc + 16 * j + (lane & 15)];
+      for (int j = 0; j < 2; ++j) bb[j] = Bs[buf][kk][wc + 16 * j + (lane & 15)];
 #pragma unroll
       for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j)
           acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], bb[j], acc[i][j], 0, 0, 0);
     }
-    __syncthreads();
+    buf ^= 1;
   }
-  // result register r of a 16 x 16 f64 product: row 4 r + lane / 16, column lane % 16
+  // result register r of a 16 x 16 f64 product: row 4 r + lane / 16, column
+  // lane % 16; with beta != 0 the 16 old values are read first, together
+  typedef double __attribute__((address_space(1)))* gout;
+  const gout Og = (gout)t.out;
+  double old[2][2][4];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int gi = bm + wr + 16 * i + 4 * r + (lane >> 4);
+        const int gj = bn + wc + 16 * j + (lane & 15);
+        old[i][j][r] = (t.beta != 0.0 && gi < d.M && gj < d.N) ? Og[(size_t)gj * t.ldo + gi] : 0.0;
+      }
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -162,9 +202,8 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmTask* __restrict__ tasks
         const int gi = bm + wr + 16 * i + 4 * r + (lane >> 4);
         const int gj = bn + wc + 16 * j + (lane & 15);
         if (gi < d.M && gj < d.N) {
-          double* o = t.out + (size_t)gj * t.ldo + gi;
           const double v = d.alpha * acc[i][j][r];
-          *o = t.beta == 0.0 ? v : v + t.beta * *o;
+          Og[(size_t)gj * t.ldo + gi] = t.beta == 0.0 ? v : v + t.beta * old[i][j][r];
         }
       }
 }
@@ -641,16 +680,26 @@ __global__ __launch_bounds__(512) void k_svd_block(const SVDDesc* __restrict__ d
         // Gram partials on the matrix cores: wave w takes rows 4 kb .. 4 kb + 3
         // for kb = w, w + 8, ...; lane l supplies L(row 4 kb + l / 16, column
         // l % 16) as both operands; result element (4 e + l / 16, l % 16) in acc[e]
+        // (four k-blocks per step: their LDS reads are issued together and
+        // feed two accumulators, so neither waits on the other)
         {
-          svd_d4 acc = {0.0, 0.0, 0.0, 0.0};
+          svd_d4 acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
           const int col = lane & 15, kr = lane >> 4;
-          for (int kb = wave; 4 * kb < m; kb += 8) {
-            const int row = 4 * kb + kr;
-            const double x = (row < m && col < nc) ? L[col * m + row] : 0.0;
-            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(x, x, acc, 0, 0, 0);
+          const bool cok = col < nc;
+          for (int kb = wave; 4 * kb < m; kb += 32) {
+            double x[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+              const int row = 4 * (kb + 8 * u) + kr;
+              x[u] = (row < m && cok) ? L[col * m + row] : 0.0;
+            }
+            acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(x[0], x[0], acc0, 0, 0, 0);
+            acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(x[1], x[1], acc1, 0, 0, 0);
+            acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(x[2], x[2], acc0, 0, 0, 0);
+            acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(x[3], x[3], acc1, 0, 0, 0);
           }
 #pragma unroll
-          for (int e = 0; e < 4; ++e) Gp[wave * 256 + (4 * e + kr) * SVD_PC + col] = acc[e];
+          for (int e = 0; e < 4; ++e) Gp[wave * 256 + (4 * e + kr) * SVD_PC + col] = acc0[e] + acc1[e];
         }
         __syncthreads();
         if (tid < SVD_PC * SVD_PC) {
@@ -751,9 +800,11 @@ __global__ __launch_bounds__(512) void k_svd_block(const SVDDesc* __restrict__ d
         }
         const double* Wf = Gp + 256;
         // columns of A (from LDS) and of V (from memory) times W on the matrix
-        // cores, 16 rows per product: lane l supplies X(row r0 + l % 16, column
-        // k0 + l / 16) and W(k0 + l / 16, l % 16); the result element
-        // (r0 + 4 e + l / 16, l % 16) is in acc[e]
+        // cores, 16 rows per product, formed transposed as W^T X^T: lane l
+        // supplies W(k0 + l / 16, l % 16) as the first operand and X(row
+        // r0 + l % 16, column k0 + l / 16) as the second; acc[e] then holds
+        // (X W)(r0 + l % 16, 4 e + l / 16), so the 16 lanes of one column
+        // store 16 consecutive rows
         if (rot_any) {
           const int kr = lane >> 4, cl = lane & 15;
           double wb[4];
@@ -763,12 +814,13 @@ __global__ __launch_bounds__(512) void k_svd_block(const SVDDesc* __restrict__ d
           auto tile = [&](const double (&x)[4], double* Y, int ldy, int r0, int rows) {
             svd_d4 acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-            for (int kk = 0; kk < 4; ++kk) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(x[kk], wb[kk], acc, 0, 0, 0);
-            if (cl < nc) {
+            for (int kk = 0; kk < 4; ++kk) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(wb[kk], x[kk], acc, 0, 0, 0);
+            const int row = r0 + cl;
+            if (row < rows) {
 #pragma unroll
               for (int e = 0; e < 4; ++e) {
-                const int row = r0 + 4 * e + kr;
-                if (row < rows) Y[(size_t)cols[cl] * ldy + row] = acc[e];
+                const int q = 4 * e + kr;
+                if (q < nc) Y[(size_t)cols[q] * ldy + row] = acc[e];
               }
             }
           };

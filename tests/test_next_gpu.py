@@ -148,7 +148,15 @@ def test_minsurf_newton_schulz_static_and_dynamic_match_oracle(dynamic):
     y = host(X.gemv(dev(x)))
     want = Xo.matvec(x)
     print("iterate |diff| %.3e of max %.3e" % (np.max(np.abs(y - want)), np.max(np.abs(want))))
-    assert st["applies"] == pr.applies
+    # the range bases' numerical rank (singular values above 1e-13 of the
+    # largest) can differ by a column whose value sits within rounding of
+    # that cut: one product more or less per level, nothing above rounding in
+    # the operator; the truncated (weak) ranks and the final ranks agree
+    k0o = [int(pr.k0[l].max()) for l in range(1, L + 1)]
+    assert all(abs(a - b) <= 1 for a, b in zip(st["range_cols"], k0o))
+    assert abs(st["applies"] - pr.applies) <= sum(abs(a - b) for a, b in zip(st["range_cols"], k0o))
+    assert st["weak_rank"] == [int(pr.kw[l].max()) for l in range(1, L + 1)]
+    assert np.max(np.abs(ya - yb)) <= 1e-10 * np.max(np.abs(yb))
     assert np.array_equal(G.ranks(), np.concatenate([H.rank[l] for l in range(T.L + 1)]))
     assert g["status"] == 0 and info["status"] == "converged"
     compare_ns(g, info, X, Xo, T.n, T.L, exact_applies=False)
