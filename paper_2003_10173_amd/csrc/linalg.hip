@@ -531,6 +531,7 @@ __global__ __launch_bounds__(512) void k_svd_sweeps(const SVDDesc* __restrict__ 
 // end within a few seconds marks status[1] (the singular values of the call
 // then come out as NaN) instead of hanging.
 constexpr int SVD_BS = 8, SVD_PC = 2 * SVD_BS, SVD_MMAX = 1024, SVD_INNER = 1, SVD_VPF = 4;
+static_assert((SVD_BS & (SVD_BS - 1)) == 0, "the cross-pair steps index blocks by masking");
 typedef double svd_d4 __attribute__((ext_vector_type(4)));
 
 // the pairs of tournament_pair without integer division (r < np - 1, k < np / 2)
@@ -710,10 +711,15 @@ __global__ __launch_bounds__(512) void k_svd_block(const SVDDesc* __restrict__ d
           Ws[tid] = (tid / SVD_PC == tid % SVD_PC) ? 1.0 : 0.0;
         }
         __syncthreads();
+        // Pairs of columns from the two blocks meet in every round; pairs
+        // within one block need one visit per sweep, which they get in the
+        // sweep's first round (and in any round with a partial block).  The
+        // other rounds test and rotate only the cross pairs.
+        const bool full = r == 0 || nc < SVD_PC;
         // convergence test on the Gram matrix of the current columns
         if (tid < SVD_PC * SVD_PC) {
           const int i = tid / SVD_PC, j = tid % SVD_PC;
-          if (i < j && j < nc) {
+          if (i < j && j < nc && (full || (i < SVD_BS && j >= SVD_BS))) {
             if (jacobi_needs(Gs[i * 17], Gs[j * 17], Gs[tid], tol)) rot_any = 1;
           }
         }
@@ -728,15 +734,26 @@ __global__ __launch_bounds__(512) void k_svd_block(const SVDDesc* __restrict__ d
           const int npc = nc + (nc & 1);
           const int P = lane >> 3, Q = lane & 7;
           const bool act = P < npc / 2 && Q < npc / 2;
+          // full rounds: the tournament over all 2 SVD_BS columns; otherwise
+          // the SVD_BS steps that pair column P of the first block with
+          // column (P + step) mod SVD_BS of the second
+          const int nsteps = full ? npc - 1 : SVD_BS;
           for (int isw = 0; isw < SVD_INNER; ++isw) {
             int rotated = 0;
-            for (int rr = 0; rr < npc - 1; ++rr) {
+            for (int rr = 0; rr < nsteps; ++rr) {
               int aP = 0, bP = 0, aQ = 0, bQ = 0;
               double g00 = 0, g01 = 0, g10 = 0, g11 = 0, w00 = 0, w01 = 0, w10 = 0, w11 = 0;
               double pa = 0, pb = 0, pg = 0, qa = 0, qb = 0, qg = 0;
               if (act) {
-                tournament_pair_fast(npc, rr, P, aP, bP);
-                tournament_pair_fast(npc, rr, Q, aQ, bQ);
+                if (full) {
+                  tournament_pair_fast(npc, rr, P, aP, bP);
+                  tournament_pair_fast(npc, rr, Q, aQ, bQ);
+                } else {
+                  aP = P;
+                  bP = SVD_BS + ((P + rr) & (SVD_BS - 1));
+                  aQ = Q;
+                  bQ = SVD_BS + ((Q + rr) & (SVD_BS - 1));
+                }
                 g00 = G[aP * SVD_PC + aQ];
                 g01 = G[aP * SVD_PC + bQ];
                 g10 = G[bP * SVD_PC + aQ];
