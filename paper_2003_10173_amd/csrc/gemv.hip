@@ -82,6 +82,17 @@ std::unique_ptr<h2_matrix> matrix_clone_layout(const h2_matrix* A) {
 }
 
 // ------------------------------------------------------------------ kernels
+// Workgroups are dealt to the 8 XCDs in turn (workgroup b runs on XCD
+// b mod 8, each XCD with its own L2).  xcd_local maps them so that every XCD
+// takes a contiguous range of [0, n): tree-ordered leaves are spatially
+// close, so the multivector blocks that neighbouring leaves share stay in
+// one L2.  The identity when n is not a multiple of 8.
+__device__ inline int xcd_local(int b, int n) {
+  constexpr int NX = 8;
+  if (n % NX) return b;
+  return (b % NX) * (n / NX) + b / NX;
+}
+
 template <class M, class V>
 __global__ void k_up_leaf(int L, const int32_t* __restrict__ cstart,
                           const int32_t* __restrict__ csize, const int32_t* __restrict__ rank,
@@ -377,7 +388,7 @@ __global__ __launch_bounds__(256) void k_leaf_mfma(
     const int64_t* __restrict__ Doff, const M* __restrict__ D, int nv, const V* __restrict__ yh,
     const V* __restrict__ x, int ldx, V alpha, V beta, V* __restrict__ y, int ldy) {
   MF_SHARED(M, NT)
-  const int i = blockIdx.x;
+  const int i = xcd_local(blockIdx.x, gridDim.x);
   const int leaf_base = (1 << L) - 1;
   const int c = leaf_base + i;
   const int r0 = cstart[c], m = csize[c];
@@ -541,7 +552,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))) voi
   constexpr int NC = 16 * NT;
   __shared__ PipeSrc ps[PIPE_MAXSRC];
   __shared__ PipeTiles<NT> tl;
-  const int i = blockIdx.x;
+  const int i = xcd_local(blockIdx.x, gridDim.x);
   const int leaf_base = (1 << L) - 1;
   const int c = leaf_base + i;
   const int r0 = cstart[c], m = csize[c];
@@ -664,59 +675,6 @@ __global__ __launch_bounds__(256) void k_coupling_mfma(
     }
 }
 
-// couplings in FP64 by the pipelined block-row product (same products, in
-// the same order, as k_coupling_mfma)
-template <int NT>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))) void k_coupling_direct(
-    const int32_t* __restrict__ rank, const int64_t* __restrict__ kpre,
-    const int32_t* __restrict__ far_ptr, const int32_t* __restrict__ far_col,
-    const int64_t* __restrict__ Soff, const double* __restrict__ S, int nv,
-    const double* __restrict__ xh, double* __restrict__ yh) {
-  constexpr int NC = 16 * NT;
-  __shared__ PipeSrc ps[PIPE_MAXSRC];
-  __shared__ PipeTiles<NT> tl;
-  const int c = blockIdx.x + 1;
-  const int kt = rank[c];
-  if (kt == 0) return;
-  const int l = 31 - __clz(c + 1);
-  const int base = (1 << l) - 1;
-  const int pb = far_ptr[c + l], pe = far_ptr[c + l + 1];
-  const int v0 = blockIdx.y * NC;
-  const int nvc = min(NC, nv - v0);
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  mf_d4 acc[NT];
-#pragma unroll
-  for (int ct = 0; ct < NT; ++ct)
-#pragma unroll
-    for (int r = 0; r < 4; ++r) acc[ct][r] = 0;
-  for (int q0 = 0; q0 < pe - pb; q0 += PIPE_MAXSRC) {
-    const int nb = min(PIPE_MAXSRC, pe - pb - q0);
-    __syncthreads();
-    if ((int)threadIdx.x < nb) {
-      const int g = pb + q0 + (int)threadIdx.x;
-      const int cs = base + far_col[g];
-      PipeSrc d;
-      d.K = rank[cs];
-      // (an empty block points at the start of the arrays, valid memory)
-      d.A = (gdptr)(d.K > 0 ? S + Soff[g] : S);
-      d.B = (gdptr)(d.K > 0 ? xh + kpre[cs] * nv + (size_t)v0 * d.K : xh);
-      d.ldb = d.K;
-      ps[threadIdx.x] = d;
-    }
-    __syncthreads();
-    blockrow_lds_pipe<NT>(kt, nb, ps, nvc, acc, tl);
-  }
-  if (16 * wave >= kt) return;
-  double* out = yh + kpre[c] * nv;
-#pragma unroll
-  for (int ct = 0; ct < NT; ++ct)
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int row = 16 * wave + mf_row<double>(r, lane), col = ct * 16 + (lane & 15);
-      if (row < kt && col < nvc) out[(size_t)(v0 + col) * kt + row] = acc[ct][r];
-    }
-}
-
 template <class V>
 __global__ void k_gather(int n, int nv, const int32_t* __restrict__ perm, const V* __restrict__ x,
                          int ldx, V* __restrict__ xt, int ldt) {
@@ -830,14 +788,12 @@ template <class M, class V, int NT>
 static void coupling_nt(const h2_matrix* A, int nv, const V* xh, V* yh, hipStream_t s) {
   const h2_tree* t = A->tree;
   const unsigned gy = (unsigned)((nv + 16 * NT - 1) / (16 * NT));
-  if constexpr (std::is_same<M, double>::value && std::is_same<V, double>::value)
-    k_coupling_direct<NT><<<dim3(t->nclusters() - 1, gy), 256, 0, s>>>(
-        A->d_rank.as<int32_t>(), A->d_kpre.as<int64_t>(), t->d_far_ptr.as<int32_t>(),
-        t->d_far_col.as<int32_t>(), A->d_S_off.as<int64_t>(), A->st.S.as<M>(), nv, xh, yh);
-  else
-    k_coupling_mfma<M, V, NT><<<dim3(t->nclusters() - 1, gy), 256, 0, s>>>(
-        A->d_rank.as<int32_t>(), A->d_kpre.as<int64_t>(), t->d_far_ptr.as<int32_t>(),
-        t->d_far_col.as<int32_t>(), A->d_S_off.as<int64_t>(), A->st.S.as<M>(), nv, xh, yh);
+  // (small blocks, many per cluster: the single-buffered LDS tiles of
+  // blockrow_mfma, which leave room for two workgroups per compute unit, beat
+  // the register-pipelined product here, in FP64 too)
+  k_coupling_mfma<M, V, NT><<<dim3(t->nclusters() - 1, gy), 256, 0, s>>>(
+      A->d_rank.as<int32_t>(), A->d_kpre.as<int64_t>(), t->d_far_ptr.as<int32_t>(),
+      t->d_far_col.as<int32_t>(), A->d_S_off.as<int64_t>(), A->st.S.as<M>(), nv, xh, yh);
 }
 template <class M, class V, int NT>
 static void leaf_nt(const h2_matrix* A, int nv, V alpha, const V* xt, int ldx, V beta, V* yt,
