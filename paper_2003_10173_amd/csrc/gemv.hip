@@ -427,46 +427,62 @@ __global__ __launch_bounds__(256) void k_leaf_mfma(
     }
 }
 
-// FP64 block-row product, pipelined through LDS: out (rows x nvc) = sum over
-// sources q of A_q B_q (A_q row-major rows x K_q, B_q column-major K_q x nvc
-// with leading dimension ldb_q; rows, K_q <= 64).  Each source is read with
-// coalesced loads (A a row at a time, B a column at a time) into registers
-// two sources ahead of its use, stored into one of two LDS tile buffers, and
-// multiplied on the matrix cores from there after a single barrier, so that
-// the loads of the next sources overlap the products of this one.  The
-// products and their order are those of blockrow_mfma (sources ascending, k
-// ascending in steps of 4); wave w owns rows 16 w..16 w + 15 and NT 16-column
-// tiles.
+// Block-row product in FP64 or FP32, pipelined through LDS: out (rows x nvc)
+// = sum over sources q of A_q B_q (A_q row-major rows x K_q, B_q
+// column-major K_q x nvc with leading dimension ldb_q; rows, K_q <= 64).
+// Each source is read with coalesced loads (A a row at a time, B a column at
+// a time) into registers two sources ahead of its use, stored into one of two
+// LDS tile buffers, and multiplied on the matrix cores (16x16x4, f64 or f32)
+// from there after a single barrier, so that the loads of the next sources
+// overlap the products of this one.  The products and their order are those
+// of blockrow_mfma (sources ascending, k ascending in steps of 4); wave w owns
+// rows 16 w..16 w + 15 and NT 16-column tiles.
 // (global-memory pointers: their loads then count only against the vector
 // memory counter, not against the LDS one that the tile accesses wait on)
-typedef const double __attribute__((address_space(1)))* gdptr;
-struct PipeSrc {
-  gdptr A;
-  gdptr B;
+template <class T> using gptr_t = const T __attribute__((address_space(1)))*;
+template <class T> struct PipeSrc {
+  gptr_t<T> A;
+  gptr_t<T> B;
   int K, ldb;
 };
-constexpr int PIPE_MAXSRC = 64, PIPE_ALD = 64 + 2;
-template <int NT> struct PipeTiles {
-  static constexpr int NC = 16 * NT, BLD = NC + 2;
+template <class T> struct PipeMfma;
+template <> struct PipeMfma<double> {
+  using Acc = mf_d4;
+  static constexpr int PAD = 2;   // row padding of the tiles (bank spread)
+  __device__ static Acc mma(double a, double b, Acc c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+};
+template <> struct PipeMfma<float> {
+  using Acc = mf_f4;
+  static constexpr int PAD = 4;
+  __device__ static Acc mma(float a, float b, Acc c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+};
+constexpr int PIPE_MAXSRC = 64;
+template <class T, int NT> struct PipeTiles {
+  static constexpr int NC = 16 * NT, ALD = 64 + PipeMfma<T>::PAD, BLD = NC + PipeMfma<T>::PAD;
   static constexpr int RA = 16, RB = NC / 4;    // registers per thread
-  double A[2][64 * PIPE_ALD];
-  double B[2][64 * BLD];
+  T A[2][64 * ALD];
+  T B[2][64 * BLD];
 };
 
-template <int NT>
-__device__ inline void blockrow_lds_pipe(int rows, int nsrc, const PipeSrc* __restrict__ ps,
-                                         int nvc, mf_d4 (&acc)[NT], PipeTiles<NT>& tl) {
-  using P = PipeTiles<NT>;
+template <class T, int NT>
+__device__ inline void blockrow_lds_pipe(int rows, int nsrc, const PipeSrc<T>* __restrict__ ps,
+                                         int nvc, typename PipeMfma<T>::Acc (&acc)[NT],
+                                         PipeTiles<T, NT>& tl) {
+  using P = PipeTiles<T, NT>;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   // A: wave w, register j holds row 4 j + w, k = lane (one row of the
   // row-major block per load instruction); B: register j holds column
   // 4 j + w, k = lane (one column per instruction).  Loads use clamped,
   // in-range addresses; the positions outside the block are zeroed when
   // stored to LDS.
-  auto gload = [&](int q, double (&ra)[P::RA], double (&rb)[P::RB]) {
+  auto gload = [&](int q, T (&ra)[P::RA], T (&rb)[P::RB]) {
     // (straight-line loads: an empty block, K = 0, carries pointers to valid
     // memory and reads its first element, stored as zeros)
-    const PipeSrc S = ps[q < nsrc ? q : nsrc - 1];
+    const PipeSrc<T> S = ps[q < nsrc ? q : nsrc - 1];
     const int kl = (S.K > 0 ? S.K : 1) - 1;
     const int kc = lane < kl ? lane : kl;
 #pragma unroll
@@ -480,17 +496,17 @@ __device__ inline void blockrow_lds_pipe(int rows, int nsrc, const PipeSrc* __re
       rb[j] = S.B[(size_t)(cb < nvc ? cb : nvc - 1) * S.ldb + kc];
     }
   };
-  auto lstore = [&](int q, int buf, const double (&ra)[P::RA], const double (&rb)[P::RB]) {
+  auto lstore = [&](int q, int buf, const T (&ra)[P::RA], const T (&rb)[P::RB]) {
     const int K = q < nsrc ? ps[q].K : 0;
 #pragma unroll
     for (int j = 0; j < P::RA; ++j) {
       const int r = 4 * j + wave;
-      tl.A[buf][r * PIPE_ALD + lane] = (r < rows && lane < K) ? ra[j] : 0.0;
+      tl.A[buf][r * P::ALD + lane] = (r < rows && lane < K) ? ra[j] : T(0);
     }
 #pragma unroll
     for (int j = 0; j < P::RB; ++j) {
       const int cb = 4 * j + wave;
-      tl.B[buf][lane * P::BLD + cb] = (cb < nvc && lane < K) ? rb[j] : 0.0;
+      tl.B[buf][lane * P::BLD + cb] = (cb < nvc && lane < K) ? rb[j] : T(0);
     }
   };
   // the k-steps in groups of four (16 k-values), each group's LDS reads
@@ -498,12 +514,12 @@ __device__ inline void blockrow_lds_pipe(int rows, int nsrc, const PipeSrc* __re
   auto mma = [&](int q, int buf) {
     if (16 * wave >= rows || q >= nsrc) return;
     const int KP = (ps[q].K + 3) & ~3;
-    const double* As = tl.A[buf] + (16 * wave + (lane & 15)) * PIPE_ALD + (lane >> 4);
-    const double* Bs = tl.B[buf] + (lane >> 4) * P::BLD + (lane & 15);
+    const T* As = tl.A[buf] + (16 * wave + (lane & 15)) * P::ALD + (lane >> 4);
+    const T* Bs = tl.B[buf] + (lane >> 4) * P::BLD + (lane & 15);
 #pragma unroll
     for (int g = 0; g < 4; ++g) {
       if (16 * g >= KP) break;
-      double a[4], b[NT][4];
+      T a[4], b[NT][4];
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
         a[t] = As[16 * g + 4 * t];
@@ -515,12 +531,11 @@ __device__ inline void blockrow_lds_pipe(int rows, int nsrc, const PipeSrc* __re
 #pragma unroll
       for (int t = 0; t < 4; ++t)
 #pragma unroll
-        for (int ct = 0; ct < NT; ++ct)
-          acc[ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[t], b[ct][t], acc[ct], 0, 0, 0);
+        for (int ct = 0; ct < NT; ++ct) acc[ct] = PipeMfma<T>::mma(a[t], b[ct][t], acc[ct]);
     }
   };
   if (nsrc <= 0) return;
-  double ra0[P::RA], rb0[P::RB], ra1[P::RA], rb1[P::RB];
+  T ra0[P::RA], rb0[P::RB], ra1[P::RA], rb1[P::RB];
   gload(0, ra0, rb0);
   gload(1, ra1, rb1);
   // (sources in pairs, an odd count padded by an empty one: the loop body
@@ -539,7 +554,7 @@ __device__ inline void blockrow_lds_pipe(int rows, int nsrc, const PipeSrc* __re
   }
 }
 
-// leaf stage in FP64: y_t = alpha (U_t y^_t + sum_near D_ts x_s) + beta y_t
+// leaf stage in FP64 or FP32: y_t = alpha (U_t y^_t + sum_near D_ts x_s) + beta y_t
 template <class M, class V, int NT>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))) void k_leaf_direct(
     int L, const int32_t* __restrict__ cstart, const int32_t* __restrict__ csize,
@@ -548,10 +563,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))) voi
     const int32_t* __restrict__ near_ptr, const int32_t* __restrict__ near_col,
     const int64_t* __restrict__ Doff, const M* __restrict__ D, int nv, const V* __restrict__ yh,
     const V* __restrict__ x, int ldx, V alpha, V beta, V* __restrict__ y, int ldy) {
-  static_assert(std::is_same<M, double>::value && std::is_same<V, double>::value, "FP64 only");
+  static_assert(std::is_same<M, V>::value &&
+                    (std::is_same<M, double>::value || std::is_same<M, float>::value),
+                "FP64 or FP32 storage and vectors");
+  using T = M;
+  using gp = gptr_t<T>;
   constexpr int NC = 16 * NT;
-  __shared__ PipeSrc ps[PIPE_MAXSRC];
-  __shared__ PipeTiles<NT> tl;
+  __shared__ PipeSrc<T> ps[PIPE_MAXSRC];
+  __shared__ PipeTiles<T, NT> tl;
   const int i = xcd_local(blockIdx.x, gridDim.x);
   const int leaf_base = (1 << L) - 1;
   const int c = leaf_base + i;
@@ -562,7 +581,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))) voi
   const int k = rank[c];
   const int g0 = near_ptr[i], nnear = near_ptr[i + 1] - g0;
   const int nsrc = nnear + (k > 0 ? 1 : 0);
-  mf_d4 acc[NT];
+  typename PipeMfma<T>::Acc acc[NT];
 #pragma unroll
   for (int ct = 0; ct < NT; ++ct)
 #pragma unroll
@@ -572,24 +591,24 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))) voi
     __syncthreads();
     if ((int)threadIdx.x < nb) {
       const int q = q0 + (int)threadIdx.x;
-      PipeSrc d;
+      PipeSrc<T> d;
       if (q < nnear) {
         const int g = g0 + q;
         const int sc = leaf_base + near_col[g];
-        d.A = (gdptr)(D + Doff[g]);
+        d.A = (gp)(D + Doff[g]);
         d.K = csize[sc];
-        d.B = (gdptr)(x + (size_t)v0 * ldx + cstart[sc]);
+        d.B = (gp)(x + (size_t)v0 * ldx + cstart[sc]);
         d.ldb = ldx;
       } else {
-        d.A = (gdptr)(U + Uoff[i]);
+        d.A = (gp)(U + Uoff[i]);
         d.K = k;
-        d.B = (gdptr)(yh + kpre[c] * nv + (size_t)v0 * k);
+        d.B = (gp)(yh + kpre[c] * nv + (size_t)v0 * k);
         d.ldb = k;
       }
       ps[threadIdx.x] = d;
     }
     __syncthreads();
-    blockrow_lds_pipe<NT>(m, nb, ps, nvc, acc, tl);
+    blockrow_lds_pipe<T, NT>(m, nb, ps, nvc, acc, tl);
   }
   if (16 * wave >= m) return;
 #pragma unroll
@@ -800,9 +819,10 @@ static void leaf_nt(const h2_matrix* A, int nv, V alpha, const V* xt, int ldx, V
                     int ldy, const V* yh, hipStream_t s) {
   const h2_tree* t = A->tree;
   const unsigned gy = (unsigned)((nv + 16 * NT - 1) / (16 * NT));
-  // FP64: operands straight from memory (8-byte loads); FP32 / BF16: LDS tiles
-  // (their 4- and 2-byte element loads would waste memory transactions)
-  if constexpr (std::is_same<M, double>::value)
+  // FP64 and FP32: the LDS-pipelined kernel; BF16 (16x16x16 products): the
+  // block-row routine
+  if constexpr (std::is_same<M, V>::value &&
+                (std::is_same<M, double>::value || std::is_same<M, float>::value))
     k_leaf_direct<M, V, NT><<<dim3(1 << t->L, gy), 256, 0, s>>>(
         t->L, t->d_cstart.as<int32_t>(), t->d_csize.as<int32_t>(), A->d_rank.as<int32_t>(),
         A->d_kpre.as<int64_t>(), A->d_U_off.as<int64_t>(), A->st.U.as<M>(),
