@@ -192,7 +192,13 @@ struct LsvTask {
   int ld, M, K;
   double* U;      // M x min(M,K)
   double* sigma;  // min(M,K)
+  double tol = 0.0;  // Jacobi tolerance (SVDDesc::tol)
 };
+
+// Jacobi tolerance of the SVDs of a build: samples known to FP32 precision
+// (rank cut 1e-7 sigma_1) are orthogonalised to 1e-2 of their rank cut, far
+// below the samples' own error; FP64 samples to the FP64 rounding level
+static double svd_tol(const BuildParams& p) { return p.rank_cut > 1e-12 ? 1e-2 * p.rank_cut : 0.0; }
 
 void left_svd_batched(Ctx& c, const std::vector<LsvTask>& tasks) {
   std::vector<CopyDesc> tr;
@@ -213,11 +219,11 @@ void left_svd_batched(Ctx& c, const std::vector<LsvTask>& tasks) {
       tr.push_back({tk.X, tk.ld, Xt, tk.K, tk.K, tk.M, 1.0, 0.0, 1});
       rq.push_back({Xt, tk.K, tk.K, tk.M, nullptr, 0, R, tk.M});
       rtr.push_back({R, tk.M, Rt, tk.M, tk.M, tk.M, 1.0, 0.0, 1});
-      svs.push_back({Rt, tk.M, tk.M, tk.M, tk.sigma, tk.U, tk.M, nullptr, 0});
+      svs.push_back({Rt, tk.M, tk.M, tk.M, tk.sigma, tk.U, tk.M, nullptr, 0, tk.tol});
     } else if (tk.K >= tk.M) {
       double* Xt = c.scratch.get((size_t)tk.K * tk.M);
       tr.push_back({tk.X, tk.ld, Xt, tk.K, tk.K, tk.M, 1.0, 0.0, 1});
-      svs.push_back({Xt, tk.K, tk.K, tk.M, tk.sigma, nullptr, 0, tk.U, tk.M});
+      svs.push_back({Xt, tk.K, tk.K, tk.M, tk.sigma, nullptr, 0, tk.U, tk.M, tk.tol});
     } else {
       double* Q = c.scratch.get((size_t)tk.M * tk.K);
       double* R = c.scratch.get((size_t)tk.K * tk.K);
@@ -225,7 +231,7 @@ void left_svd_batched(Ctx& c, const std::vector<LsvTask>& tasks) {
       double* V = c.scratch.get((size_t)tk.K * tk.K);
       qrs.push_back({tk.X, tk.ld, tk.M, tk.K, Q, tk.M, R, tk.K});
       tr.push_back({R, tk.K, Rt, tk.K, tk.K, tk.K, 1.0, 0.0, 1});
-      svs.push_back({Rt, tk.K, tk.K, tk.K, tk.sigma, nullptr, 0, V, tk.K});
+      svs.push_back({Rt, tk.K, tk.K, tk.K, tk.sigma, nullptr, 0, V, tk.K, tk.tol});
       back.push_back({Q, V, tk.U, tk.M, tk.K, tk.K, tk.M, tk.K, tk.M, 0, 0, 1.0, 0.0});
     }
   }
@@ -737,7 +743,8 @@ void build_h2_multi(std::vector<BuildJob>& jobs, Ctx& c) {
           g.push_back({s->Z + s->zoff[p], s->Qe + s->qoff[p], Rt, cp, s->kq[p], m2, m2, m2, cp, 1, 0,
                        1.0, 0.0});
           // left singular vectors of R = right singular vectors of R^T
-          svs.push_back({Rt, cp, cp, s->kq[p], s->sig_all + s->soff[p], nullptr, 0, s->Vp[p], s->kq[p]});
+          svs.push_back({Rt, cp, cp, s->kq[p], s->sig_all + s->soff[p], nullptr, 0, s->Vp[p], s->kq[p],
+                         svd_tol(*s->prm)});
         }
       }
       gemm_batched(c, g);
@@ -846,7 +853,7 @@ void build_h2_multi(std::vector<BuildJob>& jobs, Ctx& c) {
             rtc.push_back({RB, kk, RBt, kk, kk, kk, 1.0, 0.0, 1});
             s->Ub[p] = c.scratch.get((size_t)kk * kk);
             s->Vb[p] = c.scratch.get((size_t)kk * kk);
-            svs.push_back({RBt, kk, kk, kk, s->sb[p], s->Ub[p], kk, s->Vb[p], kk});
+            svs.push_back({RBt, kk, kk, kk, s->sb[p], s->Ub[p], kk, s->Vb[p], kk, svd_tol(*s->prm)});
             continue;
           }
           const bool tall = m1 >= kk;
@@ -857,7 +864,7 @@ void build_h2_multi(std::vector<BuildJob>& jobs, Ctx& c) {
           b0c.push_back({s->y + s->pr[p].a1, n, X, mm, mm, nn, 1.0, 0.0, tall ? 0 : 1});
           s->Ub[p] = c.scratch.get((size_t)mm * nn);
           s->Vb[p] = c.scratch.get((size_t)nn * nn);
-          svs.push_back({X, mm, mm, nn, s->sb[p], s->Ub[p], mm, s->Vb[p], nn});
+          svs.push_back({X, mm, mm, nn, s->sb[p], s->Ub[p], mm, s->Vb[p], nn, svd_tol(*s->prm)});
         }
       }
       copy_batched(c, b0c);
@@ -1111,7 +1118,7 @@ void build_h2_multi(std::vector<BuildJob>& jobs, Ctx& c) {
           col += k;
         }
         u.Us[i] = c.scratch.get((size_t)M * std::min(M, K));
-        tasks.push_back({G, M, M, K, u.Us[i], u.sg_all + u.goff[i]});
+        tasks.push_back({G, M, M, K, u.Us[i], u.sg_all + u.goff[i], svd_tol(*s.prm)});
       }
       ups.push_back(std::move(u));
     }

@@ -67,6 +67,11 @@ struct SVDDesc {
   int ldu;
   double* V;
   int ldv;
+  // Jacobi tolerance: columns count as orthogonal once |a.b| <= tol |a| |b|;
+  // 0 (or anything below it): the rounding level of an m-term FP64 dot
+  // product.  Input known only to a lower precision (FP32 samples) needs no
+  // sweeps that orthogonalise below that precision.
+  double tol = 0.0;
 };
 
 // dst (rows x cols) = alpha * src (+ beta * dst), column-major blocks

@@ -445,7 +445,7 @@ __device__ inline double jacobi_tol(int m) { return fmax(1e-15, (double)m * 0x1p
 
 // rotate columns a < b of A (and V) by one wave; returns true if rotated
 __device__ inline bool jacobi_rotate(double* A, int lda, int m, double* V, int ldv, int n, int a,
-                                     int b, int lane) {
+                                     int b, int lane, double tol) {
   double* ca = A + (size_t)a * lda;
   double* cb = A + (size_t)b * lda;
   double al = 0, be = 0, ga = 0;
@@ -460,7 +460,7 @@ __device__ inline bool jacobi_rotate(double* A, int lda, int m, double* V, int l
   al = sums[0];
   be = sums[1];
   ga = sums[2];
-  if (ga == 0.0 || !(fabs(ga) > jacobi_tol(m) * sqrt(al) * sqrt(be))) return false;
+  if (ga == 0.0 || !(fabs(ga) > tol * sqrt(al) * sqrt(be))) return false;
   const double zeta = (be - al) / (2.0 * ga);
   double t;
   if (fabs(zeta) > 1e150) t = 0.5 / zeta;
@@ -505,7 +505,9 @@ __global__ __launch_bounds__(512) void k_svd_sweeps(const SVDDesc* __restrict__ 
         int a, b;
         tournament_pair(np, r, k, a, b);
         if (b >= n) continue;
-        if (jacobi_rotate(d.A, d.lda, m, d.V, d.ldv, n, a, b, lane) && lane == 0) rotated = 1;
+        if (jacobi_rotate(d.A, d.lda, m, d.V, d.ldv, n, a, b, lane, fmax(d.tol, jacobi_tol(m))) &&
+            lane == 0)
+          rotated = 1;
       }
       __syncthreads();
     }
@@ -609,7 +611,7 @@ __global__ __launch_bounds__(512) void k_svd_block(const SVDDesc* __restrict__ d
   const int n = d.n, m = d.m;
   const int nb = (n + SVD_BS - 1) / SVD_BS;
   const int npb = nb + (nb & 1);
-  const double tol = jacobi_tol(m);
+  const double tol = fmax(d.tol, jacobi_tol(m));
   int* vb = ver + (size_t)mi * maxnb;
   for (int sweep = 0; sweep < 60; ++sweep) {
     int* fl = flags + (sweep % 3) * nmat;
