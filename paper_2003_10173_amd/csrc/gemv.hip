@@ -554,6 +554,93 @@ __device__ inline void blockrow_lds_pipe(int rows, int nsrc, const PipeSrc<T>* _
   }
 }
 
+// The same pipeline for BF16 storage with FP32 vectors: 16x16x16 BF16
+// products with FP32 accumulation (four consecutive k per lane and product),
+// A tiles row-major and B tiles column-major per vector (a lane's four k
+// contiguous), the vectors rounded to BF16 when stored to LDS; the products
+// and their order are those of blockrow_mfma's BF16 path.
+struct PipeSrcBF {
+  gptr_t<uint16_t> A;   // BF16 bits
+  gptr_t<float> B;
+  int K, ldb;
+};
+template <int NT> struct PipeTilesBF {
+  static constexpr int NC = 16 * NT, LD = 64 + 8;
+  static constexpr int RA = 16, RB = NC / 4;
+  uint16_t A[2][64 * LD];
+  uint16_t B[2][NC * LD];
+};
+
+template <int NT>
+__device__ inline void blockrow_lds_pipe_bf(int rows, int nsrc, const PipeSrcBF* __restrict__ ps,
+                                            int nvc, mf_f4 (&acc)[NT], PipeTilesBF<NT>& tl) {
+  using P = PipeTilesBF<NT>;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  auto gload = [&](int q, uint16_t (&ra)[P::RA], float (&rb)[P::RB]) {
+    const PipeSrcBF S = ps[q < nsrc ? q : nsrc - 1];
+    const int kl = (S.K > 0 ? S.K : 1) - 1;
+    const int kc = lane < kl ? lane : kl;
+#pragma unroll
+    for (int j = 0; j < P::RA; ++j) {
+      const int r = 4 * j + wave;
+      ra[j] = S.A[(size_t)(r < rows ? r : rows - 1) * S.K + kc];
+    }
+#pragma unroll
+    for (int j = 0; j < P::RB; ++j) {
+      const int cb = 4 * j + wave;
+      rb[j] = S.B[(size_t)(cb < nvc ? cb : nvc - 1) * S.ldb + kc];
+    }
+  };
+  auto lstore = [&](int q, int buf, const uint16_t (&ra)[P::RA], const float (&rb)[P::RB]) {
+    const int K = q < nsrc ? ps[q].K : 0;
+#pragma unroll
+    for (int j = 0; j < P::RA; ++j) {
+      const int r = 4 * j + wave;
+      tl.A[buf][r * P::LD + lane] = (r < rows && lane < K) ? ra[j] : (uint16_t)0;
+    }
+#pragma unroll
+    for (int j = 0; j < P::RB; ++j) {
+      const int cb = 4 * j + wave;
+      tl.B[buf][cb * P::LD + lane] = (cb < nvc && lane < K) ? float_to_bf16(rb[j]).bits : (uint16_t)0;
+    }
+  };
+  auto mma = [&](int q, int buf) {
+    if (16 * wave >= rows || q >= nsrc) return;
+    const int KP = (ps[q].K + 15) & ~15;
+    const uint16_t* As = tl.A[buf] + (16 * wave + (lane & 15)) * P::LD + 4 * (lane >> 4);
+    const uint16_t* Bs = tl.B[buf] + (lane & 15) * P::LD + 4 * (lane >> 4);
+    mf_s4 a[4], b[NT][4];
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+      a[g] = *reinterpret_cast<const mf_s4*>(As + 16 * g);
+#pragma unroll
+      for (int ct = 0; ct < NT; ++ct) b[ct][g] = *reinterpret_cast<const mf_s4*>(Bs + 16 * ct * P::LD + 16 * g);
+    }
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+      if (16 * g >= KP) break;
+#pragma unroll
+      for (int ct = 0; ct < NT; ++ct)
+        acc[ct] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[g], b[ct][g], acc[ct], 0, 0, 0);
+    }
+  };
+  if (nsrc <= 0) return;
+  uint16_t ra0[P::RA], ra1[P::RA];
+  float rb0[P::RB], rb1[P::RB];
+  gload(0, ra0, rb0);
+  gload(1, ra1, rb1);
+  for (int q = 0; q < nsrc; q += 2) {
+    lstore(q, 0, ra0, rb0);
+    __syncthreads();
+    gload(q + 2, ra0, rb0);
+    mma(q, 0);
+    lstore(q + 1, 1, ra1, rb1);
+    __syncthreads();
+    gload(q + 3, ra1, rb1);
+    mma(q + 1, 1);
+  }
+}
+
 // leaf stage in FP64 or FP32: y_t = alpha (U_t y^_t + sum_near D_ts x_s) + beta y_t
 template <class M, class V, int NT>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))) void k_leaf_direct(
@@ -563,14 +650,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))) voi
     const int32_t* __restrict__ near_ptr, const int32_t* __restrict__ near_col,
     const int64_t* __restrict__ Doff, const M* __restrict__ D, int nv, const V* __restrict__ yh,
     const V* __restrict__ x, int ldx, V alpha, V beta, V* __restrict__ y, int ldy) {
-  static_assert(std::is_same<M, V>::value &&
-                    (std::is_same<M, double>::value || std::is_same<M, float>::value),
-                "FP64 or FP32 storage and vectors");
-  using T = M;
-  using gp = gptr_t<T>;
+  constexpr bool BF = std::is_same<M, bf16_t>::value;
+  static_assert((std::is_same<M, V>::value &&
+                 (std::is_same<M, double>::value || std::is_same<M, float>::value)) ||
+                    (BF && std::is_same<V, float>::value),
+                "FP64 or FP32 storage and vectors, or BF16 storage with FP32 vectors");
+  using T = typename std::conditional<BF, float, M>::type;   // vector / accumulator type
+  using AT = typename std::conditional<BF, uint16_t, M>::type;
+  using Src = typename std::conditional<BF, PipeSrcBF, PipeSrc<T>>::type;
+  using Tiles = typename std::conditional<BF, PipeTilesBF<NT>, PipeTiles<T, NT>>::type;
   constexpr int NC = 16 * NT;
-  __shared__ PipeSrc<T> ps[PIPE_MAXSRC];
-  __shared__ PipeTiles<T, NT> tl;
+  __shared__ Src ps[PIPE_MAXSRC];
+  __shared__ Tiles tl;
   const int i = xcd_local(blockIdx.x, gridDim.x);
   const int leaf_base = (1 << L) - 1;
   const int c = leaf_base + i;
@@ -591,24 +682,25 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))) voi
     __syncthreads();
     if ((int)threadIdx.x < nb) {
       const int q = q0 + (int)threadIdx.x;
-      PipeSrc<T> d;
+      Src d;
       if (q < nnear) {
         const int g = g0 + q;
         const int sc = leaf_base + near_col[g];
-        d.A = (gp)(D + Doff[g]);
+        d.A = (gptr_t<AT>)(const AT*)(D + Doff[g]);
         d.K = csize[sc];
-        d.B = (gp)(x + (size_t)v0 * ldx + cstart[sc]);
+        d.B = (gptr_t<T>)(x + (size_t)v0 * ldx + cstart[sc]);
         d.ldb = ldx;
       } else {
-        d.A = (gp)(U + Uoff[i]);
+        d.A = (gptr_t<AT>)(const AT*)(U + Uoff[i]);
         d.K = k;
-        d.B = (gp)(yh + kpre[c] * nv + (size_t)v0 * k);
+        d.B = (gptr_t<T>)(yh + kpre[c] * nv + (size_t)v0 * k);
         d.ldb = k;
       }
       ps[threadIdx.x] = d;
     }
     __syncthreads();
-    blockrow_lds_pipe<T, NT>(m, nb, ps, nvc, acc, tl);
+    if constexpr (BF) blockrow_lds_pipe_bf<NT>(m, nb, ps, nvc, acc, tl);
+    else blockrow_lds_pipe<T, NT>(m, nb, ps, nvc, acc, tl);
   }
   if (16 * wave >= m) return;
 #pragma unroll
@@ -819,10 +911,10 @@ static void leaf_nt(const h2_matrix* A, int nv, V alpha, const V* xt, int ldx, V
                     int ldy, const V* yh, hipStream_t s) {
   const h2_tree* t = A->tree;
   const unsigned gy = (unsigned)((nv + 16 * NT - 1) / (16 * NT));
-  // FP64 and FP32: the LDS-pipelined kernel; BF16 (16x16x16 products): the
-  // block-row routine
-  if constexpr (std::is_same<M, V>::value &&
-                (std::is_same<M, double>::value || std::is_same<M, float>::value))
+  // the LDS-pipelined kernel (FP64, FP32, and BF16 storage with FP32 vectors)
+  if constexpr ((std::is_same<M, V>::value &&
+                 (std::is_same<M, double>::value || std::is_same<M, float>::value)) ||
+                (std::is_same<M, bf16_t>::value && std::is_same<V, float>::value))
     k_leaf_direct<M, V, NT><<<dim3(1 << t->L, gy), 256, 0, s>>>(
         t->L, t->d_cstart.as<int32_t>(), t->d_csize.as<int32_t>(), A->d_rank.as<int32_t>(),
         A->d_kpre.as<int64_t>(), A->d_U_off.as<int64_t>(), A->st.U.as<M>(),
