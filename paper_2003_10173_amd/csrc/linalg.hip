@@ -1063,12 +1063,14 @@ void svd_batched(Ctx& c, const std::vector<SVDDesc>& ds) {
 }
 
 // ------------------------------------------------------------------ TSQR
-// Tall-skinny Householder QR (n <= 96 columns): row chunks of at most 192
-// rows are factorised by one workgroup each, groups of up to 192 / n of the R
+// Tall-skinny Householder QR (n <= 96 columns): row chunks of at most 320
+// rows are factorised by one workgroup each, groups of up to 320 / n of the R
 // factors are stacked and factorised again up the tree, and the explicit Q is
 // formed top-down by batched GEMMs (Q = diag(Q_chunks) * ... * Q_root).
-// Backward stable for any rank, like a single Householder QR.
-constexpr int TS_W = 96, TS_ROWS = 192, TS_SRC = 8;
+// Backward stable for any rank, like a single Householder QR.  A node's time
+// is set by its column count (one reflector per barrier), not by its rows, so
+// nodes are as tall as the registers allow: fewer tree levels, fewer launches.
+constexpr int TS_W = 96, TS_ROWS = 320, TS_SRC = 8;
 
 struct TsqrNode {
   const double* src[TS_SRC];  // stacked row blocks, rs rows each
@@ -1081,19 +1083,21 @@ struct TsqrNode {
   int ldr;
 };
 
-// One node = Householder QR of a stacked (nsrc * rs) x w block, rows <= 192,
+// One node = Householder QR of a stacked (nsrc * rs) x w block, rows <= 64 RS,
 // w <= 96, held in registers: wave v owns columns v, v + 16, ... (at most 6),
-// lane l holds rows l, l + 64, l + 128.  Per column j the owner wave forms the
+// lane l holds rows l, l + 64, ..., l + 64 (RS - 1) (RS = 3 for nodes of at
+// most 192 rows, else 5).  Per column j the owner wave forms the
 // reflector and publishes it through LDS (double-buffered); after one barrier
 // every wave applies it to its own columns, the owner of the next column
 // first (see the factorisation loop).  The explicit Q (when requested) is
 // accumulated backwards the same way: Q = H_0 ... H_{w-1} [I; 0].
-constexpr int TS_WAVES = 16, TS_CPW = (TS_W + TS_WAVES - 1) / TS_WAVES, TS_RS = 3;
-static_assert(TS_RS * 64 >= TS_ROWS, "node rows must fit the lanes");
+constexpr int TS_WAVES = 16, TS_CPW = (TS_W + TS_WAVES - 1) / TS_WAVES, TS_RS_MAX = 5;
+static_assert(TS_RS_MAX * 64 >= TS_ROWS, "node rows must fit the lanes");
 
 // reflector of column j (rows held as col[r] = row r * 64 + lane): v below the
 // diagonal (v_j = 1) stays in col, beta goes on the diagonal; v and tau are
 // published to vb (rows) and tb (one value); returns tau
+template <int TS_RS>
 __device__ __forceinline__ double tsqr_reflect(double (&col)[TS_RS], int j, int lane, double* vb,
                                                double* tb) {
   double s = 0.0, alpha = 0.0;
@@ -1130,6 +1134,7 @@ __device__ __forceinline__ double tsqr_reflect(double (&col)[TS_RS], int j, int 
 }
 
 // explicit-Q set-up of column j: publish v_j and tau, column := e_j - tau v_j
+template <int TS_RS>
 __device__ __forceinline__ void tsqr_publish(double (&col)[TS_RS], double tau, int j, int lane, double* vb,
                                              double* tb) {
 #pragma unroll
@@ -1144,6 +1149,7 @@ __device__ __forceinline__ void tsqr_publish(double (&col)[TS_RS], double tau, i
   if (lane == 0) *tb = tau;
 }
 
+template <int TS_RS>
 __global__ __launch_bounds__(1024) void k_tsqr_node(const TsqrNode* __restrict__ nodes) {
   const TsqrNode& d = nodes[blockIdx.x];
   __shared__ double vbuf[2][TS_RS * 64];
@@ -1303,8 +1309,11 @@ static void launch_nodes(Ctx& c, const std::vector<TsqrNode>& v) {
                  nd.nsrc * nd.rs <= TS_ROWS && nd.nsrc * nd.rs >= nd.w, H2_EINVAL,
              "TSQR node shape out of range");
   auto* dd = (TsqrNode*)c.stage.put(v.data(), v.size() * sizeof(TsqrNode), c.s);
+  int rmax = 0;
+  for (auto& nd : v) rmax = std::max(rmax, nd.nsrc * nd.rs);
   VTimer vt(c.s);
-  k_tsqr_node<<<(unsigned)v.size(), 1024, 0, c.s>>>(dd);
+  if (rmax <= 192) k_tsqr_node<3><<<(unsigned)v.size(), 1024, 0, c.s>>>(dd);
+  else k_tsqr_node<TS_RS_MAX><<<(unsigned)v.size(), 1024, 0, c.s>>>(dd);
   H2_LAUNCH_CHECK();
   if (vt.on()) {
     int w = 0, rows = 0, q = 0;

@@ -172,7 +172,8 @@ def cholqr(A, mode):
 
 
 @pytest.mark.parametrize("m,n,rank,blocked", [(2048, 74, 74, 0), (900, 42, 10, 0), (500, 96, 96, 0),
-                                              (300, 20, 20, 0), (97, 96, 50, 0),
+                                              (300, 20, 20, 0), (97, 96, 50, 0), (3000, 40, 40, 0),
+                                              (1281, 64, 30, 0), (320, 96, 96, 0),
                                               (2048, 600, 600, 1), (1500, 300, 120, 1),
                                               (700, 130, 130, 1)])
 def test_tall_qr_orthonormal_and_backward_stable(m, n, rank, blocked):
