@@ -1,6 +1,7 @@
 // Batched FP64 dense kernels for the construction (Sec. 3.3: sampling by
 // batched products, compression by batched QR and SVD).  One launch covers
-// every block of a level; descriptors travel through a pinned staging ring.
+// every block of a level; descriptors travel in the kernel arguments (small
+// batches) or through a pinned staging ring.
 //
 // The GEMM is a 64x64-tile FP64 FMA kernel (FP64 vector and matrix peaks are
 // equal on CDNA4, so the vector path loses nothing for FP64); tall reductions
@@ -79,6 +80,36 @@ void Scratch::clear() {
   used = 0;
 }
 
+// ------------------------------------------------------------------ descriptor transport
+// The descriptor array of a launch travels in its kernel arguments when it is
+// small: it is then part of the launch packet, with no copy of its own on the
+// stream.  Larger arrays go through the staging ring.  Kernels index both
+// forms alike.
+template <class T>
+struct DevArr {
+  const T* p;
+  __device__ const T& operator[](int64_t i) const { return p[i]; }
+};
+template <class T, int N>
+struct ArgArr {
+  T v[N];
+  __device__ const T& operator[](int64_t i) const { return v[i]; }
+};
+constexpr size_t KARG_MAX = 3072;  // bytes of descriptors per launch's arguments
+
+// launch(arr) with the n descriptors at v as an ArgArr<T, N> (n <= N) or a DevArr<T>
+template <int N, class T, class F>
+void with_descs(Ctx& c, const T* v, size_t n, F&& launch) {
+  static_assert(sizeof(ArgArr<T, N>) <= KARG_MAX, "inline descriptors exceed the argument budget");
+  if (n <= (size_t)N) {
+    ArgArr<T, N> a{};
+    std::memcpy(a.v, v, n * sizeof(T));
+    launch(a);
+  } else {
+    launch(DevArr<T>{(const T*)c.stage.put(v, n * sizeof(T), c.s)});
+  }
+}
+
 // ------------------------------------------------------------------ GEMM
 constexpr int TM = 64, TN = 64, TK = 32, TQ = TM * TK / 256;
 
@@ -97,8 +128,8 @@ struct GemmTask {
 // are zeroed when stored), stored into one of two LDS tile buffers and
 // multiplied there on the matrix cores after a single barrier, so that the
 // loads of the next block overlap the products of this one.
-__global__ __launch_bounds__(256) void k_gemm(const GemmTask* __restrict__ tasks,
-                                              const int64_t* __restrict__ tile_start, int ntasks) {
+template <class TA, class SA>
+__global__ __launch_bounds__(256) void k_gemm(TA tasks, SA tile_start, int ntasks) {
   __shared__ double As[2][TK][TM + 1];
   __shared__ double Bs[2][TK][TN + 1];
   // locate the task of this block
@@ -216,7 +247,8 @@ struct ReduceTask {
   int nparts;
 };
 
-__global__ void k_reduce_parts(const ReduceTask* __restrict__ tasks, int ntasks) {
+template <class RA>
+__global__ void k_reduce_parts(RA tasks, int ntasks) {
   const ReduceTask& t = tasks[blockIdx.y];
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= (int64_t)t.M * t.N) return;
@@ -226,6 +258,10 @@ __global__ void k_reduce_parts(const ReduceTask* __restrict__ tasks, int ntasks)
   double* o = t.C + (size_t)j * t.ldc + i;
   *o = t.beta == 0.0 ? s : s + t.beta * *o;
 }
+
+constexpr int GEMM_ARG_TASKS = 20;
+static_assert(sizeof(ArgArr<GemmTask, GEMM_ARG_TASKS>) + sizeof(ArgArr<int64_t, GEMM_ARG_TASKS + 1>) <= KARG_MAX,
+              "GEMM tasks exceed the argument budget");
 
 void gemm_batched(Ctx& c, const std::vector<GemmDesc>& ds) {
   std::vector<GemmTask> tasks;
@@ -266,25 +302,35 @@ void gemm_batched(Ctx& c, const std::vector<GemmDesc>& ds) {
   for (size_t i = 0; i < tasks.size(); ++i)
     start[i + 1] = start[i] + (int64_t)tasks[i].tiles_m * tasks[i].tiles_n;
   H2_CHECK(start.back() < (int64_t)1 << 31, H2_EINVAL, "GEMM batch too large");
-  // tasks, tile offsets and reductions in one upload
-  const size_t bt = tasks.size() * sizeof(GemmTask), bs = start.size() * sizeof(int64_t);
-  const size_t ot = 0, os = (bt + 15) & ~(size_t)15, orr = (os + bs + 15) & ~(size_t)15;
-  std::vector<char> blob(orr + reds.size() * sizeof(ReduceTask));
-  std::memcpy(blob.data() + ot, tasks.data(), bt);
-  std::memcpy(blob.data() + os, start.data(), bs);
-  if (!reds.empty()) std::memcpy(blob.data() + orr, reds.data(), reds.size() * sizeof(ReduceTask));
-  char* dblob = (char*)c.stage.put(blob.data(), blob.size(), c.s);
-  k_gemm<<<(unsigned)start.back(), 256, 0, c.s>>>((const GemmTask*)(dblob + ot), (const int64_t*)(dblob + os),
-                                                   (int)tasks.size());
+  const unsigned nblk = (unsigned)start.back();
+  if (tasks.size() <= GEMM_ARG_TASKS) {
+    // tasks and tile offsets in the kernel arguments
+    ArgArr<GemmTask, GEMM_ARG_TASKS> ta{};
+    ArgArr<int64_t, GEMM_ARG_TASKS + 1> sa{};
+    std::memcpy(ta.v, tasks.data(), tasks.size() * sizeof(GemmTask));
+    std::memcpy(sa.v, start.data(), start.size() * sizeof(int64_t));
+    k_gemm<<<nblk, 256, 0, c.s>>>(ta, sa, (int)tasks.size());
+  } else {
+    // tasks and tile offsets in one upload
+    const size_t bt = tasks.size() * sizeof(GemmTask), bs = start.size() * sizeof(int64_t);
+    const size_t os = (bt + 15) & ~(size_t)15;
+    std::vector<char> blob(os + bs);
+    std::memcpy(blob.data(), tasks.data(), bt);
+    std::memcpy(blob.data() + os, start.data(), bs);
+    char* dblob = (char*)c.stage.put(blob.data(), blob.size(), c.s);
+    k_gemm<<<nblk, 256, 0, c.s>>>(DevArr<GemmTask>{(const GemmTask*)dblob},
+                                  DevArr<int64_t>{(const int64_t*)(dblob + os)}, (int)tasks.size());
+  }
   H2_LAUNCH_CHECK();
   if (!reds.empty()) {
     int64_t mx = 0;
     for (auto& r : reds) mx = std::max(mx, (int64_t)r.M * r.N);
-    const ReduceTask* dr = (const ReduceTask*)(dblob + orr);
     for (size_t i0 = 0; i0 < reds.size(); i0 += 65535) {
       const size_t cnt = std::min<size_t>(65535, reds.size() - i0);
       dim3 grid((unsigned)((mx + 255) / 256), (unsigned)cnt);
-      k_reduce_parts<<<grid, 256, 0, c.s>>>(dr + i0, (int)cnt);
+      with_descs<32>(c, reds.data() + i0, cnt, [&](auto ra) {
+        k_reduce_parts<<<grid, 256, 0, c.s>>>(ra, (int)cnt);
+      });
       H2_LAUNCH_CHECK();
     }
   }
@@ -1149,8 +1195,8 @@ __device__ __forceinline__ void tsqr_publish(double (&col)[TS_RS], double tau, i
   if (lane == 0) *tb = tau;
 }
 
-template <int TS_RS>
-__global__ __launch_bounds__(1024) void k_tsqr_node(const TsqrNode* __restrict__ nodes) {
+template <int TS_RS, class NA>
+__global__ __launch_bounds__(1024) void k_tsqr_node(NA nodes) {
   const TsqrNode& d = nodes[blockIdx.x];
   __shared__ double vbuf[2][TS_RS * 64];
   __shared__ double tbuf[2];
@@ -1308,12 +1354,13 @@ static void launch_nodes(Ctx& c, const std::vector<TsqrNode>& v) {
     H2_CHECK(nd.w <= TS_W && nd.nsrc >= 1 && nd.nsrc <= TS_SRC && nd.rs >= 1 &&
                  nd.nsrc * nd.rs <= TS_ROWS && nd.nsrc * nd.rs >= nd.w, H2_EINVAL,
              "TSQR node shape out of range");
-  auto* dd = (TsqrNode*)c.stage.put(v.data(), v.size() * sizeof(TsqrNode), c.s);
   int rmax = 0;
   for (auto& nd : v) rmax = std::max(rmax, nd.nsrc * nd.rs);
   VTimer vt(c.s);
-  if (rmax <= 192) k_tsqr_node<3><<<(unsigned)v.size(), 1024, 0, c.s>>>(dd);
-  else k_tsqr_node<TS_RS_MAX><<<(unsigned)v.size(), 1024, 0, c.s>>>(dd);
+  with_descs<16>(c, v.data(), v.size(), [&](auto nodes) {
+    if (rmax <= 192) k_tsqr_node<3><<<(unsigned)v.size(), 1024, 0, c.s>>>(nodes);
+    else k_tsqr_node<TS_RS_MAX><<<(unsigned)v.size(), 1024, 0, c.s>>>(nodes);
+  });
   H2_LAUNCH_CHECK();
   if (vt.on()) {
     int w = 0, rows = 0, q = 0;
@@ -1336,6 +1383,7 @@ void qr_tall_batched(Ctx& c, const std::vector<QRDesc>& ds) {
     std::vector<int> chunk_rows;               // level 0
     std::vector<std::vector<double*>> Qs, Rs;
     std::vector<std::vector<int>> nchild;      // children per node (1: R passed through)
+    bool r_direct = false;                     // the root wrote R into the output
   };
   std::vector<Mat> mats;
   for (auto& d : ds) {
@@ -1360,10 +1408,14 @@ void qr_tall_batched(Ctx& c, const std::vector<QRDesc>& ds) {
       M.Qs.push_back({});
       M.Rs.push_back({});
       M.nchild.push_back(std::vector<int>(M.chunk_rows.size(), 0));
+      // a matrix of one chunk is factorised by that node alone, which writes
+      // the outputs directly (a node reads all of its rows before it writes)
+      const bool single = M.chunk_rows.size() == 1;
+      M.r_direct = single && M.d.R != nullptr;
       int r0 = 0;
       for (int rows : M.chunk_rows) {
-        double* Q = M.d.Q ? c.scratch.get((size_t)rows * w) : nullptr;
-        double* R = c.scratch.get((size_t)w * w);
+        double* Q = M.d.Q ? (single ? M.d.Q : c.scratch.get((size_t)rows * w)) : nullptr;
+        double* R = M.r_direct ? M.d.R : c.scratch.get((size_t)w * w);
         M.Qs[0].push_back(Q);
         M.Rs[0].push_back(R);
         TsqrNode nd{};
@@ -1373,9 +1425,9 @@ void qr_tall_batched(Ctx& c, const std::vector<QRDesc>& ds) {
         nd.rs = rows;
         nd.w = w;
         nd.Q = Q;
-        nd.ldq = rows;
+        nd.ldq = single ? M.d.ldq : rows;
         nd.R = R;
-        nd.ldr = w;
+        nd.ldr = M.r_direct ? M.d.ldr : w;
         nodes.push_back(nd);
         r0 += rows;
       }
@@ -1405,8 +1457,11 @@ void qr_tall_batched(Ctx& c, const std::vector<QRDesc>& ds) {
           M.Rs[lev].push_back(prevR[k0]);
           continue;
         }
+        // the root (one node at this level) writes R into the output
+        const bool root = cnt == 1 && M.d.R != nullptr;
         double* Q = M.d.Q ? c.scratch.get((size_t)k * w * w) : nullptr;
-        double* R = c.scratch.get((size_t)w * w);
+        double* R = root ? M.d.R : c.scratch.get((size_t)w * w);
+        M.r_direct = M.r_direct || root;
         M.Qs[lev].push_back(Q);
         M.Rs[lev].push_back(R);
         TsqrNode nd{};
@@ -1420,41 +1475,34 @@ void qr_tall_batched(Ctx& c, const std::vector<QRDesc>& ds) {
         nd.Q = Q;
         nd.ldq = k * w;
         nd.R = R;
-        nd.ldr = w;
+        nd.ldr = root ? M.d.ldr : w;
         nodes.push_back(nd);
       }
     }
     if (!any) break;
     launch_nodes(c, nodes);
   }
-  // R of the whole matrix
+  // R of the whole matrix (where the root did not write it)
   {
     std::vector<CopyDesc> cp;
     for (auto& M : mats)
-      if (M.d.R) cp.push_back({M.Rs.back()[0], M.d.n, M.d.R, M.d.ldr, M.d.n, M.d.n, 1.0, 0.0, 0});
+      if (M.d.R && !M.r_direct) cp.push_back({M.Rs.back()[0], M.d.n, M.d.R, M.d.ldr, M.d.n, M.d.n, 1.0, 0.0, 0});
     copy_batched(c, cp);
   }
-  // downward: X (w x w) per node, starting from the identity at the root
-  mats.erase(std::remove_if(mats.begin(), mats.end(), [](const Mat& M) { return M.d.Q == nullptr; }),
+  // downward: X (w x w) per node; the root's children take their rows of the
+  // root's Q (X = I at the root).  Matrices of one chunk are complete.
+  mats.erase(std::remove_if(mats.begin(), mats.end(),
+                            [](const Mat& M) { return M.d.Q == nullptr || M.chunk_rows.size() == 1; }),
              mats.end());
   if (mats.empty()) return;
   int maxlev = 0;
   for (auto& M : mats) maxlev = std::max(maxlev, (int)M.Rs.size() - 1);
   std::vector<std::vector<std::vector<const double*>>> X(mats.size());
   std::vector<std::vector<std::vector<int>>> ldx(mats.size());
-  // identities of every matrix's root, one upload
-  int wmax = 0;
-  for (auto& M : mats) wmax = std::max(wmax, M.d.n);
-  std::vector<double> eye((size_t)wmax * wmax, 0.0);
-  for (int i = 0; i < wmax; ++i) eye[(size_t)i * wmax + i] = 1.0;
-  const double* deye = (const double*)c.stage.put(eye.data(), eye.size() * sizeof(double), c.s);
   for (size_t mi = 0; mi < mats.size(); ++mi) {
-    auto& M = mats[mi];
-    const int top = (int)M.Rs.size() - 1;
+    const int top = (int)mats[mi].Rs.size() - 1;
     X[mi].assign(top + 1, {});
     ldx[mi].assign(top + 1, {});
-    X[mi][top] = {deye};
-    ldx[mi][top] = {wmax};
   }
   for (int lev = maxlev; lev >= 1; --lev) {
     std::vector<GemmDesc> g;
@@ -1470,6 +1518,13 @@ void qr_tall_batched(Ctx& c, const std::vector<QRDesc>& ds) {
         if (k == 1) {  // R passed through: the child keeps this X
           X[mi][lev - 1][k0] = X[mi][lev][i];
           ldx[mi][lev - 1][k0] = ldx[mi][lev][i];
+          continue;
+        }
+        if (lev == top) {  // the root: Q_root I = Q_root
+          for (int j = 0; j < k; ++j) {
+            X[mi][lev - 1][k0 + j] = M.Qs[lev][i] + (size_t)j * w;
+            ldx[mi][lev - 1][k0 + j] = k * w;
+          }
           continue;
         }
         double* Y = c.scratch.get((size_t)k * w * w);
@@ -1643,7 +1698,8 @@ void qr_auto(Ctx& c, const std::vector<QRDesc>& ds) {
 }
 
 // ------------------------------------------------------------------ copies, norms
-__global__ void k_copy(const CopyDesc* __restrict__ ds) {
+template <class CA>
+__global__ void k_copy(CA ds) {
   const CopyDesc d = ds[blockIdx.y];
   const int64_t tot = (int64_t)d.rows * d.cols;
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < tot;
@@ -1667,15 +1723,14 @@ void copy_batched(Ctx& c, const std::vector<CopyDesc>& ds) {
   // one grid row per descriptor: launches of at most 65535 descriptors
   for (size_t i0 = 0; i0 < v.size(); i0 += 65535) {
     const size_t cnt = std::min<size_t>(65535, v.size() - i0);
-    auto* dd = (CopyDesc*)c.stage.put(v.data() + i0, cnt * sizeof(CopyDesc), c.s);
     dim3 grid((unsigned)std::min<int64_t>((mx + 255) / 256, 1024), (unsigned)cnt);
-    k_copy<<<grid, 256, 0, c.s>>>(dd);
+    with_descs<40>(c, v.data() + i0, cnt, [&](auto dd) { k_copy<<<grid, 256, 0, c.s>>>(dd); });
     H2_LAUNCH_CHECK();
   }
 }
 
-__global__ __launch_bounds__(256) void k_colnorm_max(const CopyDesc* __restrict__ ds,
-                                                     double* __restrict__ out) {
+template <class CA>
+__global__ __launch_bounds__(256) void k_colnorm_max(CA ds, double* __restrict__ out) {
   const CopyDesc d = ds[blockIdx.x];
   __shared__ double red[4];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -1703,8 +1758,8 @@ __global__ __launch_bounds__(256) void k_colnorm_max(const CopyDesc* __restrict_
 // a Gaussian vector of about unit norm (keyed by the block's key, row and
 // column), so that the projection and QR that follow give a direction
 // orthogonal to the span.  One wave per column.
-__global__ __launch_bounds__(256) void k_replace_lost_columns(const CopyDesc* __restrict__ ds,
-                                                              const uint64_t* __restrict__ keys) {
+template <class CA, class KA>
+__global__ __launch_bounds__(256) void k_replace_lost_columns(CA ds, KA keys) {
   const CopyDesc d = ds[blockIdx.x];
   const uint64_t key = keys[blockIdx.x];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -1729,18 +1784,22 @@ void replace_lost_columns(Ctx& c, const std::vector<CopyDesc>& blocks,
                           const std::vector<uint64_t>& keys) {
   if (blocks.empty()) return;
   H2_CHECK(blocks.size() == keys.size(), H2_EINVAL, "one key per block");
-  auto* dd = (CopyDesc*)c.stage.put(blocks.data(), blocks.size() * sizeof(CopyDesc), c.s);
-  auto* dk = (uint64_t*)c.stage.put(keys.data(), keys.size() * sizeof(uint64_t), c.s);
   int mc = 1;
   for (auto& b : blocks) mc = std::max(mc, b.cols);
-  k_replace_lost_columns<<<dim3((unsigned)blocks.size(), (unsigned)((mc + 3) / 4)), 256, 0, c.s>>>(dd, dk);
+  const dim3 grid((unsigned)blocks.size(), (unsigned)((mc + 3) / 4));
+  with_descs<32>(c, blocks.data(), blocks.size(), [&](auto dd) {
+    with_descs<32>(c, keys.data(), keys.size(), [&](auto dk) {
+      k_replace_lost_columns<<<grid, 256, 0, c.s>>>(dd, dk);
+    });
+  });
   H2_LAUNCH_CHECK();
 }
 
 void colnorm_max_batched(Ctx& c, const std::vector<CopyDesc>& blocks, double* out) {
   if (blocks.empty()) return;
-  auto* dd = (CopyDesc*)c.stage.put(blocks.data(), blocks.size() * sizeof(CopyDesc), c.s);
-  k_colnorm_max<<<(unsigned)blocks.size(), 256, 0, c.s>>>(dd, out);
+  with_descs<40>(c, blocks.data(), blocks.size(), [&](auto dd) {
+    k_colnorm_max<<<(unsigned)blocks.size(), 256, 0, c.s>>>(dd, out);
+  });
   H2_LAUNCH_CHECK();
 }
 
