@@ -646,6 +646,7 @@ void build_h2_multi(std::vector<BuildJob>& jobs, Ctx& c) {
         std::vector<uint64_t> lost_keys;
         std::vector<QRDesc> q1, q2, q3, t1, t2, t3;
         std::vector<GemmDesc> g1, g2, g3, g4;
+        std::vector<size_t> t3_flag;   // lost-column flag of each t3 block
         for (JobState* s : sj) {
           const int bw = s->r == 0 ? s->b0 : s->b;
           for (int p : s->act) {
@@ -670,15 +671,23 @@ void build_h2_multi(std::vector<BuildJob>& jobs, Ctx& c) {
               // a round that adds fewer directions than columns (exactly
               // low-rank blocks) leaves columns of Qn2 dependent on Qe or on
               // each other (small R2_jj): they become Gaussian, are projected
-              // once more and the block is orthonormalised again
+              // once more and the block is orthonormalised again.  Blocks
+              // with no such column skip these steps on the device (their
+              // flag stays 0): the tall QR then runs in place on Qn2.
+              const size_t fi = lost.size();
               lost.push_back({Qn2, m2, R2, kn, m2, kn, 1.0, 0.0, 0});
               lost_keys.push_back(stream_key(s->prm->seed, PHASE_LOST, (uint32_t)l,
                                              (uint32_t)(s->r * 4096 + p), s->prm->iteration));
               double* Wr = c.scratch.get((size_t)q * kn);
               g3.push_back({s->Qe + s->qoff[p], Qn2, Wr, q, kn, m2, m2, m2, q, 1, 0, 1.0, 0.0});
               g4.push_back({s->Qe + s->qoff[p], Wr, Qn2, m2, kn, q, m2, q, m2, 0, 0, -1.0, 1.0});
-              double* Qn3 = c.scratch.get((size_t)m2 * kn);
-              (tall ? t3 : q3).push_back({Qn2, m2, m2, kn, Qn3, m2, nullptr, 0});
+              double* Qn3 = tall ? Qn2 : c.scratch.get((size_t)m2 * kn);
+              if (tall) {
+                t3.push_back({Qn2, m2, m2, kn, Qn3, m2, nullptr, 0});
+                t3_flag.push_back(fi);
+              } else {
+                q3.push_back({Qn2, m2, m2, kn, Qn3, m2, nullptr, 0});
+              }
               put.push_back({Qn3, m2, s->Qe + s->qoff[p] + (size_t)q * m2, m2, m2, take, 1.0, 0.0, 0});
             } else {
               put.push_back({Qn, m2, s->Qe + s->qoff[p], m2, m2, take, 1.0, 0.0, 0});
@@ -693,7 +702,18 @@ void build_h2_multi(std::vector<BuildJob>& jobs, Ctx& c) {
         gemm_batched(c, g2);
         qr_auto(c, q2);
         qr_tall_batched(c, t2);
-        replace_lost_columns(c, lost, lost_keys);
+        int* flags = nullptr;
+        if (!lost.empty()) {
+          const int nd = (int)((lost.size() + 1) / 2);
+          flags = (int*)c.scratch.get((size_t)nd);
+          zero_block(c, (double*)flags, nd, 1, nd);
+          for (size_t i = 0; i < lost.size(); ++i) {
+            g3[i].run = flags + i;
+            g4[i].run = flags + i;
+          }
+          for (size_t i = 0; i < t3.size(); ++i) t3[i].run = flags + t3_flag[i];
+        }
+        replace_lost_columns(c, lost, lost_keys, flags);
         gemm_batched(c, g3);
         gemm_batched(c, g4);
         qr_auto(c, q3);

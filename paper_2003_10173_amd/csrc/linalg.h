@@ -43,6 +43,7 @@ struct GemmDesc {
   int lda, ldb, ldc;
   int ta, tb;
   double alpha, beta;
+  const int* run = nullptr;  // optional device flag: the product is skipped when *run == 0
 };
 
 // In-place Householder QR of A (m x n): R (min(m,n) x n, upper) to R, explicit
@@ -54,6 +55,7 @@ struct QRDesc {
   int ldq;
   double* R;
   int ldr;
+  const int* run = nullptr;  // optional device flag, TSQR only: skipped when *run == 0
 };
 
 // One-sided Jacobi SVD of A (m x n, m >= n, destroyed): sigma descending (n),
@@ -135,9 +137,10 @@ void qr_auto(Ctx& c, const std::vector<QRDesc>& d);
 // lie in a span projected out become Gaussian vectors of about unit norm,
 // keyed by keys[i], row and column: with dst == nullptr the columns of norm
 // below 1/2; with dst/ldd the R of a QR whose Q the block is, the columns
-// whose |R_jj| is below 1/2
+// whose |R_jj| is below 1/2.  With flags (device, one int per block, zeroed
+// by the caller), flags[i] becomes 1 when block i had a lost column.
 void replace_lost_columns(Ctx& c, const std::vector<CopyDesc>& blocks,
-                          const std::vector<uint64_t>& keys);
+                          const std::vector<uint64_t>& keys, int* flags = nullptr);
 // out[i] = max_j || X_i[:, j] || for blocks X_i (rows_i x cols_i, ld_i)
 void colnorm_max_batched(Ctx& c, const std::vector<CopyDesc>& blocks, double* out);
 // zero a column-major block

@@ -141,6 +141,7 @@ __global__ __launch_bounds__(256) void k_gemm(TA tasks, SA tile_start, int ntask
   }
   const GemmTask& t = tasks[lo];
   const GemmDesc& d = t.d;
+  if (d.run && *d.run == 0) return;
   const int tile = (int)(b - tile_start[lo]);
   const int bm = (tile % t.tiles_m) * TM, bn = (tile / t.tiles_m) * TN;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -245,11 +246,13 @@ struct ReduceTask {
   double beta;
   const double* parts;  // nparts consecutive M x N blocks (ld = M)
   int nparts;
+  const int* run;       // optional: skipped when *run == 0
 };
 
 template <class RA>
 __global__ void k_reduce_parts(RA tasks, int ntasks) {
   const ReduceTask& t = tasks[blockIdx.y];
+  if (t.run && *t.run == 0) return;
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= (int64_t)t.M * t.N) return;
   const int i = (int)(e % t.M), j = (int)(e / t.M);
@@ -294,7 +297,7 @@ void gemm_batched(Ctx& c, const std::vector<GemmDesc>& ds) {
         tasks.push_back(GemmTask{d, tm, tn, k0, k1, parts + (size_t)p * d.M * d.N, d.M, 0.0});
         ++used;
       }
-      reds.push_back(ReduceTask{d.C, d.ldc, d.M, d.N, d.beta, parts, used});
+      reds.push_back(ReduceTask{d.C, d.ldc, d.M, d.N, d.beta, parts, used, d.run});
     }
   }
   if (tasks.empty()) return;
@@ -1127,6 +1130,7 @@ struct TsqrNode {
   int ldq;
   double* R;          // w x w, zero below the diagonal
   int ldr;
+  const int* run;     // optional: the node does nothing when *run == 0
 };
 
 // One node = Householder QR of a stacked (nsrc * rs) x w block, rows <= 64 RS,
@@ -1198,6 +1202,7 @@ __device__ __forceinline__ void tsqr_publish(double (&col)[TS_RS], double tau, i
 template <int TS_RS, class NA>
 __global__ __launch_bounds__(1024) void k_tsqr_node(NA nodes) {
   const TsqrNode& d = nodes[blockIdx.x];
+  if (d.run && *d.run == 0) return;
   __shared__ double vbuf[2][TS_RS * 64];
   __shared__ double tbuf[2];
   __shared__ const double* rowp[TS_RS * 64];   // start of row i in its source
@@ -1428,6 +1433,7 @@ void qr_tall_batched(Ctx& c, const std::vector<QRDesc>& ds) {
         nd.ldq = single ? M.d.ldq : rows;
         nd.R = R;
         nd.ldr = M.r_direct ? M.d.ldr : w;
+        nd.run = M.d.run;
         nodes.push_back(nd);
         r0 += rows;
       }
@@ -1476,19 +1482,14 @@ void qr_tall_batched(Ctx& c, const std::vector<QRDesc>& ds) {
         nd.ldq = k * w;
         nd.R = R;
         nd.ldr = root ? M.d.ldr : w;
+        nd.run = M.d.run;
         nodes.push_back(nd);
       }
     }
     if (!any) break;
     launch_nodes(c, nodes);
   }
-  // R of the whole matrix (where the root did not write it)
-  {
-    std::vector<CopyDesc> cp;
-    for (auto& M : mats)
-      if (M.d.R && !M.r_direct) cp.push_back({M.Rs.back()[0], M.d.n, M.d.R, M.d.ldr, M.d.n, M.d.n, 1.0, 0.0, 0});
-    copy_batched(c, cp);
-  }
+  // (R: written by the root, or by the chunk's node for a matrix of one chunk)
   // downward: X (w x w) per node; the root's children take their rows of the
   // root's Q (X = I at the root).  Matrices of one chunk are complete.
   mats.erase(std::remove_if(mats.begin(), mats.end(),
@@ -1528,7 +1529,8 @@ void qr_tall_batched(Ctx& c, const std::vector<QRDesc>& ds) {
           continue;
         }
         double* Y = c.scratch.get((size_t)k * w * w);
-        g.push_back({M.Qs[lev][i], X[mi][lev][i], Y, k * w, w, w, k * w, ldx[mi][lev][i], k * w, 0, 0, 1.0, 0.0});
+        g.push_back({M.Qs[lev][i], X[mi][lev][i], Y, k * w, w, w, k * w, ldx[mi][lev][i], k * w, 0, 0, 1.0, 0.0,
+                     M.d.run});
         for (int j = 0; j < k; ++j) {
           X[mi][lev - 1][k0 + j] = Y + (size_t)j * w;
           ldx[mi][lev - 1][k0 + j] = k * w;
@@ -1545,7 +1547,8 @@ void qr_tall_batched(Ctx& c, const std::vector<QRDesc>& ds) {
     int r0 = 0;
     for (size_t i = 0; i < M.chunk_rows.size(); ++i) {
       const int rows = M.chunk_rows[i];
-      g.push_back({M.Qs[0][i], X[mi][0][i], M.d.Q + r0, rows, w, w, rows, ldx[mi][0][i], M.d.ldq, 0, 0, 1.0, 0.0});
+      g.push_back({M.Qs[0][i], X[mi][0][i], M.d.Q + r0, rows, w, w, rows, ldx[mi][0][i], M.d.ldq, 0, 0, 1.0, 0.0,
+                   M.d.run});
       r0 += rows;
     }
   }
@@ -1573,9 +1576,9 @@ void qr_blocked(Ctx& c, const std::vector<CholQRDesc>& ds) {
   if (v.empty()) return;
   for (auto& d : v) zero_block(c, d.R, d.n, d.n, d.ldr);
   for (int j = 0; j < maxp; ++j) {
-    std::vector<GemmDesc> p1, p2, p3, p4, p6, p7, rr, rs;
+    std::vector<GemmDesc> p1, p2, p3, p4, p6, p7, rr, rs, rs3;
     std::vector<QRDesc> tq1, tq2;
-    std::vector<CopyDesc> back, lost, adds;
+    std::vector<CopyDesc> back, lost;
     std::vector<uint64_t> lost_keys;
     for (auto& d : v) {
       const int j0 = j * W;
@@ -1601,30 +1604,42 @@ void qr_blocked(Ctx& c, const std::vector<CholQRDesc>& ds) {
       p3.push_back({d.P, Q1, S2, j0, w, d.m, d.ld, d.m, j0, 1, 0, 1.0, 0.0});          // S2
       p4.push_back({d.P, S2, Q1, d.m, w, j0, d.ld, j0, d.m, 0, 0, -1.0, 1.0});         // Q1 -= Q S2
       // columns of Q1 that the projection removed (dependent panel) become
-      // Gaussian; one more projection, whose coefficients join S2
+      // Gaussian; one more projection, whose coefficients S3 enter R like S2
+      // (these three products run only for blocks with a replaced column)
       lost.push_back({Q1, d.m, nullptr, 0, d.m, w, 1.0, 0.0, 0});
       lost_keys.push_back(stream_key(0x9e3779b97f4a7c15ull ^ (uint64_t)d.m, PHASE_LOST, (uint32_t)j,
                                      (uint32_t)d.n, (uint32_t)v.size()));
       p6.push_back({d.P, Q1, S3, j0, w, d.m, d.ld, d.m, j0, 1, 0, 1.0, 0.0});          // S3 = Q^T Q1
       p7.push_back({d.P, S3, Q1, d.m, w, j0, d.ld, j0, d.m, 0, 0, -1.0, 1.0});         // Q1 -= Q S3
-      adds.push_back({S3, j0, S2, j0, j0, w, 1.0, 1.0, 0});                             // S2 += S3
       tq2.push_back({Q1, d.m, d.m, w, Q2, d.m, R2, w});                                 // Q1 = Q2 R2
       rr.push_back({R2, R1, Rjj, w, w, w, w, w, d.ldr, 0, 0, 1.0, 0.0});                // R_jj
       rs.push_back({S2, R1, Rj, j0, w, w, j0, w, d.ldr, 0, 0, 1.0, 1.0});               // S1 += S2 R1
+      rs3.push_back({S3, R1, Rj, j0, w, w, j0, w, d.ldr, 0, 0, 1.0, 1.0});              // ... + S3 R1
       back.push_back({Q2, d.m, Pj, d.ld, d.m, w, 1.0, 0.0, 0});
+    }
+    // lost-column flags: p6, p7 and the S3 R1 term run only where a column was replaced
+    int* flags = nullptr;
+    if (!lost.empty()) {
+      flags = (int*)c.scratch.get((lost.size() + 1) / 2);
+      zero_block(c, (double*)flags, (int)((lost.size() + 1) / 2), 1, (int)((lost.size() + 1) / 2));
+      for (size_t i = 0; i < lost.size(); ++i) {
+        p6[i].run = flags + i;
+        p7[i].run = flags + i;
+        rs3[i].run = flags + i;
+      }
     }
     gemm_batched(c, p1);
     gemm_batched(c, p2);
     qr_tall_batched(c, tq1);
     gemm_batched(c, p3);
     gemm_batched(c, p4);
-    replace_lost_columns(c, lost, lost_keys);
+    replace_lost_columns(c, lost, lost_keys, flags);
     gemm_batched(c, p6);
     gemm_batched(c, p7);
-    copy_batched(c, adds);
     qr_tall_batched(c, tq2);
     gemm_batched(c, rr);
     gemm_batched(c, rs);
+    gemm_batched(c, rs3);
     copy_batched(c, back);
   }
 }
@@ -1637,6 +1652,7 @@ void qr_auto(Ctx& c, const std::vector<QRDesc>& ds) {
   std::vector<CopyDesc> toq2;
   for (auto d : ds) {
     if (d.m <= 0 || d.n <= 0) continue;
+    H2_CHECK(d.run == nullptr, H2_EINVAL, "QR run flags are taken by the tall QR only");
     if (d.m < d.n) {
       // wide: the m reflectors come from the first m columns, so Q is the Q of
       // those columns (TSQR) and R = [R_1, Q^T A(:, m:)] (one GEMM)
@@ -1759,7 +1775,8 @@ __global__ __launch_bounds__(256) void k_colnorm_max(CA ds, double* __restrict__
 // column), so that the projection and QR that follow give a direction
 // orthogonal to the span.  One wave per column.
 template <class CA, class KA>
-__global__ __launch_bounds__(256) void k_replace_lost_columns(CA ds, KA keys) {
+__global__ __launch_bounds__(256) void k_replace_lost_columns(CA ds, KA keys, int* __restrict__ flags,
+                                                              int* __restrict__ nlost) {
   const CopyDesc d = ds[blockIdx.x];
   const uint64_t key = keys[blockIdx.x];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -1775,24 +1792,40 @@ __global__ __launch_bounds__(256) void k_replace_lost_columns(CA ds, KA keys) {
       for (int i = lane; i < d.rows; i += 64) s += col[i] * col[i];
       lost = wave_sum(s) < 0.25;
     }
-    if (lost)
+    if (lost) {
       for (int i = lane; i < d.rows; i += 64) col[i] = sc * gauss_entry(key, (uint64_t)i, (uint64_t)j);
+      if (flags && lane == 0) flags[blockIdx.x] = 1;
+      if (nlost && lane == 0) atomicAdd(nlost, 1);
+    }
   }
 }
 
 void replace_lost_columns(Ctx& c, const std::vector<CopyDesc>& blocks,
-                          const std::vector<uint64_t>& keys) {
+                          const std::vector<uint64_t>& keys, int* flags) {
   if (blocks.empty()) return;
   H2_CHECK(blocks.size() == keys.size(), H2_EINVAL, "one key per block");
   int mc = 1;
   for (auto& b : blocks) mc = std::max(mc, b.cols);
   const dim3 grid((unsigned)blocks.size(), (unsigned)((mc + 3) / 4));
+  // verbose runs count the replaced columns
+  int* nlost = nullptr;
+  if (verbose()) {
+    nlost = (int*)c.scratch.get(1);
+    H2_HIP(hipMemsetAsync(nlost, 0, sizeof(int), c.s));
+  }
   with_descs<32>(c, blocks.data(), blocks.size(), [&](auto dd) {
     with_descs<32>(c, keys.data(), keys.size(), [&](auto dk) {
-      k_replace_lost_columns<<<grid, 256, 0, c.s>>>(dd, dk);
+      k_replace_lost_columns<<<grid, 256, 0, c.s>>>(dd, dk, flags, nlost);
     });
   });
   H2_LAUNCH_CHECK();
+  if (nlost) {
+    int n = 0, tot = 0;
+    H2_HIP(hipMemcpyAsync(&n, nlost, sizeof(int), hipMemcpyDeviceToHost, c.s));
+    H2_HIP(hipStreamSynchronize(c.s));
+    for (auto& b : blocks) tot += b.cols;
+    std::fprintf(stderr, "    [lost] %d of %d columns in %zu blocks\n", n, tot, blocks.size());
+  }
 }
 
 void colnorm_max_batched(Ctx& c, const std::vector<CopyDesc>& blocks, double* out) {
