@@ -642,6 +642,40 @@ __device__ inline void blockrow_lds_pipe_bf(int rows, int nsrc, const PipeSrcBF*
 }
 
 // leaf stage in FP64 or FP32: y_t = alpha (U_t y^_t + sum_near D_ts x_s) + beta y_t
+// Split far lists: when the coupling stage has few output tiles, each tile's
+// list of blocks is cut into G consecutive groups taken by G workgroups
+// (blockIdx.z), which store partial sums; the last to arrive adds the G
+// partials in group order, so the sums do not depend on arrival order or on
+// the tile width.  Publication as in the block Jacobi: every wave's stores
+// complete at the L2, thread 0 fences at device scope before it increments
+// the tile's counter, and the last workgroup resets the counter and fences
+// again before its waves read the other partials.
+template <class V>
+struct Split {
+  int G = 1;            // groups per block row
+  V* part = nullptr;    // the G partial outputs, pstride elements apart
+  int64_t pstride = 0;
+  int* cnt = nullptr;   // arrival counters, one per output tile, zero between products
+};
+
+__device__ inline bool split_last(int* cnt, int G) {
+  __shared__ int last;
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();
+    const int old = atomicAdd(cnt, 1);
+    last = old == G - 1;
+    if (last) {
+      atomicExch(cnt, 0);
+      __threadfence();
+    }
+  }
+  __syncthreads();
+  return last != 0;
+}
+
 template <class M, class V, int NT>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))) void k_leaf_direct(
     int L, const int32_t* __restrict__ cstart, const int32_t* __restrict__ csize,
@@ -755,14 +789,17 @@ __global__ __launch_bounds__(256) void k_coupling_mfma(
     const int32_t* __restrict__ rank, const int64_t* __restrict__ kpre,
     const int32_t* __restrict__ far_ptr, const int32_t* __restrict__ far_col,
     const int64_t* __restrict__ Soff, const M* __restrict__ S, int nv, const V* __restrict__ xh,
-    V* __restrict__ yh) {
+    V* __restrict__ yh, Split<V> sp) {
   MF_SHARED(M, NT)
   const int c = blockIdx.x + 1;
   const int kt = rank[c];
   if (kt == 0) return;
   const int l = 31 - __clz(c + 1);
   const int base = (1 << l) - 1;
-  const int pb = far_ptr[c + l], pe = far_ptr[c + l + 1];
+  // this workgroup's group of the far partners (all of them when G = 1)
+  const int G = sp.G;
+  const int f0 = far_ptr[c + l], nf = far_ptr[c + l + 1] - f0, chunk = (nf + G - 1) / G;
+  const int pb = f0 + min(nf, (int)blockIdx.z * chunk), pe = f0 + min(nf, ((int)blockIdx.z + 1) * chunk);
   const int v0 = blockIdx.y * NC_;
   const int nvc = min(NC_, nv - v0);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -777,12 +814,27 @@ __global__ __launch_bounds__(256) void k_coupling_mfma(
   };
   blockrow_mfma<M, V, NT>(kt, pe - pb, src, nvc, acc, As, Bs);
   V* out = yh + kpre[c] * nv;
+  V* dst = G == 1 ? out : sp.part + blockIdx.z * sp.pstride + kpre[c] * nv;
 #pragma unroll
   for (int ct = 0; ct < NT; ++ct)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int row = 16 * wave + mf_row<M>(r, lane), col = ct * 16 + (lane & 15);
-      if (row < kt && col < nvc) out[(size_t)(v0 + col) * kt + row] = (V)acc[ct][r];
+      if (row < kt && col < nvc) dst[(size_t)(v0 + col) * kt + row] = (V)acc[ct][r];
+    }
+  if (G == 1 || !split_last(sp.cnt + (size_t)blockIdx.x * gridDim.y + blockIdx.y, G)) return;
+  const V* p0 = sp.part + kpre[c] * nv;
+#pragma unroll
+  for (int ct = 0; ct < NT; ++ct)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = 16 * wave + mf_row<M>(r, lane), col = ct * 16 + (lane & 15);
+      if (row < kt && col < nvc) {
+        const size_t e = (size_t)(v0 + col) * kt + row;
+        V sum = p0[e];
+        for (int z = 1; z < G; ++z) sum += p0[z * sp.pstride + e];
+        out[e] = sum;
+      }
     }
 }
 
@@ -896,15 +948,16 @@ static void up_leaf_nt(const h2_matrix* A, int nv, const V* xt, int ldx, V* xh, 
       A->d_kpre.as<int64_t>(), A->d_U_off.as<int64_t>(), A->st.U.as<M>(), xt, ldx, nv, xh);
 }
 template <class M, class V, int NT>
-static void coupling_nt(const h2_matrix* A, int nv, const V* xh, V* yh, hipStream_t s) {
+static void coupling_nt(const h2_matrix* A, int nv, const V* xh, V* yh, hipStream_t s,
+                        Split<V> sp) {
   const h2_tree* t = A->tree;
   const unsigned gy = (unsigned)((nv + 16 * NT - 1) / (16 * NT));
   // (small blocks, many per cluster: the single-buffered LDS tiles of
   // blockrow_mfma, which leave room for two workgroups per compute unit, beat
   // the register-pipelined product here, in FP64 too)
-  k_coupling_mfma<M, V, NT><<<dim3(t->nclusters() - 1, gy), 256, 0, s>>>(
+  k_coupling_mfma<M, V, NT><<<dim3(t->nclusters() - 1, gy, sp.G), 256, 0, s>>>(
       A->d_rank.as<int32_t>(), A->d_kpre.as<int64_t>(), t->d_far_ptr.as<int32_t>(),
-      t->d_far_col.as<int32_t>(), A->d_S_off.as<int64_t>(), A->st.S.as<M>(), nv, xh, yh);
+      t->d_far_col.as<int32_t>(), A->d_S_off.as<int64_t>(), A->st.S.as<M>(), nv, xh, yh, sp);
 }
 template <class M, class V, int NT>
 static void leaf_nt(const h2_matrix* A, int nv, V alpha, const V* xt, int ldx, V beta, V* yt,
@@ -928,18 +981,50 @@ static void leaf_nt(const h2_matrix* A, int nv, V alpha, const V* xt, int ldx, V
         A->st.D.as<M>(), nv, yh, xt, ldx, alpha, beta, yt, ldy);
 }
 
+__global__ void k_zero_i32(int* p, int64_t n) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < n) p[e] = 0;
+}
+
+// groups per far list of the coupling stage: split only where the couplings
+// are large (mean rank of at least 32: a list's chain of k x k products is
+// long next to the cost of the partial sums) and the tiles at the narrowest
+// width (16 vectors) are too few to fill the chip (about 2048 workgroups).
+// Independent of the chosen width, so every width sums alike.
+static int split_groups(int64_t tiles, double mean_rank) {
+  if (mean_rank < 32.0 || tiles >= 2048) return 1;
+  return (int)std::min<int64_t>(4, (2048 + tiles - 1) / tiles);
+}
+
 // coef: 2 * (sum of ranks) * nv coefficient words (x-hat, y-hat); nullptr:
-// the matrix's own workspace, grown on demand
+// the matrix's own workspace, grown on demand, which also holds the partial
+// sums of split far lists (coef given: no split)
 template <class M, class V>
 static void gemv_tree_run(const h2_matrix* A, int nv, V alpha, const V* xt, int ldx, V beta,
                           V* yt, int ldy, hipStream_t s, int nt, V* coef = nullptr) {
   const h2_tree* t = A->tree;
   const int L = t->L;
   const int64_t ktot = A->kpre.back();
+  const int64_t gy1 = (nv + 15) / 16;
+  Split<V> spc;   // coupling stage
   if (!coef) {
-    const size_t need = (size_t)2 * ktot * nv * sizeof(V);
+    if (nt > 0 && L >= 1)
+      spc.G = split_groups((int64_t)(t->nclusters() - 1) * gy1, (double)ktot / (t->nclusters() - 1));
+    const int64_t wc = spc.G > 1 ? spc.G * ktot * nv : 0;
+    const size_t need = (size_t)(2 * ktot * nv + wc) * sizeof(V);
     A->ws.reserve(std::max<size_t>(need, 256));
     coef = A->ws.as<V>();
+    spc.part = coef + 2 * ktot * nv;
+    spc.pstride = ktot * nv;
+    if (spc.G > 1) {
+      // arrival counters, one per coupling tile (zero at rest)
+      const int64_t nc = (int64_t)t->nclusters() * gy1;
+      if ((size_t)nc * sizeof(int) > A->ws_cnt.bytes) {
+        A->ws_cnt.alloc((size_t)nc * sizeof(int));
+        k_zero_i32<<<(unsigned)((nc + 255) / 256), 256, 0, s>>>(A->ws_cnt.as<int>(), nc);
+      }
+      spc.cnt = A->ws_cnt.as<int>();
+    }
   }
   V* xh = coef;
   V* yh = xh + ktot * nv;
@@ -977,9 +1062,9 @@ static void gemv_tree_run(const h2_matrix* A, int nv, V alpha, const V* xt, int 
                                                   xh);
     }
     if constexpr (has_mfma<M, V>()) {
-      if (nt == 1) coupling_nt<M, V, 1>(A, nv, xh, yh, s);
-      else if (nt == 2) coupling_nt<M, V, 2>(A, nv, xh, yh, s);
-      else if (nt == 4) coupling_nt<M, V, 4>(A, nv, xh, yh, s);
+      if (nt == 1) coupling_nt<M, V, 1>(A, nv, xh, yh, s, spc);
+      else if (nt == 2) coupling_nt<M, V, 2>(A, nv, xh, yh, s, spc);
+      else if (nt == 4) coupling_nt<M, V, 4>(A, nv, xh, yh, s, spc);
     }
     if (!mf)
       k_coupling<M, V><<<t->nclusters() - 1, 256, 0, s>>>(

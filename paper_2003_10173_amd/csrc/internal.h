@@ -139,6 +139,8 @@ struct h2_matrix {
   // HGEMV workspace (grown on demand): tree-order x, y and coefficient vectors
   mutable h2::DevBuf ws;
   mutable h2::DevBuf ws_vec;  // user <-> tree order staging of h2_gemv
+  // arrival counters of the split block rows (zero between products)
+  mutable h2::DevBuf ws_cnt;
   int64_t nU() const { return U_off.back(); }
   int64_t nE() const { return E_off.back(); }
   int64_t nS() const { return S_off.back(); }

@@ -532,11 +532,13 @@ __device__ inline bool jacobi_rotate(double* A, int lda, int m, double* V, int l
   return true;
 }
 
+// V = I, a workgroup per 16 columns (blockIdx.y)
 __global__ void k_svd_init_v(const SVDDesc* __restrict__ descs) {
   const SVDDesc d = descs[blockIdx.x];
   if (!d.V) return;
-  for (int e = threadIdx.x; e < d.n * d.n; e += blockDim.x)
-    d.V[(size_t)(e / d.n) * d.ldv + e % d.n] = (e / d.n == e % d.n) ? 1.0 : 0.0;
+  const int c0 = 16 * blockIdx.y;
+  for (int c = c0; c < min(d.n, c0 + 16); ++c)
+    for (int i = threadIdx.x; i < d.n; i += blockDim.x) d.V[(size_t)c * d.ldv + i] = i == c ? 1.0 : 0.0;
 }
 
 // single workgroup per matrix (small n): 8 waves rotate 8 disjoint pairs at a time
@@ -949,16 +951,25 @@ __global__ __launch_bounds__(512) void k_svd_block(const SVDDesc* __restrict__ d
 __device__ inline double svd_rank_key(double s) { return s == s ? s : -__builtin_inf(); }
 
 // singular values = column norms, sorted descending; U = normalised columns;
-// V columns permuted accordingly (through A, which is no longer needed)
+// V columns permuted alike.  k_svd_order (one workgroup per matrix) finds
+// the norms and their order; k_svd_permute and k_svd_vback (a workgroup per
+// 16 output columns) write U and the permuted V through a scratch copy.
 // status[1] set (a block Jacobi wait timed out): singular values are NaN
-__global__ __launch_bounds__(1024) void k_svd_final(const SVDDesc* __restrict__ descs,
+struct SvdFin {
+  int* ord;      // n: source column of output column r
+  double* nrm;   // n: column norms, unsorted
+  double* T;     // n x n (ld n): permuted V before it is copied back
+};
+
+__global__ __launch_bounds__(1024) void k_svd_order(const SVDDesc* __restrict__ descs,
+                                                    const SvdFin* __restrict__ fin,
                                                     const int* __restrict__ status) {
   const SVDDesc d = descs[blockIdx.x];
+  const SvdFin f = fin[blockIdx.x];
   const int n = d.n, m = d.m;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   __shared__ double sig[1024];
-  __shared__ int order[1024];
-  double* A = d.A;
+  const double* A = d.A;
   const int lda = d.lda;
   for (int col = wave; col < n; col += 16) {
     const double* ca = A + (size_t)col * lda;
@@ -970,7 +981,8 @@ __global__ __launch_bounds__(1024) void k_svd_final(const SVDDesc* __restrict__ 
   __syncthreads();
   // descending order, equal values by index: position of i = number of
   // values ranked before it.  A value that is not a number ranks as -inf, so
-  // the ranking is a total order and order[] a permutation for any input
+  // the ranking is a total order and ord a permutation for any input
+  const bool failed = status[1] != 0;
   for (int i = tid; i < n; i += 1024) {
     const double si = svd_rank_key(sig[i]);
     int r = 0;
@@ -978,30 +990,47 @@ __global__ __launch_bounds__(1024) void k_svd_final(const SVDDesc* __restrict__ 
       const double sj = svd_rank_key(sig[j]);
       r += (sj > si) || (sj == si && j < i);
     }
-    order[r] = i;
+    f.ord[r] = i;
+    f.nrm[i] = sig[i];
+    d.sigma[r] = failed ? __builtin_nan("") : sig[i];
   }
-  __syncthreads();
-  const bool failed = status[1] != 0;
-  for (int e = tid; e < n; e += 1024) d.sigma[e] = failed ? __builtin_nan("") : sig[order[e]];
-  if (d.U) {
-    for (int e = tid; e < m * n; e += 1024) {
-      const int i = e % m, r = e / m;
-      const int src = order[r];
-      const double s = sig[src];
-      d.U[(size_t)r * d.ldu + i] = s > 0 ? A[(size_t)src * lda + i] / s : 0.0;
+}
+
+// output columns 16 y .. 16 y + 15 of matrix x: U(:, r) = A(:, ord r) / nrm,
+// T(:, r) = V(:, ord r)
+__global__ __launch_bounds__(256) void k_svd_permute(const SVDDesc* __restrict__ descs,
+                                                     const SvdFin* __restrict__ fin) {
+  const SVDDesc d = descs[blockIdx.x];
+  const SvdFin f = fin[blockIdx.x];
+  const int n = d.n, m = d.m;
+  const int r0 = 16 * blockIdx.y;
+  for (int r = r0; r < min(n, r0 + 16); ++r) {
+    const int src = f.ord[r];
+    if (d.U) {
+      const double s = f.nrm[src];
+      const double* a = d.A + (size_t)src * d.lda;
+      double* u = d.U + (size_t)r * d.ldu;
+      for (int i = threadIdx.x; i < m; i += 256) u[i] = s > 0 ? a[i] / s : 0.0;
+    }
+    if (d.V) {
+      const double* v = d.V + (size_t)src * d.ldv;
+      double* t = f.T + (size_t)r * n;
+      for (int i = threadIdx.x; i < n; i += 256) t[i] = v[i];
     }
   }
-  __syncthreads();
-  if (d.V) {
-    for (int e = tid; e < n * n; e += 1024) {
-      const int i = e % n, c = e / n;
-      A[(size_t)c * lda + i] = d.V[(size_t)c * d.ldv + i];
-    }
-    __syncthreads();
-    for (int e = tid; e < n * n; e += 1024) {
-      const int i = e % n, r = e / n;
-      d.V[(size_t)r * d.ldv + i] = A[(size_t)order[r] * lda + i];
-    }
+}
+
+__global__ __launch_bounds__(256) void k_svd_vback(const SVDDesc* __restrict__ descs,
+                                                   const SvdFin* __restrict__ fin) {
+  const SVDDesc d = descs[blockIdx.x];
+  if (!d.V) return;
+  const SvdFin f = fin[blockIdx.x];
+  const int n = d.n;
+  const int r0 = 16 * blockIdx.y;
+  for (int r = r0; r < min(n, r0 + 16); ++r) {
+    const double* t = f.T + (size_t)r * n;
+    double* v = d.V + (size_t)r * d.ldv;
+    for (int i = threadIdx.x; i < n; i += 256) v[i] = t[i];
   }
 }
 
@@ -1023,7 +1052,9 @@ void svd_batched(Ctx& c, const std::vector<SVDDesc>& ds) {
   }
   if (all.empty()) return;
   auto* dall = (SVDDesc*)c.stage.put(all.data(), all.size() * sizeof(SVDDesc), c.s);
-  k_svd_init_v<<<(unsigned)all.size(), 256, 0, c.s>>>(dall);
+  int nmx = 1;
+  for (auto& d : all) nmx = std::max(nmx, d.n);
+  k_svd_init_v<<<dim3((unsigned)all.size(), (unsigned)((nmx + 15) / 16)), 256, 0, c.s>>>(dall);
   H2_LAUNCH_CHECK();
   if (!small.empty()) {
     auto* dd = (SVDDesc*)c.stage.put(small.data(), small.size() * sizeof(SVDDesc), c.s);
@@ -1107,7 +1138,20 @@ void svd_batched(Ctx& c, const std::vector<SVDDesc>& ds) {
       i0 = i1;
     }
   }
-  k_svd_final<<<(unsigned)all.size(), 1024, 0, c.s>>>(dall, status);
+  std::vector<SvdFin> fin(all.size());
+  int nmax = 1;
+  for (size_t i = 0; i < all.size(); ++i) {
+    const int n = all[i].n;
+    nmax = std::max(nmax, n);
+    fin[i].ord = (int*)c.scratch.get((size_t)(n + 1) / 2);
+    fin[i].nrm = c.scratch.get((size_t)n);
+    fin[i].T = all[i].V ? c.scratch.get((size_t)n * n) : nullptr;
+  }
+  auto* dfin = (SvdFin*)c.stage.put(fin.data(), fin.size() * sizeof(SvdFin), c.s);
+  k_svd_order<<<(unsigned)all.size(), 1024, 0, c.s>>>(dall, dfin, status);
+  const dim3 g2((unsigned)all.size(), (unsigned)((nmax + 15) / 16));
+  k_svd_permute<<<g2, 256, 0, c.s>>>(dall, dfin);
+  k_svd_vback<<<g2, 256, 0, c.s>>>(dall, dfin);
   H2_LAUNCH_CHECK();
 }
 
@@ -1746,12 +1790,13 @@ void copy_batched(Ctx& c, const std::vector<CopyDesc>& ds) {
 }
 
 template <class CA>
-__global__ __launch_bounds__(256) void k_colnorm_max(CA ds, double* __restrict__ out) {
+__global__ __launch_bounds__(1024) void k_colnorm_max(CA ds, double* __restrict__ out) {
+  // one wave per column, 16 waves
   const CopyDesc d = ds[blockIdx.x];
-  __shared__ double red[4];
+  __shared__ double red[16];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   double best = 0;
-  for (int j = wave; j < d.cols; j += 4) {
+  for (int j = wave; j < d.cols; j += 16) {
     const double* col = d.src + (size_t)j * d.lds;
     double s = 0;
     for (int i = lane; i < d.rows; i += 64) s += col[i] * col[i];
@@ -1760,7 +1805,11 @@ __global__ __launch_bounds__(256) void k_colnorm_max(CA ds, double* __restrict__
   }
   if (lane == 0) red[wave] = best;
   __syncthreads();
-  if (threadIdx.x == 0) out[blockIdx.x] = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+  if (threadIdx.x == 0) {
+    double m = red[0];
+    for (int w = 1; w < 16; ++w) m = fmax(m, red[w]);
+    out[blockIdx.x] = m;
+  }
 }
 
 // Columns of a projected orthonormal block that lie (numerically) in the
@@ -1831,7 +1880,7 @@ void replace_lost_columns(Ctx& c, const std::vector<CopyDesc>& blocks,
 void colnorm_max_batched(Ctx& c, const std::vector<CopyDesc>& blocks, double* out) {
   if (blocks.empty()) return;
   with_descs<40>(c, blocks.data(), blocks.size(), [&](auto dd) {
-    k_colnorm_max<<<(unsigned)blocks.size(), 256, 0, c.s>>>(dd, out);
+    k_colnorm_max<<<(unsigned)blocks.size(), 1024, 0, c.s>>>(dd, out);
   });
   H2_LAUNCH_CHECK();
 }
