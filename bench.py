@@ -522,6 +522,8 @@ def main():
         "build_applies": bst["applies"],
         "build_ms": round(bst["time_ms"][7], 2),
         "ns_ms": round(nst["time_ms"][3], 2),
+        "ns_phase_ms": {"residual": round(nst["time_ms"][0], 2), "build": round(nst["time_ms"][1], 2),
+                        "refine": round(nst["time_ms"][2], 2)},
         "hgemv_gbs": round(gbs, 2),
         "checks": checks,
         "unmeasured": "build + inverse of the 256x256 kernel Hessian (N=65536, FP32 Newton-"

@@ -1264,8 +1264,8 @@ void build_h2_multi(std::vector<BuildJob>& jobs, Ctx& c) {
         }
         const int l = sib_level(L, a, bb);
         const int kl = s.pair_rank(l, L, a);
-        if (kl == 0) {
-          zero_block(c, Dd + A->D_off[q], mb, ma, mb);
+        if (kl == 0) {  // an empty product (K = 0) writes the zero block, in the same launch
+          gs.push_back({nullptr, nullptr, Dd + A->D_off[q], mb, ma, 0, 1, 1, mb, 0, 0, 1.0, 0.0});
           continue;
         }
         gs.push_back({s.Frows(l, L, bb), s.Frows(l, L, a), Dd + A->D_off[q], mb, ma, kl, n, n, mb, 0, 1, 1.0, 0.0});
