@@ -174,7 +174,7 @@ def learned_form(h2, torch, si):
     return out
 
 
-def batched_form(h2, torch, si, count=32):
+def batched_form(h2, torch, si, count=256):
     """Construction of `count` uneven 2D kernel Hessians (N log-uniform in
     [1024, 16384] on random-aspect grids, ell ~ U[0.02, 0.2], cap 32, eps 1e-4)
     in one level-synchronous batch against one build after the other."""
