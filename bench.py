@@ -174,6 +174,45 @@ def learned_form(h2, torch, si):
     return out
 
 
+def c3_inverse_form(h2, torch, si):
+    """Build and 20 Newton-Schulz iterations (from I / nu, dynamic threshold)
+    of the 2D kernel Hessian on a 256 x 256 grid (N = 65536, leaf 64, cap 32,
+    build at 1e-4), with FP32 samplers while the residual is large (FP64
+    residuals and refinement) and all in FP64.  With rank cap 32 the iterates
+    cannot represent the inverse to 1e-4 (at 128 x 128 the residual levels
+    off near 2e-2), so the form runs the fixed count of the 1D configuration
+    and reports the residual it reaches.  Not part of the default run
+    (about a minute per form): `--forms-only --only c3_inverse`."""
+    cfg = si.config_kernel2d(256)
+    tree = h2.Tree(cfg["points"], cfg["leaf"], cfg["eta"])
+    S = h2.KernelSampler(cfg["points"], cfg["ell"], cfg["shift"])
+    o = h2.opts(rank_cap=cfg["cap"], oversample=cfg["p"], tol=cfg["tol"], adaptive=1,
+                max_rounds=16, seed=cfg["seed"])
+    out = {"workload": "kernel2d 256x256 (N=65536), leaf 64, cap 32, build at 1e-4 + 20 Newton-Schulz "
+                       "iterations (dynamic threshold, X0 = I/nu)"}
+    for name, prec in (("fp32_samplers", h2.H2_FP32), ("fp64", h2.H2_FP64)):
+        nopts = h2.ns_opts(eps=1e-4, max_iter=20, x0=0, dynamic=1, rank_cap=cfg["cap"],
+                           oversample=cfg["p"], adaptive=1, max_rounds=16, seed=cfg["seed"],
+                           prec=prec)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        A, bst = h2.build(tree, S, o)
+        torch.cuda.synchronize()
+        t_build = time.perf_counter() - t0
+        X, nst = h2.newton_schulz(A, nopts)
+        torch.cuda.synchronize()
+        t_all = time.perf_counter() - t0
+        # a fixed count: valid when the 20 iterations ran without divergence
+        ok = bool(bst["converged"]) and nst["status"] in (0, 1) and nst["iterations"] == 20
+        out[name] = {"s": round(t_all, 3), "build_s": round(t_build, 3),
+                     "iterations": nst["iterations"], "low_iterations": nst.get("low_iterations"),
+                     "residual": nst["resid"][-1], "valid": ok}
+        print("c3 inverse %s: %.1f s (build %.1f s), %d iterations, residual %.2e" % (
+            name, t_all, t_build, nst["iterations"], nst["resid"][-1]), file=sys.stderr, flush=True)
+        del A, X
+    return out
+
+
 def batched_form(h2, torch, si, count=256):
     """Construction of `count` uneven 2D kernel Hessians (N log-uniform in
     [1024, 16384] on random-aspect grids, ell ~ U[0.02, 0.2], cap 32, eps 1e-4)
@@ -375,7 +414,8 @@ def main():
                "global_lowrank": lambda: lowrank_form(h2, torch, si),
                "precision_ladder": lambda: precision_ladder(h2, torch, si, stream),
                "learned": lambda: learned_form(h2, torch, si),
-               "batched": lambda: batched_form(h2, torch, si)}
+               "batched": lambda: batched_form(h2, torch, si),
+               "c3_inverse": lambda: c3_inverse_form(h2, torch, si)}
         print(json.dumps({k: fns[k]() for k in args.only.split(",")}), flush=True)
         return
     cfg = si.config_diffusion2d(args.grid)

@@ -32,6 +32,13 @@ struct Scratch {
   size_t used = 0;
   double* get(size_t elems);  // returns a fresh region valid until clear()
   void clear();               // only when the stream is idle
+  // Stream-ordered reuse: release(mark()) hands the regions obtained after
+  // the mark out again.  Every user of the arena enqueues on the one stream
+  // of its context, so work enqueued later runs after the work that used
+  // the released regions; the host must not read them afterwards.
+  struct Mark { size_t nbufs, used; };
+  Mark mark() const { return {bufs.size(), used}; }
+  void release(const Mark& m) { used = bufs.size() == m.nbufs ? m.used : 0; }
 };
 
 // C (M x N) = alpha op(A) op(B) + beta C, column-major; op(X) = X or X^T.

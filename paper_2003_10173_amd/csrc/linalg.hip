@@ -1620,6 +1620,9 @@ void qr_blocked(Ctx& c, const std::vector<CholQRDesc>& ds) {
   if (v.empty()) return;
   for (auto& d : v) zero_block(c, d.R, d.n, d.n, d.ldr);
   for (int j = 0; j < maxp; ++j) {
+    // a panel's temporaries (and those of its tall QRs) are dead once its
+    // results are in P and R: the next panel reuses their memory
+    const Scratch::Mark panel_mark = c.scratch.mark();
     std::vector<GemmDesc> p1, p2, p3, p4, p6, p7, rr, rs, rs3;
     std::vector<QRDesc> tq1, tq2;
     std::vector<CopyDesc> back, lost;
@@ -1685,6 +1688,7 @@ void qr_blocked(Ctx& c, const std::vector<CholQRDesc>& ds) {
     gemm_batched(c, rs);
     gemm_batched(c, rs3);
     copy_batched(c, back);
+    c.scratch.release(panel_mark);
   }
 }
 
