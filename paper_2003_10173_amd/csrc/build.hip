@@ -200,6 +200,19 @@ struct LsvTask {
 // below the samples' own error; FP64 samples to the FP64 rounding level
 static double svd_tol(const BuildParams& p) { return p.rank_cut > 1e-12 ? 1e-2 * p.rank_cut : 0.0; }
 
+// Jacobi tolerance of the range-basis SVD.  Its only outputs that matter are
+// the count of singular values above rank_cut sigma_1 and, when directions
+// are cut, the kept span; the basis is otherwise used only through its span
+// (the projection's truncation SVD absorbs any rotation of it).  One-sided
+// Jacobi stopped at column cosines <= t leaves columns A = Q D with
+// |Q^T Q - I| <= n t, so every column norm is its singular value to relative
+// accuracy n t / 2 (Ostrowski), tiny ones included: t = 1e-8 (n <= 1024:
+// 5e-6 relative) decides the count like the rounding-level tolerance, and a
+// cut direction (below rank_cut sigma_1) keeps cosines <= 1e-8 with the
+// kept ones.  (t = 1e-6 moved built operators by up to 4e-10 relative,
+// through the kept span where directions were cut.)
+static double range_svd_tol(const BuildParams& p) { return std::max(svd_tol(p), 1e-8); }
+
 void left_svd_batched(Ctx& c, const std::vector<LsvTask>& tasks) {
   std::vector<CopyDesc> tr;
   std::vector<QRDesc> qrs;
@@ -764,7 +777,7 @@ void build_h2_multi(std::vector<BuildJob>& jobs, Ctx& c) {
                        1.0, 0.0});
           // left singular vectors of R = right singular vectors of R^T
           svs.push_back({Rt, cp, cp, s->kq[p], s->sig_all + s->soff[p], nullptr, 0, s->Vp[p], s->kq[p],
-                         svd_tol(*s->prm)});
+                         range_svd_tol(*s->prm)});
         }
       }
       gemm_batched(c, g);
@@ -788,6 +801,9 @@ void build_h2_multi(std::vector<BuildJob>& jobs, Ctx& c) {
           }
           s->k0[p] = k;
           s->K0 = std::max(s->K0, k);
+          if (verbose() && s->kq[p] >= 24)
+            std::fprintf(stderr, "    [range] kq %d k0 %d smallest/largest %.2e\n", s->kq[p], k,
+                         s->kq[p] > 0 && sv[0] > 0 ? sv[s->kq[p] - 1] / sv[0] : 0.0);
           const int m2 = s->pr[p].m2;
           s->Q0[p] = c.scratch.get((size_t)m2 * std::max(k, 1));
           if (k > 0) {
