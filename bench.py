@@ -150,7 +150,9 @@ def precision_ladder(h2, torch, si, stream, reps=20):
 def learned_form(h2, torch, si):
     """Build of the advection-diffusion Gauss-Newton Hessian on a 128 x 128 grid
     (N = 16384, cap 32, eps 1e-4) with plain adaptive sampling and with the
-    trained first-round predictor: wall time, Hessian applies, sampling rounds."""
+    trained first-round predictor: wall time, Hessian applies, sampling rounds,
+    and each build's relative error on 8 Gaussian probes against the Hessian
+    itself (valid: the estimator converged and the error is at most 10 eps)."""
     from paper_2003_10173_amd import learned as LN
     net = LN.load()
     if net is None:
@@ -165,12 +167,18 @@ def learned_form(h2, torch, si):
         h2.build(tree, S, o)                      # warm-up (allocations)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        _, st = h2.build(tree, S, o)
+        Ab, st = h2.build(tree, S, o)
         torch.cuda.synchronize()
-        out[name] = {"s": round(time.perf_counter() - t0, 4), "applies": st["applies"],
-                     "rounds": sum(st["rounds"]), "first_cols": st["first_cols"]}
-        print("learned form %s: %.3f s, %d applies, %d rounds" % (
-            name, out[name]["s"], st["applies"], out[name]["rounds"]), file=sys.stderr, flush=True)
+        t_b = time.perf_counter() - t0
+        x = torch.tensor(si.gaussian_vectors(tree.n, 8, 77).T.copy(), device="cuda")
+        y_ref = S(x)
+        err = float(torch.linalg.norm(Ab.gemv(x) - y_ref) / torch.linalg.norm(y_ref))
+        out[name] = {"s": round(t_b, 4), "applies": st["applies"],
+                     "rounds": sum(st["rounds"]), "first_cols": st["first_cols"],
+                     "probe_rel_err": err, "valid": bool(st["converged"]) and err <= 1e-3}
+        print("learned form %s: %.3f s, %d applies, %d rounds, probe error %.1e" % (
+            name, out[name]["s"], st["applies"], out[name]["rounds"], err), file=sys.stderr,
+            flush=True)
     return out
 
 
