@@ -17,7 +17,7 @@ sys.path.insert(0, ROOT)
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--runs", type=int, default=400)
+    ap.add_argument("--runs", type=int, default=2000)
     ap.add_argument("--epochs", type=int, default=60)
     ap.add_argument("--out", default=None)
     a = ap.parse_args()
