@@ -1618,7 +1618,12 @@ void qr_blocked(Ctx& c, const std::vector<CholQRDesc>& ds) {
       maxp = std::max(maxp, (d.n + W - 1) / W);
     }
   if (v.empty()) return;
-  for (auto& d : v) zero_block(c, d.R, d.n, d.n, d.ldr);
+  {
+    // R = 0 for every matrix in one launch (empty products write zeros)
+    std::vector<GemmDesc> zr;
+    for (auto& d : v) zr.push_back({nullptr, nullptr, d.R, d.n, d.n, 0, 1, 1, d.ldr, 0, 0, 1.0, 0.0});
+    gemm_batched(c, zr);
+  }
   for (int j = 0; j < maxp; ++j) {
     // a panel's temporaries (and those of its tall QRs) are dead once its
     // results are in P and R: the next panel reuses their memory
