@@ -48,6 +48,9 @@ h2_status h2_test_gemv_tile(const h2_matrix* A, int nv, const double* x, double*
 /* the tile width the autotuner chose for FP64 products with nv vectors on
    A's tree (0: not tuned yet) */
 int h2_test_tuned_tile(const h2_matrix* A, int nv);
+/* groups per far list that h2_gemv's coupling stage uses for nv vectors on A
+   (1: no split) */
+int h2_test_gemv_split_groups(const h2_matrix* A, int nv);
 h2_status h2_test_svd_batch(int count, const int* m, const int* n, const double* A, double* sigma,
                             double* U, double* V);
 /* keep the weak factors of subsequent h2_build calls on this thread (1) or not (0) */

@@ -126,6 +126,7 @@ SIGNATURES = {
     "h2_test_svd_spin_limit": (None, [C.c_int]),
     "h2_test_gemv_tile": (C.c_int, [vp, C.c_int, vp, vp, C.c_int]),
     "h2_test_tuned_tile": (C.c_int, [vp, C.c_int]),
+    "h2_test_gemv_split_groups": (C.c_int, [vp, C.c_int]),
     "h2_test_cholqr": (C.c_int, [C.c_int, C.c_int, vp, vp, vp, C.c_int]),
     "h2_test_keep_factors": (None, [C.c_int]),
     "h2_test_factors": (C.c_int, [C.c_int, vp, vp, vp]),

@@ -1312,6 +1312,12 @@ int64_t gemv_noalloc_words(const h2_matrix* A, int nv) {
 
 using namespace h2;
 
+extern "C" int h2_test_gemv_split_groups(const h2_matrix* A, int nv) {
+  if (!A || nv <= 0 || A->tree->L < 1) return 1;
+  const int64_t nc = A->tree->nclusters() - 1;
+  return split_groups(nc * ((nv + 15) / 16), (double)A->kpre.back() / nc);
+}
+
 extern "C" h2_status h2_gemv_noalloc(const h2_matrix* A, int nv, double alpha, const double* x,
                                      int ldx, double beta, double* y, int ldy, hipStream_t s) {
   return guarded_status([&] {

@@ -19,12 +19,12 @@ torch = pytest.importorskip("torch")
 h2 = pytest.importorskip("paper_2003_10173_amd")
 
 
-def _random_h2(T, kmax, seed):
+def _random_h2(T, kmax, seed, kmin=0):
     g = np.random.Generator(np.random.PCG64(seed))
     H = OH2(T)
     L = T.L
     for l in range(2, L + 1):
-        H.rank[l][:] = g.integers(0, kmax + 1, size=1 << l)
+        H.rank[l][:] = g.integers(kmin, kmax + 1, size=1 << l)
     for i in range(1 << L):
         H.U[i] = g.standard_normal((T.size(L, i), H.rank[L][i]))
     for l in range(1, L + 1):
@@ -156,3 +156,34 @@ def test_hgemv_tile_widths_agree_and_tuner_picks_one(nv):
     torch.cuda.synchronize()
     assert np.array_equal(y.cpu().numpy(), outs[0])
     assert lib().h2_test_tuned_tile(G.handle, nv) in (1, 2, 4)
+
+
+@pytest.mark.parametrize("nv", [20, 64])
+def test_hgemv_split_far_lists(nv):
+    """Couplings of large rank on few tiles: the far lists are split over
+    workgroups (partial sums added in group order by the last to arrive).
+    Every tile width gives the same sums, the product matches the oracle's,
+    and the unsplit product (the entry point that allocates nothing) agrees
+    to rounding."""
+    from paper_2003_10173_amd._lib import lib
+    pts = np.random.Generator(np.random.PCG64(37)).uniform(size=(1500, 2))
+    T = OTree(pts, 64, 0.7)
+    H = _random_h2(T, 64, 8, kmin=40)
+    gt = h2.Tree(pts, 64, 0.7)
+    G = h2.H2Matrix.from_host(gt, *oracle_to_packed(H))
+    assert lib().h2_test_gemv_split_groups(G.handle, nv) > 1
+    x = torch.tensor(si.gaussian_vectors(T.n, nv, 6).T.copy(), device="cuda")
+    outs = []
+    for nt in (1, 2, 4):
+        y = torch.empty_like(x)
+        h2.check(lib().h2_test_gemv_tile(G.handle, nv, x.data_ptr(), y.data_ptr(), nt), "tile")
+        outs.append(y.cpu().numpy())
+    assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[0], outs[2])
+    y = G.gemv(x)
+    y_na = torch.empty_like(x)
+    G.gemv_noalloc(x, y_na)
+    torch.cuda.synchronize()
+    want = H.matvec(si.gaussian_vectors(T.n, nv, 6))
+    got = y.cpu().numpy().T
+    assert np.abs(got - want).max() <= 1e-12 * np.abs(want).max()
+    assert float((y - y_na).abs().max() / y_na.abs().max()) <= 1e-13
