@@ -147,6 +147,30 @@ def test_build_python_sampler_and_rebuild():
     assert (G.gemv(x) - G2.gemv(x)).norm() <= 1e-11 * G.gemv(x).norm()
 
 
+
+@pytest.mark.parametrize("adaptive", [False, True])
+def test_build_of_a_multiple_of_the_identity(adaptive):
+    """Degenerate case of the construction: every admissible block of 2.5 I is
+    zero, so each pair's samples vanish, no range column is kept and every
+    basis has rank 0; the H2 matrix is its dense near blocks and reproduces
+    2.5 x (to rounding).  Applies, rounds (one per level without adaptivity, a
+    confirming second round with it) and ranks equal the oracle's."""
+    pts = si.points_1d_cell_centres(512)
+    T = OTree(pts, 32, 0.7)
+    A = tree_order(lambda X: 2.5 * X, T.perm)
+    nu, _ = power_norm(A, T.n, 1)
+    H, pr = obuild(A, T, 1e-8, nu, 16, 10, adaptive=adaptive, max_rounds=16, seed=1)
+    gt = h2.Tree(pts, 32, 0.7)
+    I = h2.H2Matrix.identity(gt, 2.5)
+    G, st = h2.build(gt, h2.H2Sampler(I), h2.opts(rank_cap=16, oversample=10, tol=1e-8,
+                                                 adaptive=int(adaptive), max_rounds=16,
+                                                 seed=1))
+    _compare(T, H, pr, nu, G, st)
+    assert not G.ranks().any()
+    assert st["range_cols"] == [0] * T.L
+    x = torch.randn(3, T.n, dtype=torch.float64, device="cuda")
+    assert float((G.gemv(x) - 2.5 * x).abs().max()) <= 1e-14 * float(x.abs().max())
+
 def test_build_failure_paths():
     gt = h2.Tree(si.points_1d_cell_centres(256), 32, 0.7)
     failing = h2.PythonSampler(256, lambda om: None)

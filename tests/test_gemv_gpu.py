@@ -187,3 +187,30 @@ def test_hgemv_split_far_lists(nv):
     got = y.cpu().numpy().T
     assert np.abs(got - want).max() <= 1e-12 * np.abs(want).max()
     assert float((y - y_na).abs().max() / y_na.abs().max()) <= 1e-13
+
+
+def test_hgemv_empty_and_invalid_calls():
+    """No vectors is a valid call that leaves y untouched, through all three
+    entry points; a negative count or a leading dimension below n is
+    H2_EINVAL (host checks, nothing is launched)."""
+    n = 300
+    gt = h2.Tree(np.linspace(0, 1, n), 32, 0.7)
+    I = h2.H2Matrix.identity(gt, 2.0)
+    for dt in (torch.float64, torch.float32):
+        x = torch.empty(0, n, dtype=dt, device="cuda")
+        assert I.gemv(x).shape == (0, n)
+    x0 = torch.empty(0, n, dtype=torch.float64, device="cuda")
+    assert I.gemv_noalloc(x0, torch.empty_like(x0)).shape == (0, n)
+    x = torch.randn(2, n, dtype=torch.float64, device="cuda")
+    y = torch.full_like(x, 7.0)
+    lib = h2._lib.lib()
+    p = h2._ptr
+    for f in (lib.h2_gemv, lib.h2_gemv_noalloc):
+        assert f(I.handle, 0, 1.0, None, n, 0.0, None, n, None) == 0
+        assert f(I.handle, -1, 1.0, p(x), n, 0.0, p(y), n, None) == -1
+        assert f(I.handle, 2, 1.0, p(x), n - 1, 0.0, p(y), n, None) == -1
+        assert f(I.handle, 2, 1.0, p(x), n, 0.0, p(y), n - 1, None) == -1
+        assert f(I.handle, 2, 1.0, None, n, 0.0, p(y), n, None) == -1
+    torch.cuda.synchronize()
+    assert bool((y == 7.0).all())
+    assert torch.equal(I.gemv(x), 2.0 * x)
