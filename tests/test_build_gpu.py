@@ -171,6 +171,33 @@ def test_build_of_a_multiple_of_the_identity(adaptive):
     x = torch.randn(3, T.n, dtype=torch.float64, device="cuda")
     assert float((G.gemv(x) - 2.5 * x).abs().max()) <= 1e-14 * float(x.abs().max())
 
+
+@pytest.mark.parametrize("dynamic", [0, 1])
+def test_newton_schulz_of_a_multiple_of_the_identity(dynamic):
+    """Degenerate case of the iteration: for A = 2.5 I the start X0 = I / nu
+    is the inverse, the first residual I - A X0 is zero up to the rounding of
+    the products, and the iteration stops before its first step, as the
+    oracle's does (whose residual happens to round to exactly 0)."""
+    pts = si.points_1d_cell_centres(512)
+    T = OTree(pts, 32, 0.7)
+    A = tree_order(lambda X: 2.5 * X, T.perm)
+    nu, _ = power_norm(A, T.n, 1)
+    H, _ = obuild(A, T, 1e-8, nu, 16, 10, adaptive=True, max_rounds=16, seed=1)
+    Xo, info = ons(H, 1e-4, 40, 32, 10, x0="identity", dynamic=bool(dynamic), adaptive=True,
+                   seed=2)
+    assert info["iterations"] == 0 and info["E"][0] <= 1e-15
+    gt = h2.Tree(pts, 32, 0.7)
+    G = h2.H2Matrix.identity(gt, 2.5)
+    X, ginfo = h2.newton_schulz(G, h2.ns_opts(eps=1e-4, max_iter=40, x0=0, dynamic=dynamic,
+                                              rank_cap=32, oversample=10, adaptive=1, seed=2))
+    assert ginfo["status"] == 0
+    assert ginfo["iterations"] == info["iterations"]
+    assert len(ginfo["resid"]) == 1 and ginfo["resid"][0] <= 1e-15
+    assert ginfo["applies"] == info["applies"] == []
+    assert ginfo["norm"] == pytest.approx(2.5, rel=1e-15)
+    assert op_err(X, Xo, T.n) <= 1e-15
+    assert h2.residual_norm(G, X, rel=1e-6, max_iter=30) <= 1e-15
+
 def test_build_failure_paths():
     gt = h2.Tree(si.points_1d_cell_centres(256), 32, 0.7)
     failing = h2.PythonSampler(256, lambda om: None)
