@@ -27,10 +27,6 @@ h2_status h2_test_qr(int m, int n, const double* A, double* Q, double* R);
 h2_status h2_test_cholqr(int m, int n, const double* A, double* Q, double* R, int mode);
 /* one-sided Jacobi SVD of A (m x n, m >= n): sigma (n), U (m x n), V (n x n) */
 h2_status h2_test_svd(int m, int n, const double* A, double* sigma, double* U, double* V);
-// The same for `count` matrices in one batched call: matrix i is m[i] x n[i]
-// (m[i] >= n[i]); A and U are the column-major matrices stored one after the
-// other, sigma the n[i] values one after the other, V the n[i] x n[i] factors
-// one after the other.
 /* raw accumulator of one 16x16 matrix-core product (kind 0: f64 16x16x4,
    1: f32 16x16x4, 2: bf16 16x16x16) of known operands; out[lane*4 + reg]
    (256 values) -- pins the operand and result lane layouts the kernels use */
@@ -51,6 +47,10 @@ int h2_test_tuned_tile(const h2_matrix* A, int nv);
 /* groups per far list that h2_gemv's coupling stage uses for nv vectors on A
    (1: no split) */
 int h2_test_gemv_split_groups(const h2_matrix* A, int nv);
+/* the one-sided Jacobi SVD for `count` matrices in one batched call: matrix i
+   is m[i] x n[i] (m[i] >= n[i]); A and U are the column-major matrices stored
+   one after the other, sigma the n[i] values one after the other, V the
+   n[i] x n[i] factors one after the other */
 h2_status h2_test_svd_batch(int count, const int* m, const int* n, const double* A, double* sigma,
                             double* U, double* V);
 /* keep the weak factors of subsequent h2_build calls on this thread (1) or not (0) */

@@ -75,8 +75,11 @@ def svd(A):
 
 @pytest.mark.parametrize("m,n,decay", [(40, 40, 0.0), (102, 64, 0.3), (200, 64, 0.6),
                                        (256, 256, 0.1), (70, 70, 1.0), (665, 104, 0.2),
-                                       (600, 600, 0.02), (1100, 100, 0.1), (97, 97, 0.0)])
+                                       (600, 600, 0.02), (1100, 100, 0.1), (97, 97, 0.0),
+                                       (1024, 1024, 0.01), (1024, 1000, 0.05)])
 def test_jacobi_svd_matches_lapack(m, n, decay):
+    """Square, tall and ragged shapes on both Jacobi kernels, up to the
+    multi-workgroup kernel's largest matrix (1024 x 1024)."""
     g = np.random.default_rng(m * n)
     U0 = np.linalg.qr(g.standard_normal((m, n)))[0]
     V0 = np.linalg.qr(g.standard_normal((n, n)))[0]
@@ -91,6 +94,15 @@ def test_jacobi_svd_matches_lapack(m, n, decay):
     assert np.abs(V.T @ V - np.eye(n)).max() <= 1e-12
     assert np.abs(U[:, keep] * s[keep] @ V[:, keep].T - A).max() <= 1e-12 * sl[0] * n
 
+
+
+def test_svd_rejects_shapes_beyond_its_limits():
+    """More than 1024 columns, or fewer rows than columns, is H2_EINVAL
+    (checked on the host before anything is launched)."""
+    for shape in ((1100, 1025), (10, 20)):
+        with pytest.raises(h2.H2Error) as e:
+            svd(np.ones(shape))
+        assert e.value.status == -1
 
 def test_svd_ordering_with_nan_column_is_a_permutation():
     """Singular values are ordered by a ranking that treats NaN as below every
