@@ -148,6 +148,23 @@ def test_build_python_sampler_and_rebuild():
 
 
 
+
+@pytest.mark.parametrize("adaptive", [False, True])
+def test_build_on_a_single_leaf_matches_oracle(adaptive):
+    """Degenerate tree: fewer points than the leaf size gives L = 0, no
+    admissible block and no level to peel; the construction is the dense
+    leaf sampled with identity columns (one apply per point), as in the
+    oracle, and reproduces the operator to rounding."""
+    cfg = dict(points=si.points_1d_cell_centres(40), leaf=64, eta=0.7, seed=1, tol=1e-8,
+               cap=16, p=10)
+    K = KernelHessian(cfg["points"], 0.1, 1e-2)
+    T, H, pr, nu = _oracle_build(cfg, K.apply, adaptive)
+    assert T.L == 0 and pr.applies == 40
+    gt, G, st = _gpu_build(cfg, h2.KernelSampler(cfg["points"], 0.1, 1e-2), adaptive)
+    _compare(T, H, pr, nu, G, st)
+    Gd = host(G.gemv(torch.eye(40, dtype=torch.float64, device="cuda")))
+    assert np.abs(Gd - K.dense()).max() <= 1e-13 * np.abs(K.dense()).max()
+
 @pytest.mark.parametrize("adaptive", [False, True])
 def test_build_of_a_multiple_of_the_identity(adaptive):
     """Degenerate case of the construction: every admissible block of 2.5 I is

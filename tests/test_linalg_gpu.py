@@ -183,6 +183,15 @@ def cholqr(A, mode):
     return Q, R
 
 
+
+def test_tall_qr_rejects_shapes_beyond_its_limits():
+    """TSQR takes at most 96 columns; both tall QRs need m >= n; the hook's
+    mode is 0..3.  Each is H2_EINVAL from a host check."""
+    for shape, mode in (((500, 97), 0), ((50, 60), 0), ((50, 60), 1), ((50, 20), 4)):
+        with pytest.raises(h2.H2Error) as e:
+            cholqr(np.ones(shape), mode)
+        assert e.value.status == -1, (shape, mode)
+
 @pytest.mark.parametrize("m,n,rank,blocked", [(2048, 74, 74, 0), (900, 42, 10, 0), (500, 96, 96, 0),
                                               (300, 20, 20, 0), (97, 96, 50, 0), (3000, 40, 40, 0),
                                               (1281, 64, 30, 0), (320, 96, 96, 0),
