@@ -48,6 +48,33 @@ def test_build_batched_equals_individual_builds():
             assert np.array_equal(x, y), i
 
 
+
+def test_build_batched_with_degenerate_members_equals_individual_builds():
+    """A batch that mixes a single-leaf problem (L = 0, no level to peel) and a
+    problem whose admissible blocks are all zero (2.5 I: every rank 0) with an
+    ordinary one: each result equals its own single build, array for array."""
+    p = problems(1)[0]
+    pts1 = si.points_1d_cell_centres(40)
+    pts2 = si.points_1d_cell_centres(512)
+    trees = [h2.Tree(pts1, 64, 0.7), h2.Tree(p["points"], p["leaf"], p["eta"]),
+             h2.Tree(pts2, 32, 0.7)]
+    ident = h2.H2Matrix.identity(trees[2], 2.5)
+    samp = [h2.KernelSampler(pts1, 0.1, 1e-2), h2.KernelSampler(p["points"], p["ell"], p["shift"]),
+            h2.H2Sampler(ident)]
+    opts = [h2.opts(rank_cap=16, oversample=10, tol=1e-8, adaptive=1, max_rounds=16, seed=1),
+            h2.opts(rank_cap=p["cap"], oversample=p["p"], tol=p["tol"], adaptive=1,
+                    max_rounds=16, seed=p["seed"]),
+            h2.opts(rank_cap=16, oversample=10, tol=1e-8, adaptive=1, max_rounds=16, seed=1)]
+    assert trees[0].L == 0 and trees[1].L >= 2
+    mats, stats, rc = h2.build_batched(trees, samp, opts)
+    assert rc == 0
+    assert not mats[2].ranks().any()
+    for i in range(3):
+        G, st = h2.build(trees[i], samp[i], opts[i])
+        assert st["rounds"] == stats[i]["rounds"] and st["applies"] == stats[i]["applies"], i
+        for x, y in zip(G.export(), mats[i].export()):
+            assert np.array_equal(x, y), i
+
 def test_build_batched_matches_oracle():
     ps = problems(3, nmax=2500)
     trees, samp, opts = setup(ps)
