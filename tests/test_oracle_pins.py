@@ -34,6 +34,24 @@ def test_splitmix64_published_vector():
     assert [int(x) for x in rng.splitmix64_stream(1234567, 5)] == want
 
 
+
+def test_gaussian_entries_from_the_published_vector():
+    """Entry (row r, column c) of a block keyed by k is the Box-Muller
+    transform (Box and Muller 1958: sqrt(-2 ln u1) cos(2 pi u2)) of outputs
+    2j + 1 and 2j + 2 of splitmix64 seeded with k, j = r 2^16 + c, each mapped
+    to (0, 1] by its top 53 bits plus one.  With k = 1234567 the entries of
+    row 0, columns 0 and 1, come from the five published outputs above."""
+    pub = [6457827717110365317, 3203168211198807973, 9817491932198370423,
+           4593380528125082431]
+
+    def unit(x):
+        return ((x >> 11) + 1) * 2.0 ** -53
+
+    want = [math.sqrt(-2.0 * math.log(unit(pub[2 * j]))) * math.cos(2.0 * math.pi * unit(pub[2 * j + 1]))
+            for j in range(2)]
+    got = rng.gaussian(1234567, np.array([0]), np.array([0, 1]))[0]
+    assert np.allclose(got, want, rtol=1e-15, atol=0)
+
 def test_gaussian_stream_statistics():
     key = rng.stream_key(7, rng.PHASE_RANGE, 3, 1, 0)
     z = rng.gaussian(key, np.arange(15625), np.arange(64)).ravel()
@@ -382,6 +400,32 @@ def test_residual_norm_matches_dense(kernel_small):
     R = np.eye(T.n) - H.dense_tree() @ X.dense_tree()
     assert abs(E - np.linalg.norm(R, 2)) <= 1e-3 * np.linalg.norm(R, 2)
 
+
+
+def test_dynamic_threshold_keeps_the_quadratic_rate():
+    """Appendix A, dynamic threshold: the iterates' construction threshold
+    starts loose (1e-2) and tightens as the iteration converges.  One
+    Newton-Schulz step squares the residual (R_{k+1} = R_k^2), and building
+    X_{k+1} to an operator error eps_k / nu adds at most eps_k to the next
+    residual, so E_{k+1} <= E_k^2 + eps_k: a schedule that tightens with E_k^2
+    keeps the quadratic rate, one that tightens only with E_k loses it near
+    the end.  Pinned with the construction floor below every residual:
+    eps_0 = 1e-2, eps_k non-increasing, E_{k+1} <= 1.2 E_k^2 from E_k < 0.5."""
+    pts = si.points_1d_cell_centres(256)
+    T = Tree(pts, 32, 0.7)
+    A = tree_order(KernelHessian(pts, 0.1, 1e-2).apply, T.perm)
+    nu, _ = power_norm(A, T.n, 1)
+    H, _ = build(A, T, 1e-12, nu, 32, 10, adaptive=True, seed=1)
+    _, info = newton_schulz(H, 1e-9, 60, 64, 10, x0="identity", dynamic=True, eps_build=1e-13,
+                            adaptive=True, seed=2)
+    assert info["status"] == "converged"
+    E, ek = info["E"], info["eps_k"]
+    assert E[0] > 0.5 and ek[0] == 1e-2
+    assert all(b <= a for a, b in zip(ek, ek[1:]))
+    steps = [(E[k], E[k + 1]) for k in range(len(E) - 1) if E[k] < 0.5]
+    assert len(steps) >= 4
+    for a, b in steps:
+        assert b <= 1.2 * a * a, (a, b)
 
 @pytest.mark.parametrize("x0", ["identity", "scaled"])
 def test_newton_schulz_closed_form(kernel_small, x0):
