@@ -427,6 +427,37 @@ def test_dynamic_threshold_keeps_the_quadratic_rate():
     for a, b in steps:
         assert b <= 1.2 * a * a, (a, b)
 
+
+@pytest.mark.parametrize("case", ["diffusion2d", "kernel2d"])
+def test_recompression_stays_within_its_error_share(case):
+    """Sec. 3.3 with the per-level threshold tau_c = eps nu / (4 L): each
+    level's truncation of the nested bases may cost tau_c, so the strong
+    H2 matrix differs from the peeled weak representation it was folded from
+    by at most L tau_c = eps nu / 4 in the 2-norm (dense comparison of the
+    two operators).  Workloads with a decaying spectrum, so that singular
+    values lie just above the cut."""
+    if case == "diffusion2d":
+        cfg = si.config_diffusion2d(24)
+        pts, apply_user = cfg["points"], DiffusionGN(cfg).apply
+        cap = 32
+    else:
+        pts = si.points_grid_cell_centres(24, 24)
+        apply_user = KernelHessian(pts, 0.05, 1e-3).apply
+        cap = 64
+    tol = 1e-6
+    T = Tree(pts, 32, 0.7)
+    A = tree_order(apply_user, T.perm)
+    nu, _ = power_norm(A, T.n, 1)
+    pr = peel_mod.peel(A, T, tol, nu, cap, 10, True, 16, 1)
+    eye = np.eye(T.n)
+    W = sum(peel_mod.weak_apply(T, l, pr.F[l], eye) for l in range(1, T.L + 1))
+    for i in range(1 << T.L):
+        a, b = T.rng(T.L, i)
+        W[a:b, a:b] += pr.Ddiag[i]
+    H = peel_mod.recompress(T, pr, tol, nu, cap)
+    err = np.linalg.norm(H.dense_tree() - W, 2)
+    assert 0.0 < err <= tol * nu / 4, (err, tol * nu / 4)
+
 @pytest.mark.parametrize("x0", ["identity", "scaled"])
 def test_newton_schulz_closed_form(kernel_small, x0):
     # X0 = p(H) gives X_k = p_k(H) and E_k = max_i |1 - lam_i x0(lam_i)|^(2^k)
