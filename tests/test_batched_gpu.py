@@ -158,6 +158,31 @@ def test_newton_schulz_batched_equals_individual():
             assert np.array_equal(x, y), i
 
 
+
+def test_newton_schulz_batched_with_a_member_converged_at_the_start():
+    """Lock step with a member that needs no step: 2.5 I starts at its
+    inverse (residual at rounding level), finishes before the first
+    construction and leaves the others' lock-step iterations unchanged;
+    every member equals its own single run."""
+    ps = problems(2, nmax=3000)
+    trees, samp, opts = setup(ps)
+    mats, _, _ = h2.build_batched(trees, samp, opts)
+    t3 = h2.Tree(si.points_1d_cell_centres(512), 32, 0.7)
+    mats = [mats[0], h2.H2Matrix.identity(t3, 2.5), mats[1]]
+    seeds = [ps[0]["seed"], 5, ps[1]["seed"]]
+    nopts = [h2.ns_opts(eps=1e-4, max_iter=40, x0=0, dynamic=1, rank_cap=0, oversample=10,
+                        adaptive=1, max_rounds=16, seed=sd) for sd in seeds]
+    Xs, infos = h2.newton_schulz_batched(mats, nopts)
+    assert infos[1]["iterations"] == 0 and infos[1]["resid"][0] <= 1e-15
+    assert infos[0]["iterations"] > 0 and infos[2]["iterations"] > 0
+    for i in range(3):
+        X, info = h2.newton_schulz(mats[i], nopts[i])
+        assert infos[i]["status"] == 0 and info["status"] == 0
+        assert infos[i]["iterations"] == info["iterations"]
+        assert infos[i]["resid"] == info["resid"]
+        for x, y in zip(X.export(), Xs[i].export()):
+            assert np.array_equal(x, y), i
+
 def test_build_batched_rejects_bad_problem():
     ps = problems(2)
     trees, samp, opts = setup(ps)
